@@ -1,0 +1,29 @@
+"""FP64 CPU oracle for the matrix power kernel -- TEST INFRASTRUCTURE ONLY.
+
+This package is the plain, slow, obviously correct reference that the HIP
+path is checked against.  Only ``tests/``, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import it; the product package never
+does, and it shares no code with the HIP path (it imports nothing from
+``paper_2309_02228_amd``; inputs come from the separate ``synth`` generators).
+
+Everything is written from the paper's statement of the method
+(Alappat, Thies, Hager, Fehske, Wellein: "Algebraic temporal blocking for
+sparse iterative solvers on multi-core CPUs"):
+
+* ``spmv``, ``mpk``                 -- Sec. 3, Alg. 1 and Alg. 2
+* ``newton_basis``                  -- Sec. 4 (Newton basis of the s-step method)
+* ``poly_monomial``/``poly_newton``  -- Sec. 5.2, Eq. (3)
+* ``poly_chebyshev``                -- Sec. 5.3 (Chebyshev smoother; the
+  three-term recurrence itself is not printed in the paper)
+* ``pattern_graph``, ``bfs_levels``,
+  ``level_permutation``             -- Sec. 3 (BFS level structure of the
+  matrix graph) and Sec. 5.1.2 (levels come from A alone)
+* ``group_levels``, ``wavefront_schedule``, ``validate_schedule``,
+  ``blocked_mpk``                   -- Sec. 3 (execution order from the level
+  structure and the cache size; p_opt and the remainder loop)
+
+Parity status of each function is stated in its docstring.  The readings
+taken where the paper is silent are listed in ``mpk_oracle.READINGS``.
+"""
+from .mpk_oracle import *  # noqa: F401,F403
+from .mpk_oracle import READINGS  # noqa: F401

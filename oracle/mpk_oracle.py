@@ -1,0 +1,456 @@
+"""FP64 CPU oracle for the matrix power kernel (MPK) -- TEST INFRASTRUCTURE ONLY.
+
+Plain, single-threaded NumPy (plus pure-Python loops for tiny cases).  Only
+``tests/``, ``__graft_entry__.smoke()`` and ``bench.py``'s ``cpu_baseline``
+leg may use it.  It shares no code with the HIP path.
+
+Matrices are ``(n, rowptr, col, val)`` CSR tuples (0-based, columns sorted
+and unique within a row), vectors are float64 NumPy arrays.
+
+Parity status
+-------------
+pinned   spmv, mpk, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
+         pattern_graph, bfs_levels, level_permutation, permute_symmetric,
+         chunk_owner, chunk_dependencies, hop_min, window_ok,
+         simulate_blocked_mpk
+         (pins: exact integer arithmetic, closed-form Laplacian eigenpairs,
+         closed-form grid levels, scipy shortest paths, brute force on tiny
+         inputs, special cases; see tests/test_oracle_pins.py)
+unpinned the choice of chunk-to-XCD ownership and the execution order are this
+         project's own readings (R5-R7 below); the paper gives no rule to
+         check them against, so only their validity (coverage, read-after-
+         write order, deadlock freedom, bitwise equality with the plain
+         MPK) is pinned, not their identity with the paper's library.
+"""
+from collections import deque
+
+import numpy as np
+
+# Readings taken where the paper is silent or garbled.  Each is implemented
+# below exactly as stated; the HIP planner implements the same statements
+# independently.
+READINGS = {
+    "R1": "BFS runs on the undirected graph of pattern(A) union pattern(A^T) without "
+          "self-loops; explicitly stored zeros count as edges (Sec. 3: levels from "
+          "the matrix graph; Sec. 5.1.2: levels come from A alone).",
+    "R2": "Root of each connected component: George-Liu pseudo-peripheral node. Start "
+          "at the component's lowest-index vertex r; BFS from r; among the last level "
+          "take the vertex x of minimum degree (ties: lowest index); BFS from x; if "
+          "ecc(x) > ecc(r) set r = x and repeat, else stop at r. An explicit root "
+          "replaces this search for the component that contains it.",
+    "R3": "Components are processed in order of their lowest vertex index; the levels "
+          "of each component continue after the last level of the previous one.",
+    "R4": "Within a level, rows keep ascending original index: perm[new] = old, "
+          "iperm[old] = new.",
+    "R5": "Rows are cut, in permuted order, into chunks of C consecutive rows (the last "
+          "may be shorter); a chunk is the unit of work and of synchronisation.",
+    "R6": "Chunk c is owned by partition x = floor(P * (r0 - level_start) / level_size), "
+          "where r0 = C*c is its first row and level_start/level_size describe the "
+          "level of r0; each partition processes its chunks in ascending order.",
+    "R7": "Chunk c may compute power k once every chunk holding a row adjacent to c's "
+          "rows in the symmetrised pattern has finished power k-1. Partition x runs W_x "
+          "workers; worker i takes the partition's chunks i, i+W_x, ... and carries each "
+          "through all q powers of a block before taking the next. This order cannot "
+          "deadlock when, for every partition and every position i >= W_x, the chunk at "
+          "position i - W_x has a smaller index than every chunk within q-1 dependency "
+          "hops of the chunk at position i.",
+    "R8": "Newton basis: V_k = (A - lambda_k I) V_{k-1} / sigma_k, the product of distinct "
+          "shifted factors (the printed powers (A - lambda_2 I)^2 ... are read as this "
+          "product).",
+    "R9": "Chebyshev polynomial on [theta - delta, theta + delta]: t_0 = x, "
+          "t_1 = (A - theta I) x / delta, t_{k+1} = 2 (A - theta I) t_k / delta - t_{k-1}; "
+          "result sum_k c_k t_k.",
+    "R10": "Powers beyond one block of q are computed as consecutive blocks of q powers "
+           "and a last block of the remaining r < q powers, each seeded with the last "
+           "vector of the previous block (Sec. 3, p_opt and the remainder loop).",
+}
+
+
+# --------------------------------------------------------------------------- #
+# Sec. 3, Alg. 1 and Alg. 2: the plain MPK
+# --------------------------------------------------------------------------- #
+def _arrays(A):
+    n, rowptr, col, val = A
+    return int(n), np.asarray(rowptr, dtype=np.int64), np.asarray(col, dtype=np.int64), \
+        np.asarray(val, dtype=np.float64)
+
+
+def spmv(A, x):
+    """y = A x, every row summed as in Alg. 2: tmp = 0, then tmp += val*y[col] over
+    the row's stored entries in order.
+
+    Each product is rounded on its own (no fused multiply-add); ``np.bincount``
+    adds the weights into the output one after the other in input order, so
+    row i is accumulated left to right starting from 0.0.
+    """
+    n, rowptr, col, val = _arrays(A)
+    x = np.asarray(x, dtype=np.float64)
+    prod = val * x[col]
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    return np.bincount(rows, weights=prod, minlength=n)
+
+
+def spmv_rowloop(A, x):
+    """The same product with explicit Python loops (tiny matrices only)."""
+    n, rowptr, col, val = _arrays(A)
+    y = np.zeros(n)
+    for i in range(n):
+        tmp = 0.0
+        for idx in range(rowptr[i], rowptr[i + 1]):
+            tmp += float(val[idx]) * float(x[col[idx]])
+        y[i] = tmp
+    return y
+
+
+def spmv_rows(A, x, r0, r1):
+    """Rows r0..r1-1 of A x, with the same per-row summation order as ``spmv``."""
+    n, rowptr, col, val = _arrays(A)
+    a, b = rowptr[r0], rowptr[r1]
+    prod = val[a:b] * np.asarray(x, dtype=np.float64)[col[a:b]]
+    rows = np.repeat(np.arange(r1 - r0, dtype=np.int64), np.diff(rowptr[r0:r1 + 1]))
+    return np.bincount(rows, weights=prod, minlength=r1 - r0)
+
+
+def mpk(A, x, p):
+    """Alg. 1: y_0 = x and y_k = A y_{k-1} for k = 1..p.  Returns Y with Y[k-1] = y_k."""
+    y = np.asarray(x, dtype=np.float64)
+    out = np.empty((p, y.size))
+    for k in range(p):
+        y = spmv(A, y)
+        out[k] = y
+    return out
+
+
+# --------------------------------------------------------------------------- #
+# Sec. 4 (Newton basis) and Sec. 5.2/5.3 (polynomials applied through the MPK)
+# --------------------------------------------------------------------------- #
+def newton_basis(A, v, lambdas, sigmas=None):
+    """s-step basis with constant real shifts (Sec. 4; reading R8).
+
+    V_0 = v and V_k = (A - lambda_k I) V_{k-1} / sigma_k for k = 1..s
+    (sigma_k = 1 when ``sigmas`` is None; lambda_k = 0 gives the monomial basis).
+    Returns an (s+1, n) array.
+    """
+    lambdas = np.asarray(lambdas, dtype=np.float64)
+    s = lambdas.size
+    V = np.empty((s + 1, np.asarray(v).size))
+    V[0] = v
+    for k in range(1, s + 1):
+        w = spmv(A, V[k - 1]) - lambdas[k - 1] * V[k - 1]
+        if sigmas is not None:
+            w = w / sigmas[k - 1]
+        V[k] = w
+    return V
+
+
+def poly_monomial(A, x, c):
+    """Eq. (3): sum_{k=0..d} c_k A^k x with the powers from the plain MPK."""
+    c = np.asarray(c, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    out = c[0] * x
+    if c.size > 1:
+        Y = mpk(A, x, c.size - 1)
+        for k in range(1, c.size):
+            out = out + c[k] * Y[k - 1]
+    return out
+
+
+def poly_newton(A, x, c, lambdas):
+    """sum_{k=0..d} c_k phi_k with phi_0 = x, phi_k = (A - lambda_k I) phi_{k-1}."""
+    c = np.asarray(c, dtype=np.float64)
+    V = newton_basis(A, x, np.asarray(lambdas, dtype=np.float64)[: c.size - 1])
+    out = c[0] * V[0]
+    for k in range(1, c.size):
+        out = out + c[k] * V[k]
+    return out
+
+
+def poly_chebyshev(A, x, c, theta, delta):
+    """sum_{k=0..d} c_k t_k with the Chebyshev three-term recurrence (reading R9)."""
+    c = np.asarray(c, dtype=np.float64)
+    x = np.asarray(x, dtype=np.float64)
+    out = c[0] * x
+    if c.size == 1:
+        return out
+    t_prev = x
+    t = (spmv(A, x) - theta * x) / delta
+    out = out + c[1] * t
+    for k in range(2, c.size):
+        t_next = 2.0 * (spmv(A, t) - theta * t) / delta - t_prev
+        out = out + c[k] * t_next
+        t_prev, t = t, t_next
+    return out
+
+
+def chebyshev_basis(A, x, d, theta, delta):
+    """The vectors t_0..t_d of reading R9 (used by tests)."""
+    T = np.empty((d + 1, np.asarray(x).size))
+    T[0] = x
+    if d >= 1:
+        T[1] = (spmv(A, T[0]) - theta * T[0]) / delta
+    for k in range(2, d + 1):
+        T[k] = 2.0 * (spmv(A, T[k - 1]) - theta * T[k - 1]) / delta - T[k - 2]
+    return T
+
+
+# --------------------------------------------------------------------------- #
+# Sec. 3: level structure from a BFS of the matrix graph (readings R1-R4)
+# --------------------------------------------------------------------------- #
+def pattern_graph(A):
+    """Undirected adjacency of pattern(A) union pattern(A^T) without self-loops (R1).
+
+    Returns (ptr, adj) with adj[ptr[i]:ptr[i+1]] the sorted neighbours of i.
+    """
+    n, rowptr, col, _ = _arrays(A)
+    rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
+    r = np.concatenate([rows, col])
+    c = np.concatenate([col, rows])
+    keep = r != c
+    key = np.unique(r[keep] * max(n, 1) + c[keep])
+    r, c = key // max(n, 1), key % max(n, 1)
+    ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(r, minlength=n), out=ptr[1:])
+    return ptr, c
+
+
+def _neighbours(ptr, adj, frontier):
+    starts = ptr[frontier]
+    lens = ptr[frontier + 1] - starts
+    total = int(lens.sum())
+    if total == 0:
+        return np.zeros(0, dtype=np.int64)
+    offs = np.repeat(starts - np.concatenate([[0], np.cumsum(lens)[:-1]]), lens)
+    return adj[offs + np.arange(total)]
+
+
+def bfs_layers(ptr, adj, root, dist):
+    """Breadth-first search from ``root``: layer d holds the vertices at distance d.
+
+    ``dist`` (int64, -1 = unvisited) is updated in place; returns the list of
+    layers, each sorted ascending.
+    """
+    frontier = np.array([root], dtype=np.int64)
+    dist[root] = 0
+    layers = [frontier]
+    d = 0
+    while True:
+        nb = np.unique(_neighbours(ptr, adj, frontier))
+        nb = nb[dist[nb] < 0]
+        if nb.size == 0:
+            return layers
+        d += 1
+        dist[nb] = d
+        layers.append(nb)
+        frontier = nb
+
+
+def bfs_layers_queue(ptr, adj, root, n):
+    """Textbook FIFO-queue BFS (pure Python, small graphs): distance of every vertex."""
+    dist = [-1] * n
+    dist[root] = 0
+    q = deque([root])
+    while q:
+        u = q.popleft()
+        for v in adj[ptr[u]:ptr[u + 1]]:
+            if dist[v] < 0:
+                dist[v] = dist[u] + 1
+                q.append(int(v))
+    return dist
+
+
+def pseudo_peripheral_root(ptr, adj, start, n):
+    """George-Liu pseudo-peripheral node search from ``start`` (reading R2).
+
+    Returns (root, layers of the BFS from root).
+    """
+    r = int(start)
+    layers_r = bfs_layers(ptr, adj, r, np.full(n, -1, dtype=np.int64))
+    while True:
+        last = layers_r[-1]
+        deg = ptr[last + 1] - ptr[last]
+        x = int(last[int(np.argmin(deg))])  # first minimum = lowest index (layers are sorted)
+        layers_x = bfs_layers(ptr, adj, x, np.full(n, -1, dtype=np.int64))
+        if len(layers_x) > len(layers_r):
+            r, layers_r = x, layers_x
+            continue
+        return r, layers_r
+
+
+def bfs_levels(A, root=None):
+    """Level of every row (readings R1-R3).
+
+    Returns (level, nlevels, roots) where ``roots`` lists the BFS root chosen
+    for each component in processing order.
+    """
+    n = int(A[0])
+    ptr, adj = pattern_graph(A)
+    level = np.full(n, -1, dtype=np.int64)
+    seen = np.zeros(n, dtype=bool)
+    base = 0
+    roots = []
+    for v in range(n):
+        if seen[v]:
+            continue
+        # the component of the lowest-index unvisited vertex
+        comp_dist = np.full(n, -1, dtype=np.int64)
+        comp = np.concatenate(bfs_layers(ptr, adj, v, comp_dist))
+        if root is not None and comp_dist[int(root)] >= 0:
+            r = int(root)
+            layers = bfs_layers(ptr, adj, r, np.full(n, -1, dtype=np.int64))
+        else:
+            r, layers = pseudo_peripheral_root(ptr, adj, v, n)
+        for d, layer in enumerate(layers):
+            level[layer] = base + d
+        seen[comp] = True
+        base += len(layers)
+        roots.append(r)
+    return level, base, roots
+
+
+def level_permutation(level, nlevels):
+    """perm sorts rows by (level, original index) (R4).  Returns perm, iperm, level_ptr."""
+    level = np.asarray(level, dtype=np.int64)
+    n = level.size
+    perm = np.lexsort((np.arange(n), level)).astype(np.int64)
+    iperm = np.empty(n, dtype=np.int64)
+    iperm[perm] = np.arange(n)
+    level_ptr = np.zeros(nlevels + 1, dtype=np.int64)
+    np.cumsum(np.bincount(level, minlength=nlevels), out=level_ptr[1:])
+    return perm, iperm, level_ptr
+
+
+def permute_symmetric(A, perm, iperm):
+    """B = P A P^T: B[i, j] = A[perm[i], perm[j]], columns re-sorted within each row."""
+    n, rowptr, col, val = _arrays(A)
+    lens = np.diff(rowptr)[perm]
+    bptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(lens, out=bptr[1:])
+    # entry positions of old row perm[i], laid out row after row
+    src = np.repeat(rowptr[perm] - bptr[:-1], lens) + np.arange(bptr[-1], dtype=np.int64)
+    bcol = iperm[col[src]]
+    bval = val[src]
+    rows = np.repeat(np.arange(n, dtype=np.int64), lens)
+    order = np.lexsort((bcol, rows))
+    return (n, bptr, bcol[order], bval[order])
+
+
+# --------------------------------------------------------------------------- #
+# Execution order of the blocked MPK (readings R5-R7)
+# --------------------------------------------------------------------------- #
+def chunk_owner(level_ptr, level_of_new_row, n, chunk_rows, nparts):
+    """Owner partition of every chunk (reading R6)."""
+    nchunks = (n + chunk_rows - 1) // chunk_rows
+    owner = np.empty(nchunks, dtype=np.int64)
+    for c in range(nchunks):
+        r0 = c * chunk_rows
+        lv = int(level_of_new_row[r0])
+        start, size = int(level_ptr[lv]), int(level_ptr[lv + 1] - level_ptr[lv])
+        owner[c] = (nparts * (r0 - start)) // size
+    return owner
+
+
+def chunk_dependencies(B, chunk_rows):
+    """For every chunk, the sorted other chunks holding a row adjacent to one of
+    its rows in pattern(B) union pattern(B^T) (reading R7)."""
+    n = int(B[0])
+    ptr, adj = pattern_graph(B)
+    nchunks = (n + chunk_rows - 1) // chunk_rows
+    deps = []
+    for c in range(nchunks):
+        r0, r1 = c * chunk_rows, min(n, (c + 1) * chunk_rows)
+        nb = adj[ptr[r0]:ptr[r1]] // chunk_rows
+        nb = np.unique(nb)
+        deps.append(nb[nb != c])
+    return deps
+
+
+def hop_min(deps, hops):
+    """B[c] = smallest chunk index within ``hops`` dependency hops of c (c included).
+
+    The dependency relation is symmetric (it comes from a symmetrised pattern),
+    so this is also the smallest chunk from which c is reachable in ``hops``.
+    """
+    b = np.arange(len(deps), dtype=np.int64)
+    for _ in range(max(0, hops)):
+        nb = b.copy()
+        for c, dl in enumerate(deps):
+            if dl.size:
+                nb[c] = min(nb[c], int(b[dl].min()))
+        b = nb
+    return b
+
+
+def window_ok(seq, workers, bmin):
+    """Deadlock-freedom condition of reading R7 for one partition's chunk sequence
+    ``seq`` (ascending chunk indices) run by ``workers`` workers, where ``bmin`` is
+    ``hop_min(deps, q - 1)``.
+
+    Proof sketch: in a deadlock take the waiting (chunk, power) of smallest chunk
+    index c.  Each chunk on its chain of waits lies within q-1 hops of c (powers
+    drop by one per hop and power 1 never waits).  A worker that has not reached
+    such a chunk c' is at least W_x positions behind it, hence on a chunk of index
+    below bmin[c'] <= c, and is itself waiting: a contradiction with the choice
+    of c.
+    """
+    seq = np.asarray(seq, dtype=np.int64)
+    if seq.size <= workers:
+        return True
+    return bool(np.all(seq[:-workers] < np.asarray(bmin)[seq[workers:]]))
+
+
+def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None):
+    """Execute the blocked MPK on permuted matrix B sequentially, in the worker
+    order of reading R7, and return Y (p, n) in permuted space.
+
+    ``workers`` is the number of workers per partition (an int, or one int per
+    partition).  Every worker repeatedly tries to advance its current
+    (chunk, power); a chunk's power k is computed only when all chunks it waits
+    on have finished power k-1.  Values not yet computed are NaN, so a wrong
+    order shows up as NaN in the result; a full sweep without progress raises
+    (deadlock).  Powers are done in blocks of q (R10).  ``kind`` is None for
+    plain powers, or a callable (k, acc, prev, prev2) -> y_k for the shifted
+    and three-term forms, where acc = (A y_{k-1}) on the chunk's rows and
+    prev/prev2 are y_{k-1}/y_{k-2} on the same rows.
+    """
+    n = int(B[0])
+    nchunks = len(deps)
+    Y = np.full((p + 1, n), np.nan)
+    Y[0] = x
+    nparts = int(np.max(owner)) + 1 if nchunks else 0
+    seqs = [np.nonzero(np.asarray(owner) == part)[0] for part in range(nparts)]
+    wk = [int(workers[i]) if np.ndim(workers) else int(workers) for i in range(nparts)]
+    base = 0
+    while base < p:
+        qb = min(q, p - base)
+        done = np.zeros(nchunks, dtype=np.int64)  # powers finished in this block
+        state = [[part, w, 1] for part in range(nparts) for w in range(wk[part])]
+        remaining = nchunks * qb
+        while remaining:
+            progress = False
+            for st in state:
+                part, pos, k = st
+                seq = seqs[part]
+                if pos >= seq.size:
+                    continue
+                c = int(seq[pos])
+                if k > 1 and deps[c].size and done[deps[c]].min() < k - 1:
+                    continue
+                r0, r1 = c * chunk_rows, min(n, (c + 1) * chunk_rows)
+                gk = base + k
+                acc = spmv_rows(B, Y[gk - 1], r0, r1)
+                if kind is None:
+                    Y[gk, r0:r1] = acc
+                else:
+                    prev2 = Y[gk - 2, r0:r1] if gk >= 2 else None
+                    Y[gk, r0:r1] = kind(gk, acc, Y[gk - 1, r0:r1], prev2)
+                done[c] = k
+                remaining -= 1
+                progress = True
+                if k == qb:
+                    st[1], st[2] = pos + wk[part], 1
+                else:
+                    st[2] = k + 1
+            if not progress:
+                raise RuntimeError("blocked MPK schedule deadlocked")
+        base += qb
+    return Y[1:]

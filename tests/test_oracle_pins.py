@@ -1,0 +1,453 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself:
+exact integer arithmetic, closed-form Laplacian eigenpairs and grid levels,
+SciPy's shortest paths, hand-worked fixtures, brute force and special cases.
+Each test names the plausible oracle mistake it would catch."""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.sparse import csr_matrix
+from scipy.sparse.csgraph import shortest_path
+
+import oracle as O
+import synth as S
+
+EPS = np.finfo(np.float64).eps
+
+
+def dense(A):
+    n, rp, c, v = A
+    M = np.zeros((n, n))
+    for i in range(n):
+        M[i, c[rp[i]:rp[i + 1]]] = v[rp[i]:rp[i + 1]]
+    return M
+
+
+def int_dense(A):
+    n, rp, c, v = A
+    M = np.zeros((n, n), dtype=np.int64)
+    for i in range(n):
+        M[i, c[rp[i]:rp[i + 1]]] = np.asarray(v[rp[i]:rp[i + 1]]).astype(np.int64)
+    return M
+
+
+# ----------------------------------------------------------------- SpMV / MPK
+@pytest.mark.parametrize("seed", range(5))
+def test_spmv_matches_plain_row_loop_bitwise(seed):
+    # catches: a summation order other than Alg. 2's left-to-right row sum
+    A = S.random_pattern(40, 6, seed)
+    x = S.uniform_vector(40, seed + 100)
+    assert np.array_equal(O.spmv(A, x), O.spmv_rowloop(A, x))
+
+
+@pytest.mark.parametrize("mk", [lambda: S.laplacian_2d(5, 7), lambda: S.laplacian_3d(3, 4, 2),
+                                lambda: S.random_pattern(50, 5, 3, integer=True)])
+@pytest.mark.parametrize("p", [1, 2, 5, 8])
+def test_mpk_exact_against_integer_dense_powers(mk, p):
+    # catches: dropped/duplicated powers, wrong operand (A^T), index slips
+    A = mk()
+    x = S.integer_vector(A.n, 7, bound=1 << 16)
+    M = int_dense(A)
+    y = x.astype(np.int64)
+    Y = O.mpk(A, x, p)
+    for k in range(p):
+        y = M @ y
+        assert np.array_equal(Y[k], y.astype(np.float64)), k
+
+
+def test_mpk_hand_worked_grid3x3(golden_dir):
+    rows = {}
+    with open(os.path.join(golden_dir, "grid3x3_power2.txt")) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            tag, *vals = line.split()
+            rows[tag] = np.array([float(v) for v in vals])
+    A = S.laplacian_2d(3)
+    x = np.zeros(9)
+    x[4] = 1.0
+    Y = O.mpk(A, x, 2)
+    assert np.array_equal(Y[0], rows["y1"])
+    assert np.array_equal(Y[1], rows["y2"])
+
+
+def _sine_mode_1d(n, j):
+    i = np.arange(1, n + 1)
+    return np.sin(j * np.pi * i / (n + 1)), 2.0 - 2.0 * math.cos(j * math.pi / (n + 1))
+
+
+def _grid_mode(shape, js):
+    vec = np.ones(1)
+    lam = 0.0
+    # row index i + nx*(j + ny*k): the first axis varies fastest
+    for n, j in reversed(list(zip(shape, js))):
+        v, l = _sine_mode_1d(n, j)
+        vec = np.kron(vec, v)
+        lam += l
+    return vec, lam
+
+
+@pytest.mark.parametrize("case", [("1d", (30,), (25,)), ("2d", (12, 9), (10, 8)),
+                                  ("3d", (7, 6, 5), (6, 5, 4))])
+@pytest.mark.parametrize("p", [1, 4, 8])
+def test_mpk_laplacian_eigen_relation(case, p):
+    # closed form: A^p v = lambda^p v for sine modes of the Dirichlet Laplacians
+    # catches: wrong stencil sign or coefficient, a transposed or shifted index
+    name, shape, js = case
+    A = {"1d": lambda: S.laplacian_1d(*shape), "2d": lambda: S.laplacian_2d(*shape),
+         "3d": lambda: S.laplacian_3d(*shape)}[name]()
+    v, lam = _grid_mode(shape, js)
+    normA = 4.0 * len(shape)
+    assert lam >= normA / 2
+    Y = O.mpk(A, v, p)
+    for k in range(1, p + 1):
+        err = np.linalg.norm(Y[k - 1] - lam ** k * v)
+        bound = 20 * k * len(shape) * EPS * np.linalg.norm(v) * normA ** k
+        assert err <= bound, (k, err, bound)
+
+
+# ------------------------------------------------------------ polynomial forms
+@pytest.mark.parametrize("seed", [0, 1])
+def test_newton_basis_on_eigenvector(seed):
+    # closed form: V_k = prod_{i<=k} (lambda - lambda_i) / sigma_i * v
+    # catches: shift applied to the wrong vector, shifts out of order, sigma misuse
+    shape, js = (11, 8), (9, 7)
+    A = S.laplacian_2d(*shape)
+    v, lam = _grid_mode(shape, js)
+    rng = np.random.default_rng(seed)
+    lambdas = rng.uniform(0, 2, 6)
+    sigmas = rng.uniform(1, 3, 6)
+    V = O.newton_basis(A, v, lambdas, sigmas)
+    f = 1.0
+    assert np.array_equal(V[0], v)
+    for k in range(1, 7):
+        f *= (lam - lambdas[k - 1]) / sigmas[k - 1]
+        assert np.linalg.norm(V[k] - f * v) <= 1e-12 * np.linalg.norm(v) * 8 ** k
+
+
+def test_newton_basis_integer_exact():
+    A = S.laplacian_3d(4, 3, 3)
+    x = S.integer_vector(A.n, 3, bound=1 << 12)
+    lambdas = [1.0, -2.0, 3.0, 0.0]
+    M = int_dense(A)
+    y = x.astype(np.int64)
+    V = O.newton_basis(A, x, lambdas)
+    for k, lm in enumerate(lambdas, start=1):
+        y = M @ y - int(lm) * y
+        assert np.array_equal(V[k], y.astype(np.float64))
+
+
+def test_poly_monomial_on_diagonal():
+    # Eq. (3) on A = diag(d): (sum_k c_k d_i^k) x_i, evaluated by Horner's rule
+    # catches: off-by-one in the coefficient index
+    rng = np.random.default_rng(4)
+    d = rng.uniform(-1.5, 1.5, 300)
+    x = rng.uniform(-1, 1, 300)
+    c = rng.uniform(-1, 1, 9)
+    ref = np.zeros_like(d)
+    for ck in c[::-1]:
+        ref = ref * d + ck
+    got = O.poly_monomial(S.diagonal(d), x, c)
+    assert np.max(np.abs(got - ref * x)) <= 1e-13
+
+
+def test_poly_newton_on_diagonal():
+    rng = np.random.default_rng(5)
+    d = rng.uniform(-1, 1, 200)
+    x = rng.uniform(-1, 1, 200)
+    c = rng.uniform(-1, 1, 7)
+    lam = rng.uniform(-1, 1, 6)
+    ref = np.zeros_like(d)
+    phi = np.ones_like(d)
+    for k in range(7):
+        if k:
+            phi = phi * (d - lam[k - 1])
+        ref += c[k] * phi
+    got = O.poly_newton(S.diagonal(d), x, c, lam)
+    assert np.max(np.abs(got - ref * x)) <= 1e-13
+
+
+@pytest.mark.parametrize("theta,delta", [(0.0, 1.0), (2.0, 1.9), (6.0, 5.5)])
+def test_poly_chebyshev_on_diagonal(theta, delta):
+    # closed form T_k(u) = cos(k arccos u) for |u| <= 1
+    # catches: missing factor 2, wrong sign of t_{k-1}, theta/delta swapped
+    rng = np.random.default_rng(6)
+    u = rng.uniform(-1, 1, 400)
+    d = theta + delta * u
+    x = rng.uniform(-1, 1, 400)
+    c = rng.uniform(-1, 1, 10)
+    ref = sum(c[k] * np.cos(k * np.arccos(u)) for k in range(10))
+    got = O.poly_chebyshev(S.diagonal(d), x, c, theta, delta)
+    assert np.max(np.abs(got - ref * x)) <= 1e-12
+
+
+def test_chebyshev_basis_on_laplacian_mode():
+    shape, js = (10, 10), (8, 9)
+    A = S.laplacian_2d(*shape)
+    v, lam = _grid_mode(shape, js)
+    theta, delta = 4.0, 4.0
+    u = (lam - theta) / delta
+    T = O.chebyshev_basis(A, v, 8, theta, delta)
+    for k in range(9):
+        assert np.linalg.norm(T[k] - math.cos(k * math.acos(u)) * v) <= 1e-12 * 3 ** k * np.linalg.norm(v)
+
+
+# -------------------------------------------------------------- special cases
+def test_special_cases():
+    x = S.uniform_vector(37, 1)
+    assert np.array_equal(O.mpk(S.identity(37), x, 5), np.tile(x, (5, 1)))
+    d = S.uniform_vector(37, 2)
+    Y = O.mpk(S.diagonal(d), x, 4)
+    for k in range(4):
+        ref = x.copy()
+        for _ in range(k + 1):
+            ref = d * ref
+        assert np.array_equal(Y[k], ref)
+    Y = O.mpk(S.cyclic_shift(37), x, 6)
+    for k in range(6):
+        assert np.array_equal(Y[k], np.roll(x, -(k + 1)))
+    Z = S.CSR(37, np.zeros(38, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert np.array_equal(O.mpk(Z, x, 3), np.zeros((3, 37)))
+    one = S.from_dense([[3.0]])
+    assert np.array_equal(O.mpk(one, np.array([2.0]), 3)[:, 0], [6.0, 18.0, 54.0])
+
+
+# --------------------------------------------------------------------- levels
+def _levels_of(A, root=None):
+    level, nl, roots = O.bfs_levels(A, root)
+    return level, nl, roots
+
+
+def test_levels_path_hand_worked(golden_dir):
+    lines = [l.split() for l in open(os.path.join(golden_dir, "path7_levels.txt"))
+             if l.strip() and not l.startswith("#")]
+    edges = [tuple(map(int, e.split("-"))) for e in lines[0][1:]]
+    root = int(lines[1][1])
+    want = {int(a): int(b) for a, b in lines[2:]}
+    M = np.eye(7) * 2
+    for a, b in edges:
+        M[a, b] = M[b, a] = -1
+    level, nl, roots = _levels_of(S.from_dense(M))
+    assert roots == [root]
+    assert nl == 7
+    assert {i: int(level[i]) for i in range(7)} == want
+
+
+def test_levels_closed_forms():
+    lv, nl, r = _levels_of(S.laplacian_1d(50))
+    assert np.array_equal(lv, np.arange(50)) and nl == 50 and r == [0]
+    nx, ny = 13, 9
+    lv, nl, r = _levels_of(S.laplacian_2d(nx, ny))
+    idx = np.arange(nx * ny)
+    assert np.array_equal(lv, idx % nx + idx // nx) and nl == nx + ny - 1
+    n3 = (6, 5, 4)
+    lv, nl, r = _levels_of(S.laplacian_3d(*n3))
+    idx = np.arange(np.prod(n3))
+    i, j, k = idx % 6, (idx // 6) % 5, idx // 30
+    assert np.array_equal(lv, i + j + k) and nl == 6 + 5 + 4 - 2
+    # a directed cyclic shift symmetrises to a ring: level(i) = min(i, n - i)
+    lv, nl, r = _levels_of(S.cyclic_shift(20))
+    assert np.array_equal(lv, np.minimum(np.arange(20), 20 - np.arange(20)))
+
+
+def test_levels_64x64_grid_count():
+    lv, nl, _ = _levels_of(S.laplacian_2d(64))
+    assert nl == 127
+    counts = np.bincount(lv)
+    ell = np.arange(127)
+    assert np.array_equal(counts, np.minimum(ell + 1, 127 - ell))
+
+
+def test_levels_single_long_range_entry():
+    # upper triangular pattern with one entry (0, n-1): symmetrisation makes 0 and
+    # n-1 neighbours (reading R1); every other row is its own component (R3)
+    n = 9
+    M = np.eye(n)
+    M[0, n - 1] = 5.0
+    lv, nl, roots = _levels_of(S.from_dense(M))
+    want = np.array([0] + [i + 1 for i in range(1, n - 1)] + [1])
+    assert np.array_equal(lv, want) and nl == n
+
+
+def test_levels_explicit_root():
+    lv, nl, roots = _levels_of(S.laplacian_2d(8, 8), root=27)
+    i, j = np.arange(64) % 8, np.arange(64) // 8
+    assert roots == [27]
+    assert np.array_equal(lv, np.abs(i - 3) + np.abs(j - 3))
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_levels_against_scipy_and_invariants(seed):
+    # SciPy's unweighted shortest paths are an independent BFS
+    blocks = [S.random_pattern(60 + 10 * seed, 1.2 + 0.4 * (seed % 3), seed + b) for b in range(3)]
+    A = S.block_diagonal(*blocks) if seed % 2 else blocks[0]
+    n = A.n
+    level, nl, roots = O.bfs_levels(A)
+    ptr, adj = O.pattern_graph(A)
+    G = csr_matrix((np.ones(adj.size), adj, ptr), shape=(n, n))
+    D = shortest_path(G, unweighted=True, directed=False, indices=roots)
+    assigned = np.zeros(n, dtype=bool)
+    base = 0
+    for r, drow in zip(roots, D):
+        comp = np.isfinite(drow) & ~assigned
+        assert np.array_equal(level[comp], base + drow[comp].astype(np.int64))
+        base += int(drow[comp].max()) + 1
+        assigned |= comp
+    assert assigned.all() and base == nl
+    # invariants: neighbours differ by <= 1 level, each non-root has a parent one level up
+    rows = np.repeat(np.arange(n), np.diff(ptr))
+    assert np.all(np.abs(level[rows] - level[adj]) <= 1)
+    has_parent = np.zeros(n, dtype=bool)
+    np.logical_or.at(has_parent, rows, level[adj] == level[rows] - 1)
+    is_root = np.zeros(n, dtype=bool)
+    is_root[roots] = True
+    assert np.all(has_parent | is_root)
+    # roots are the components' lowest vertices' pseudo-peripheral nodes: check
+    # George-Liu's stopping rule holds (the last BFS does not increase the eccentricity)
+    for r in roots:
+        lay = O.bfs_layers(ptr, adj, r, np.full(n, -1, dtype=np.int64))
+        last = lay[-1]
+        xm = int(last[np.argmin(ptr[last + 1] - ptr[last])])
+        lay_x = O.bfs_layers(ptr, adj, xm, np.full(n, -1, dtype=np.int64))
+        assert len(lay_x) <= len(lay)
+
+
+def test_bfs_queue_and_layers_agree():
+    A = S.random_pattern(300, 2.5, 11)
+    ptr, adj = O.pattern_graph(A)
+    q = O.bfs_layers_queue(ptr, adj, 0, A.n)
+    dist = np.full(A.n, -1, dtype=np.int64)
+    O.bfs_layers(ptr, adj, 0, dist)
+    assert list(dist) == q
+
+
+def test_permutation_and_permuted_matrix():
+    A = S.random_pattern(120, 4, 21, integer=True)
+    level, nl, _ = O.bfs_levels(A)
+    perm, iperm, level_ptr = O.level_permutation(level, nl)
+    assert np.array_equal(np.sort(perm), np.arange(120))
+    assert np.array_equal(perm[iperm], np.arange(120))
+    assert np.all(np.diff(level[perm]) >= 0)
+    for l in range(nl):
+        seg = perm[level_ptr[l]:level_ptr[l + 1]]
+        assert np.all(level[seg] == l) and np.all(np.diff(seg) > 0)
+    B = O.permute_symmetric(A, perm, iperm)
+    assert np.array_equal(dense(B), dense(A)[np.ix_(perm, perm)])
+    x = S.integer_vector(120, 2, bound=1 << 10)
+    assert np.array_equal(O.mpk(B, x[perm], 4), O.mpk(A, x, 4)[:, perm])
+
+
+# ----------------------------------------------------------- blocked schedule
+def _schedule(A, chunk_rows, nparts):
+    level, nl, _ = O.bfs_levels(A)
+    perm, iperm, level_ptr = O.level_permutation(level, nl)
+    B = O.permute_symmetric(A, perm, iperm)
+    lnew = level[perm]
+    owner = O.chunk_owner(level_ptr, lnew, A.n, chunk_rows, nparts)
+    deps = O.chunk_dependencies(B, chunk_rows)
+    clev = lnew[np.arange(len(deps)) * chunk_rows]
+    return B, perm, owner, deps, clev
+
+
+def test_chunk_owner_and_deps_on_grid():
+    A = S.laplacian_2d(20, 20)
+    B, perm, owner, deps, clev = _schedule(A, 8, 4)
+    assert owner.min() >= 0 and owner.max() <= 3
+    # one hop from every chunk reaches the level before it
+    b1 = O.hop_min(deps, 1)
+    assert np.all(b1[1:] < np.arange(1, len(deps)))
+    # brute force: chunk c waits on c' iff some row of c touches a row of c'
+    Bd = dense(B) != 0
+    Bd = Bd | Bd.T
+    for c in range(len(deps)):
+        touch = Bd[c * 8:(c + 1) * 8].any(axis=0)
+        want = sorted({j // 8 for j in np.nonzero(touch)[0]} - {c})
+        assert list(deps[c]) == want
+
+
+def test_chunk_owner_fraction_rule():
+    # the level sizes of a 1D chain are all 1: every chunk belongs to partition 0
+    A = S.laplacian_1d(40)
+    _, _, owner, _, _ = _schedule(A, 4, 8)
+    assert np.all(owner == 0)
+    # star with centre 0 and leaves 1..16: George-Liu moves the root to leaf 1
+    # (ecc 2 > 1), so the levels are {1}, {0}, {2..16}; the last level of 15 rows
+    # is cut into 8 partitions by position
+    M = np.eye(17)
+    M[0, 1:] = 1
+    A = S.from_dense(M + M.T)
+    level, nl, roots = O.bfs_levels(A)
+    assert roots == [1] and list(np.bincount(level)) == [1, 1, 15]
+    perm, iperm, lp = O.level_permutation(level, nl)
+    own = O.chunk_owner(lp, level[perm], 17, 1, 8)
+    assert list(own) == [0, 0] + [(8 * i) // 15 for i in range(15)]
+
+
+def _min_workers(owner, deps, parts, q):
+    bmin = O.hop_min(deps, q - 1)
+    seqs = [np.nonzero(owner == part)[0] for part in range(parts)]
+    for w in range(1, len(owner) + 1):
+        if all(O.window_ok(sq, w, bmin) for sq in seqs):
+            return w
+    return len(owner)
+
+
+@pytest.mark.parametrize("mk,cr,parts,q,p", [
+    (lambda: S.laplacian_2d(16, 16), 8, 4, 3, 7),
+    (lambda: S.laplacian_3d(6, 6, 6), 16, 8, 4, 4),
+    (lambda: S.random_pattern(200, 3, 5), 8, 2, 2, 5),
+    (lambda: S.block_diagonal(S.laplacian_2d(9, 7), S.identity(5), S.laplacian_1d(30)), 4, 8, 4, 9),
+])
+def test_blocked_schedule_equals_plain_mpk(mk, cr, parts, q, p):
+    # with the fewest workers that meet the window condition, the blocked order
+    # completes and gives bitwise the plain powers of the permuted matrix
+    A = mk()
+    B, perm, owner, deps, clev = _schedule(A, cr, parts)
+    x = S.uniform_vector(A.n, 3)
+    w = _min_workers(owner, deps, parts, q)
+    Y = O.simulate_blocked_mpk(B, x[perm], p, q, cr, owner, deps, w)
+    assert not np.isnan(Y).any()
+    assert np.array_equal(Y, O.mpk(B, x[perm], p))
+
+
+def test_blocked_schedule_deadlocks_when_window_too_small():
+    # a 1D chain with single-row chunks and one worker: power 2 of chunk 0 waits on
+    # chunk 1, which that same worker only starts after finishing chunk 0
+    A = S.laplacian_1d(12)
+    B, perm, owner, deps, clev = _schedule(A, 1, 1)
+    bmin = O.hop_min(deps, 2)
+    assert list(bmin) == [max(0, c - 2) for c in range(12)]
+    seq = np.arange(12)
+    assert not O.window_ok(seq, 1, bmin)
+    with pytest.raises(RuntimeError):
+        O.simulate_blocked_mpk(B, np.ones(12), 3, 3, 1, owner, deps, 1)
+    assert not O.window_ok(seq, 2, bmin) and O.window_ok(seq, 3, bmin)
+    Y = O.simulate_blocked_mpk(B, np.ones(12), 3, 3, 1, owner, deps, 3)
+    assert np.array_equal(Y, O.mpk(B, np.ones(12), 3))
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_window_condition_is_sufficient(seed):
+    rng = np.random.default_rng(seed)
+    A = S.laplacian_2d(int(rng.integers(8, 20)), int(rng.integers(8, 20)))
+    B, perm, owner, deps, clev = _schedule(A, 4, 2)
+    q = int(rng.integers(2, 5))
+    w = _min_workers(owner, deps, 2, q)
+    Y = O.simulate_blocked_mpk(B, np.ones(A.n), q, q, 4, owner, deps, w)
+    assert np.array_equal(Y, O.mpk(B, np.ones(A.n), q))
+
+
+def test_blocked_schedule_operator_kinds():
+    A = S.laplacian_2d(12, 10)
+    B, perm, owner, deps, clev = _schedule(A, 8, 4)
+    x = S.uniform_vector(A.n, 9)[perm]
+    lam = [0.5, 1.0, 1.5, 2.0, 2.5]
+    newton = lambda k, acc, prev, prev2: acc - lam[k - 1] * prev
+    Y = O.simulate_blocked_mpk(B, x, 5, 3, 8, owner, deps, 4, kind=newton)
+    assert np.array_equal(Y, O.newton_basis(B, x, lam)[1:])
+    th, de = 4.0, 4.0
+    cheb = lambda k, acc, prev, prev2: ((acc - th * prev) / de if k == 1
+                                        else 2.0 * (acc - th * prev) / de - prev2)
+    Y = O.simulate_blocked_mpk(B, x, 6, 4, 8, owner, deps, 4, kind=cheb)
+    assert np.array_equal(Y, O.chebyshev_basis(B, x, 6, th, de)[1:])
