@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the temporally blocked matrix power kernel on one MI355X.
+
+Workload: 3D 7-point Laplacian on a 160^3 grid (N = 4,096,000 rows,
+28,518,400 nonzeros, FP64), x uniform[-1, 1] from seed 0, p = 4 powers
+y_k = A^k x, all four stored.  A step is one MPK call with inputs and outputs
+resident in HBM in level order (the plan's permuted space); the plan (BFS
+levels, permutation, layout, schedule) is built once beforehand and its cost
+is reported separately, as the paper treats it as a one-time preprocessing
+cost.  The plain comparator (p back-to-back SpMV launches on the same layout)
+is timed the same way.  GF/s counts 2 flops per nonzero per power.
+
+One JSON line goes to stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_mpk_block_lap3d160_p4.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2309_02228_amd", "csrc", "mpk.hip")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def algorithmic_bytes(n, nnz, p):
+    """Bytes the blocked MPK must move: the CSR matrix once (8-byte values,
+    4-byte column indices, 4-byte row pointers), x read once, p outputs written."""
+    b_mat = nnz * 12 + 4 * (n + 1)
+    return b_mat + 8 * n * (p + 1), b_mat
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()
+
+
+def load_traffic(sha):
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256") != sha:
+        return None
+    return t.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(A, x, p, budget_s):
+    import numpy as np
+    import oracle
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.mpk(A, x, p)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 20:
+            break
+    gf = 2.0 * A.col.size * p * reps / el / 1e9
+    return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+            "sample": f"full 160^3 matrix, p={p}, {reps} complete MPK calls "
+                      f"({el:.1f} s, single-threaded NumPy)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--p", type=int, default=4)
+    ap.add_argument("--grid", type=int, default=160)
+    ap.add_argument("--p-block", type=int, default=0)
+    ap.add_argument("--chunks-per-worker", type=int, default=0)
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["both", "blocked", "plain"], default="both",
+                    help="restrict the launches (for profiler runs)")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU matrix power "
+              "kernel; no multi-GPU path exists (use --gpus 1).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import synth
+    from paper_2309_02228_amd import Plan
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = "cuda:0"
+    g, p = args.grid, args.p
+    A = synth.laplacian_3d(g)
+    n, nnz = A.n, int(A.col.size)
+    log(f"matrix: 3D 7-point Laplacian {g}^3, N={n}, nnz={nnz}")
+    t0 = time.perf_counter()
+    plan = Plan.from_csr(A, p_block=args.p_block or min(p, 15),
+                         chunks_per_worker=args.chunks_per_worker)
+    t_plan = time.perf_counter() - t0
+    plan.upload(dev)
+    torch.cuda.synchronize()
+    t_upload = time.perf_counter() - t0 - t_plan
+    info = plan.info()
+    log(f"plan: {t_plan:.2f} s host planning, {t_upload:.2f} s upload; {info}")
+
+    x = synth.uniform_vector(n, 0)
+    xd = plan.permute(torch.tensor(x, device=dev), 0)  # into level order, on the device
+    Y = torch.empty((p, n), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def timed(plain):
+        for _ in range(args.warmup):
+            plan.apply(xd, p, Y=Y, plain=plain)
+        plan.check()
+        evs = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        evs[0].record(stream)
+        for k in range(args.steps):
+            plan.apply(xd, p, Y=Y, plain=plain)
+            evs[k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t_start
+        plan.check()
+        per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]) * 1e-3
+        return wall, per
+
+    res = {}
+    if args.only in ("both", "blocked"):
+        wall_b, per_b = timed(False)
+        res["blocked"] = (wall_b, per_b)
+        log(f"blocked: {wall_b / args.steps * 1e6:.1f} us/step (median event {np.median(per_b) * 1e6:.1f} us)")
+    if args.only in ("both", "plain"):
+        wall_p, per_p = timed(True)
+        res["plain"] = (wall_p, per_p)
+        log(f"plain:   {wall_p / args.steps * 1e6:.1f} us/step (median event {np.median(per_p) * 1e6:.1f} us)")
+
+    flops = 2.0 * nnz * p
+    b_blk, b_mat = algorithmic_bytes(n, nnz, p)
+    key = "blocked" if "blocked" in res else "plain"
+    wall, per = res[key]
+    value = flops * args.steps / wall / 1e9
+    launches_per_step = (-(-p // info["p_block"])) if key == "blocked" else p
+    avg_launch = float(np.mean(per)) / launches_per_step
+    bytes_per_launch = (b_blk if key == "blocked" else (b_mat + 16 * n)) / launches_per_step
+    achieved = bytes_per_launch / avg_launch / 1e9
+    sha = kernel_sha()
+    traffic = load_traffic(sha) if key == "blocked" else None
+
+    out = {
+        "metric": "MPK GFLOP/s vs p×SpMV (7-pt 160^3, p=4) + solve p50/p99 latency",
+        "value": round(value, 2),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"3D 7-point Laplacian {g}^3 (N={n}, nnz={nnz}), FP64, SELL-64 in BFS level "
+                        f"order, x uniform[-1,1] seed 0, p={p} powers stored, I/O in level order",
+            "p": p, "p_block": info["p_block"], "kernel": key,
+            "chunks_per_worker": args.chunks_per_worker or None,
+            "workers_per_xcd": info["workers_per_xcd"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "kernel": "mpk_block_kernel" if key == "blocked" else "spmv_kernel",
+            "bytes_per_launch": int(bytes_per_launch),
+            "avg_launch_us": round(avg_launch * 1e6, 2),
+        },
+        "plan_build_s": round(t_plan, 3),
+        "plan_upload_s": round(t_upload, 3),
+    }
+    if "plain" in res and "blocked" in res:
+        wp = res["plain"][0]
+        out["plain_gflops"] = round(flops * args.steps / wp / 1e9, 2)
+        out["speedup_vs_plain"] = round(wp / res["blocked"][0], 3)
+        out["plan_build_spmv_equivalents"] = round(t_plan / (wp / args.steps / p), 1)
+        out["roofline_equivalent_frac"] = round(value / (flops / (b_blk / (HBM_PEAK_GBS * 1e9)) / 1e9), 4)
+    out["solve_latency_ms"] = {"p50": None, "p99": None, "note": "served solve not built"}
+    if not args.no_cpu_baseline and args.only == "both":
+        log("cpu baseline: FP64 oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(A, x, p, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,265 @@
+/*
+ * mpk.h -- C ABI of the MI355X matrix power kernel library (libmpk.so).
+ *
+ * The library computes the matrix power kernel (MPK) of Sec. 3 of
+ * "Algebraic temporal blocking for sparse iterative solvers on multi-core
+ * CPUs" (Alappat, Thies, Hager, Fehske, Wellein): for a square sparse A and a
+ * vector x, y_k = A y_{k-1} for k = 1..p with y_0 = x (Alg. 1), every power
+ * stored.  Powers are temporally blocked by the BFS level structure of the
+ * matrix graph (Sec. 3): a persistent kernel keeps each 64-row chunk of the
+ * matrix in registers while it advances that chunk through a block of q
+ * powers, waiting only for the neighbouring chunks of the previous power.
+ * The polynomial forms built on the MPK are also provided: a fixed-coefficient
+ * polynomial p(A) x (Sec. 5.2, Eq. (3); Chebyshev as in Sec. 5.3) and the
+ * Newton basis of the s-step Krylov method (Sec. 4).
+ *
+ * Conventions (every entry point):
+ *   - Return an mpk_status; nothing aborts the process and no C++ exception
+ *     crosses the ABI.  mpk_last_error() returns a thread-local message for
+ *     the last failing call of the calling thread.
+ *   - Argument and CSR validation is synchronous.  Device work is enqueued
+ *     asynchronously on `stream` (a hipStream_t passed as void*; NULL is the
+ *     legacy default stream).  Device-side failures (the watchdog of the
+ *     blocked kernel) are reported by mpk_check_device().
+ *   - Vector pointers marked "device" must point to device memory of the
+ *     current device and hold FP64 values; they must not alias each other
+ *     unless stated.  The caller owns every buffer it passes; the library
+ *     owns only the plan object (host memory), released by mpk_destroy().
+ *   - A plan may be used from one stream at a time (its launches share
+ *     per-plan synchronisation counters).  Calls that overlap on two streams
+ *     are not supported.
+ *   - Indices are 0-based int32; n and nnz must be below 2^31.
+ */
+#ifndef MPK_H
+#define MPK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpk_plan_s* mpk_plan_t; /* opaque; owned by the library */
+
+typedef enum {
+    MPK_OK = 0,
+    MPK_ERR_ARG = -1,         /* bad scalar argument or null pointer          */
+    MPK_ERR_CSR = -2,         /* malformed CSR input                          */
+    MPK_ERR_NOMEM = -3,       /* host allocation failed, or buffer too small  */
+    MPK_ERR_HIP = -4,         /* a HIP runtime call failed                    */
+    MPK_ERR_UNSUPPORTED = -5, /* valid request the library does not provide   */
+    MPK_ERR_STATE = -6,       /* call order violated (e.g. apply before upload) */
+    MPK_ERR_DEVICE = -7       /* device-side failure reported by the kernel   */
+} mpk_status;
+
+/* flags for mpk_apply / poly_apply / sstep_basis */
+#define MPK_IO_PERMUTED 1u /* x and outputs are in the plan's level order (perm space) */
+#define MPK_PLAIN 2u       /* comparator: one full SpMV launch per power (Alg. 1),
+                              same layout and same per-row arithmetic            */
+
+/* polynomial kinds for poly_apply */
+#define MPK_POLY_MONOMIAL 0  /* phi_k = A^k                                     */
+#define MPK_POLY_NEWTON 1    /* phi_k = prod_{i<=k} (A - lambda_i I)            */
+#define MPK_POLY_CHEBYSHEV 2 /* phi_k = T_k((A - theta I) / delta)             */
+
+/* call kinds for mpk_work_bytes */
+#define MPK_CALL_APPLY 0
+#define MPK_CALL_POLY 1
+#define MPK_CALL_SSTEP 2
+
+typedef struct {
+    int32_t root_mode;       /* 0: per connected component, the George-Liu
+                                pseudo-peripheral node reached from the
+                                component's lowest-index row; 1: `root` is the
+                                BFS root of its component (others as in 0)    */
+    int32_t root;            /* used when root_mode == 1; 0 <= root < n       */
+    int32_t p_block;         /* powers per blocked launch, q (p_opt of Sec. 3);
+                                1..15; 0 selects 4                           */
+    int32_t workers_per_xcd; /* waves per XCD of the blocked kernel; 0 = as
+                                many as stay resident together               */
+    int32_t watchdog_polls;  /* polls before a dependency wait of the blocked
+                                kernel gives up and reports MPK_ERR_DEVICE;
+                                0 = default (2^20, about a second); a
+                                negative value makes every wait give up at
+                                once (forces the failure path in tests)      */
+    int32_t chunks_per_worker; /* chunks a wave of the blocked kernel carries
+                                together through a block (1, 2 or 4; 0 = 2;
+                                1 when rows need more than 16 register slots) */
+    int32_t reserved[10];    /* must be zero                                  */
+} mpk_options;
+
+/* Fills *opt with the defaults (all zero). */
+void mpk_options_default(mpk_options* opt);
+
+/* Library version string (static storage). */
+const char* mpk_version(void);
+
+/* Message for the last failing call on this thread (static thread-local
+ * storage, valid until the next failing call on the thread). */
+const char* mpk_last_error(void);
+
+/*
+ * Host-side planning (Sec. 3: BFS levels of the matrix graph and an execution
+ * order derived from them).  Input is a host CSR matrix: rowptr[n+1] monotone
+ * with rowptr[0] == 0, col[rowptr[n]] with columns strictly ascending in each
+ * row and in [0, n), val[rowptr[n]] FP64.  Empty rows and explicit zeros are
+ * allowed; n == 0 is allowed.  The library copies what it needs: the caller
+ * keeps ownership of the arrays, which may be freed on return.
+ *
+ * Steps: (1) the undirected graph of pattern(A) union pattern(A^T) without
+ * self-loops; (2) BFS levels per component from the root chosen by
+ * opt->root_mode, components in order of their lowest row index, levels of a
+ * later component numbered after those of earlier ones; (3) perm sorts rows
+ * by (level, original index); (4) the permuted matrix P A P^T in SELL-64
+ * layout (chunks of 64 consecutive permuted rows, column-major inside a
+ * chunk); (5) chunk ownership by XCD from each chunk's position inside its
+ * level, per-XCD chunk sequences, and per-chunk dependency lists.
+ *
+ * On success *plan_out owns a new plan and *device_bytes_out (if not NULL)
+ * receives the size of the device buffer mpk_upload needs.
+ * Errors: MPK_ERR_ARG (null pointers, n < 0, bad options), MPK_ERR_CSR
+ * (non-monotone rowptr, column out of range, unsorted or duplicate columns),
+ * MPK_ERR_NOMEM.
+ */
+mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int32_t* col,
+                            const double* val, const mpk_options* opt,
+                            mpk_plan_t* plan_out, size_t* device_bytes_out);
+
+/*
+ * Level structure of a plan (host arrays supplied by the caller; any pointer
+ * may be NULL to skip it).  nlevels receives L; level_ptr[L+1] the first
+ * permuted row of each level; level_of_row[n] the level of each original row;
+ * perm[n] with perm[new] = old; iperm[n] with iperm[old] = new.
+ */
+mpk_status mpk_get_levels(mpk_plan_t plan, int32_t* nlevels, int32_t* level_ptr,
+                          int32_t* level_of_row, int32_t* perm, int32_t* iperm);
+
+/*
+ * Chunk partition of a plan: *nchunks chunks of *chunk_rows (= 64) permuted
+ * rows (the last may be shorter); owner[nchunks] (may be NULL) receives the
+ * XCD partition (0..*nparts-1) that computes each chunk.
+ */
+mpk_status mpk_get_partition(mpk_plan_t plan, int32_t* nchunks, int32_t* chunk_rows,
+                             int32_t* nparts, int32_t* owner);
+
+/*
+ * Chunk dependency lists: chunk c waits, before computing power k >= 2 of a
+ * block, until every chunk in dep_idx[dep_ptr[c] .. dep_ptr[c+1]-1] has
+ * finished power k-1.  The lists are the chunks holding a row adjacent to a
+ * row of c in the symmetrised pattern, c itself excluded, ascending.  Call
+ * once with dep_ptr = dep_idx = NULL to get *ndeps, then with arrays of
+ * nchunks+1 and *ndeps entries.
+ */
+mpk_status mpk_get_deps(mpk_plan_t plan, int64_t* ndeps, int32_t* dep_ptr, int32_t* dep_idx);
+
+/*
+ * Smallest number of workers (waves) per XCD partition for which the blocked
+ * kernel cannot deadlock with blocks of q powers: for every partition and
+ * every position i >= W in its chunk sequence, the chunk at position i - W
+ * has a smaller index than every chunk within q-1 dependency hops of the
+ * chunk at position i.  1 <= q <= p_block.
+ */
+mpk_status mpk_min_workers(mpk_plan_t plan, int32_t q, int32_t* workers_per_xcd);
+
+/*
+ * Binds caller-owned device memory (at least device_bytes from
+ * mpk_build_levels; 256-byte aligned) and uploads the permuted matrix, the
+ * permutation, the schedule tables and zeroed synchronisation counters on
+ * `stream`.  The buffer must stay allocated, and must not be written by the
+ * caller, for as long as the plan is used.  Re-uploading into another buffer
+ * is allowed once earlier work on the plan has finished.
+ */
+mpk_status mpk_upload(mpk_plan_t plan, void* dev_buf, size_t bytes, void* stream);
+
+/*
+ * Device work-buffer size (bytes) that mpk_apply (call = MPK_CALL_APPLY),
+ * poly_apply (MPK_CALL_POLY, p = degree d) or sstep_basis (MPK_CALL_SSTEP,
+ * p = s) needs with the given flags.  Zero when none is needed.
+ */
+mpk_status mpk_work_bytes(mpk_plan_t plan, int32_t call, int32_t p, uint32_t flags,
+                          size_t* bytes);
+
+/*
+ * Matrix power kernel (Sec. 3, Alg. 1): Y[(k-1)*ldy + i] = (A^k x)[i] for
+ * k = 1..p.  x (device, n) is only read; Y (device, p*ldy, ldy >= n) receives
+ * p vectors; y_0 = x is not stored.  With MPK_IO_PERMUTED, x and Y are in perm
+ * space (x_perm[i] = x[perm[i]]), which is the fast path; otherwise the library
+ * permutes through `work` (mpk_work_bytes).  Powers run in blocks of
+ * q = p_block (the last block holds the remaining p mod q, Sec. 3 remainder
+ * loop).  MPK_PLAIN runs p full SpMV launches instead (the comparator).
+ * Results of the blocked and plain paths are bitwise identical.
+ * Errors: MPK_ERR_ARG (p < 1, ldy < n, null pointers, work too small),
+ * MPK_ERR_STATE (not uploaded), MPK_ERR_HIP.
+ */
+mpk_status mpk_apply(mpk_plan_t plan, const double* x, double* Y, int64_t ldy, int32_t p,
+                     uint32_t flags, void* work, size_t work_bytes, void* stream);
+
+/*
+ * Polynomial applied to a vector (Sec. 5.2, Eq. (3)):
+ *   out = sum_{k=0..d} c[k] * phi_k(A) x
+ * kind MPK_POLY_MONOMIAL: phi_k = A^k; MPK_POLY_NEWTON: phi_0 = I,
+ * phi_k = (A - params[k-1] I) phi_{k-1} (params = lambda[d]);
+ * MPK_POLY_CHEBYSHEV: the Chebyshev polynomials on [theta - delta,
+ * theta + delta] with params = {theta, delta}: t_0 = x,
+ * t_1 = (A - theta I) x / delta, t_{k+1} = 2 (A - theta I) t_k / delta - t_{k-1}.
+ * c (host, d+1 entries) and params (host) are copied before return.
+ * x and out are device vectors of n entries (perm space with
+ * MPK_IO_PERMUTED); out must not alias x.  Intermediate vectors live in
+ * `work` (two vectors, plus two more without MPK_IO_PERMUTED).
+ * Errors: MPK_ERR_ARG (d < 0, unknown kind, delta == 0, null pointers, work
+ * too small), MPK_ERR_STATE, MPK_ERR_HIP.
+ */
+mpk_status poly_apply(mpk_plan_t plan, int32_t kind, int32_t d, const double* c,
+                      const double* params, const double* x, double* out, uint32_t flags,
+                      void* work, size_t work_bytes, void* stream);
+
+/*
+ * s-step Krylov basis with constant real shifts (Sec. 4):
+ *   V[:,0] = v, V[:,k] = (A - lambda[k-1] I) V[:,k-1] / sigma[k-1], k = 1..s,
+ * with column k at V + k*ldv (device, ldv >= n).  lambda (host, s entries) are
+ * the Newton shifts (all zero gives the monomial basis); sigma (host, s
+ * entries) are column scalings, NULL meaning all ones.  v (device, n) may
+ * alias V's column 0.  Perm space with MPK_IO_PERMUTED; otherwise through
+ * `work`.  Errors: MPK_ERR_ARG (s < 1, ldv < n, zero sigma, null pointers,
+ * work too small), MPK_ERR_STATE, MPK_ERR_HIP.
+ */
+mpk_status sstep_basis(mpk_plan_t plan, int32_t s, const double* lambda, const double* sigma,
+                       const double* v, double* V, int64_t ldv, uint32_t flags, void* work,
+                       size_t work_bytes, void* stream);
+
+/*
+ * Permutes a device vector into the plan's level order, x_perm[i] = x[perm[i]]
+ * (direction 0), or back, x[perm[i]] = x_perm[i] (direction 1).  in and out
+ * must not alias.
+ */
+mpk_status mpk_permute(mpk_plan_t plan, const double* in, double* out, int32_t direction,
+                       void* stream);
+
+/*
+ * Waits for `stream`, then reads the plan's device status word.  MPK_OK if
+ * every blocked launch so far finished normally; MPK_ERR_DEVICE if a wave of
+ * the blocked kernel gave up waiting (watchdog: a dependency not satisfied
+ * within about a second, e.g. because the GPU could not keep every worker
+ * resident); the message names the chunk and power.  Clears the word.
+ */
+mpk_status mpk_check_device(mpk_plan_t plan, void* stream);
+
+/*
+ * Plan facts: n, nnz, number of levels, chunk count, SELL slots (padded
+ * entries), register slots per row used by the blocked kernel, the blocked
+ * kernel's workers per XCD for blocks of p_block powers, and the effective
+ * p_block.  Any pointer may be NULL.
+ */
+mpk_status mpk_plan_info(mpk_plan_t plan, int64_t* n, int64_t* nnz, int32_t* nlevels,
+                         int32_t* nchunks, int64_t* sell_slots, int32_t* reg_slots,
+                         int32_t* workers_per_xcd, int32_t* p_block);
+
+/* Releases the plan (not the caller's device buffers).  NULL is ignored. */
+void mpk_destroy(mpk_plan_t plan);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MPK_H */

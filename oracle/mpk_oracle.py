@@ -11,7 +11,8 @@ Parity status
 -------------
 pinned   spmv, mpk, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
-         chunk_owner, chunk_dependencies, hop_min, window_ok,
+         chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
+         hop_min, window_ok, min_workers,
          simulate_blocked_mpk
          (pins: exact integer arithmetic, closed-form Laplacian eigenpairs,
          closed-form grid levels, scipy shortest paths, brute force on tiny
@@ -48,12 +49,13 @@ READINGS = {
           "where r0 = C*c is its first row and level_start/level_size describe the "
           "level of r0; each partition processes its chunks in ascending order.",
     "R7": "Chunk c may compute power k once every chunk holding a row adjacent to c's "
-          "rows in the symmetrised pattern has finished power k-1. Partition x runs W_x "
-          "workers; worker i takes the partition's chunks i, i+W_x, ... and carries each "
-          "through all q powers of a block before taking the next. This order cannot "
-          "deadlock when, for every partition and every position i >= W_x, the chunk at "
-          "position i - W_x has a smaller index than every chunk within q-1 dependency "
-          "hops of the chunk at position i.",
+          "rows in the symmetrised pattern has finished power k-1. Each partition's "
+          "ascending chunk sequence is cut into units of G consecutive chunks; the "
+          "partition runs W_x workers, worker i takes units i, i+W_x, ... and carries "
+          "all chunks of a unit together through the q powers of a block before taking "
+          "the next. This order cannot deadlock when, for every partition and every "
+          "unit position j >= W_x, the first chunk of unit j - W_x has a smaller index "
+          "than the first chunk of every unit within q-1 unit-dependency hops of unit j.",
     "R8": "Newton basis: V_k = (A - lambda_k I) V_{k-1} / sigma_k, the product of distinct "
           "shifted factors (the printed powers (A - lambda_2 I)^2 ... are read as this "
           "product).",
@@ -364,49 +366,88 @@ def chunk_dependencies(B, chunk_rows):
     return deps
 
 
-def hop_min(deps, hops):
-    """B[c] = smallest chunk index within ``hops`` dependency hops of c (c included).
+def worker_units(owner, group):
+    """Units of ``group`` consecutive chunks of each partition's ascending sequence
+    (reading R7).  Returns (units, unit_part): a list of chunk-index arrays and the
+    partition of each unit, units of partition 0 first, each partition in order."""
+    owner = np.asarray(owner)
+    nparts = int(owner.max()) + 1 if owner.size else 0
+    units, part = [], []
+    for x in range(nparts):
+        seq = np.nonzero(owner == x)[0]
+        for j in range(0, seq.size, group):
+            units.append(seq[j:j + group])
+            part.append(x)
+    return units, np.asarray(part, dtype=np.int64)
 
-    The dependency relation is symmetric (it comes from a symmetrised pattern),
-    so this is also the smallest chunk from which c is reachable in ``hops``.
-    """
-    b = np.arange(len(deps), dtype=np.int64)
+
+def unit_dependencies(units, deps, nchunks):
+    """Other units holding a chunk that some chunk of the unit waits on."""
+    unit_of = np.empty(nchunks, dtype=np.int64)
+    for u, ch in enumerate(units):
+        unit_of[ch] = u
+    out = []
+    for u, ch in enumerate(units):
+        d = np.unique(np.concatenate([unit_of[deps[c]] for c in ch])) if len(ch) else \
+            np.zeros(0, dtype=np.int64)
+        out.append(d[d != u])
+    return out
+
+
+def hop_min(udeps, first, hops):
+    """B[u] = smallest first-chunk index among units within ``hops`` dependency hops
+    of unit u (u included).  The relation is symmetric (it comes from a
+    symmetrised pattern), so this is also the smallest first chunk of a unit from
+    which u is reachable in ``hops``."""
+    b = np.asarray(first, dtype=np.int64).copy()
     for _ in range(max(0, hops)):
         nb = b.copy()
-        for c, dl in enumerate(deps):
+        for u, dl in enumerate(udeps):
             if dl.size:
-                nb[c] = min(nb[c], int(b[dl].min()))
+                nb[u] = min(nb[u], int(b[dl].min()))
         b = nb
     return b
 
 
-def window_ok(seq, workers, bmin):
-    """Deadlock-freedom condition of reading R7 for one partition's chunk sequence
-    ``seq`` (ascending chunk indices) run by ``workers`` workers, where ``bmin`` is
-    ``hop_min(deps, q - 1)``.
+def window_ok(first, workers, bmin):
+    """Deadlock-freedom condition of reading R7 for one partition: ``first`` are the
+    first-chunk indices of the partition's units in order, ``bmin`` their values of
+    ``hop_min(..., q - 1)``.
 
-    Proof sketch: in a deadlock take the waiting (chunk, power) of smallest chunk
-    index c.  Each chunk on its chain of waits lies within q-1 hops of c (powers
-    drop by one per hop and power 1 never waits).  A worker that has not reached
-    such a chunk c' is at least W_x positions behind it, hence on a chunk of index
-    below bmin[c'] <= c, and is itself waiting: a contradiction with the choice
-    of c.
+    Proof sketch: in a deadlock take the waiting unit whose first chunk c is
+    smallest.  Each unit on its chain of waits lies within q-1 hops (powers drop
+    by one per hop and power 1 never waits).  A worker that has not reached such a
+    unit u is at least W_x units behind it, hence on a unit whose first chunk is
+    below bmin[u] <= c, and is itself waiting: a contradiction with the choice of c.
     """
-    seq = np.asarray(seq, dtype=np.int64)
-    if seq.size <= workers:
+    first = np.asarray(first, dtype=np.int64)
+    if first.size <= workers:
         return True
-    return bool(np.all(seq[:-workers] < np.asarray(bmin)[seq[workers:]]))
+    return bool(np.all(first[:-workers] < np.asarray(bmin)[workers:]))
 
 
-def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None):
+def min_workers(owner, deps, group, q):
+    """Smallest W meeting ``window_ok`` in every partition (direct search)."""
+    units, upart = worker_units(owner, group)
+    udeps = unit_dependencies(units, deps, len(deps))
+    first = np.array([u[0] for u in units], dtype=np.int64)
+    bmin = hop_min(udeps, first, q - 1)
+    parts = [np.nonzero(upart == x)[0] for x in range(int(upart.max()) + 1 if upart.size else 0)]
+    for w in range(1, len(units) + 1):
+        if all(window_ok(first[pu], w, bmin[pu]) for pu in parts):
+            return w
+    return max(1, len(units))
+
+
+def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None, group=1):
     """Execute the blocked MPK on permuted matrix B sequentially, in the worker
     order of reading R7, and return Y (p, n) in permuted space.
 
-    ``workers`` is the number of workers per partition (an int, or one int per
-    partition).  Every worker repeatedly tries to advance its current
-    (chunk, power); a chunk's power k is computed only when all chunks it waits
-    on have finished power k-1.  Values not yet computed are NaN, so a wrong
-    order shows up as NaN in the result; a full sweep without progress raises
+    ``workers`` is the number of workers per partition.  A worker repeatedly
+    tries to advance its current (unit, power): power k of all chunks of the unit
+    is computed only when every chunk they wait on, outside the unit, has
+    finished power k-1.  Values not yet computed are NaN, so a wrong order
+    shows up as NaN in the result; a full sweep without progress raises
     (deadlock).  Powers are done in blocks of q (R10).  ``kind`` is None for
     plain powers, or a callable (k, acc, prev, prev2) -> y_k for the shifted
     and three-term forms, where acc = (A y_{k-1}) on the chunk's rows and
@@ -416,38 +457,40 @@ def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None
     nchunks = len(deps)
     Y = np.full((p + 1, n), np.nan)
     Y[0] = x
-    nparts = int(np.max(owner)) + 1 if nchunks else 0
-    seqs = [np.nonzero(np.asarray(owner) == part)[0] for part in range(nparts)]
-    wk = [int(workers[i]) if np.ndim(workers) else int(workers) for i in range(nparts)]
+    units, upart = worker_units(owner, group)
+    nparts = int(upart.max()) + 1 if upart.size else 0
+    pu = [np.nonzero(upart == part)[0] for part in range(nparts)]
+    inside = [set(u.tolist()) for u in units]
     base = 0
     while base < p:
         qb = min(q, p - base)
         done = np.zeros(nchunks, dtype=np.int64)  # powers finished in this block
-        state = [[part, w, 1] for part in range(nparts) for w in range(wk[part])]
-        remaining = nchunks * qb
+        state = [[part, w, 1] for part in range(nparts) for w in range(workers)]
+        remaining = len(units) * qb
         while remaining:
             progress = False
             for st in state:
                 part, pos, k = st
-                seq = seqs[part]
-                if pos >= seq.size:
+                if pos >= pu[part].size:
                     continue
-                c = int(seq[pos])
-                if k > 1 and deps[c].size and done[deps[c]].min() < k - 1:
+                u = int(pu[part][pos])
+                if k > 1 and any(done[d] < k - 1 for c in units[u] for d in deps[c]
+                                 if int(d) not in inside[u]):
                     continue
-                r0, r1 = c * chunk_rows, min(n, (c + 1) * chunk_rows)
                 gk = base + k
-                acc = spmv_rows(B, Y[gk - 1], r0, r1)
-                if kind is None:
-                    Y[gk, r0:r1] = acc
-                else:
-                    prev2 = Y[gk - 2, r0:r1] if gk >= 2 else None
-                    Y[gk, r0:r1] = kind(gk, acc, Y[gk - 1, r0:r1], prev2)
-                done[c] = k
+                for c in units[u]:
+                    r0, r1 = int(c) * chunk_rows, min(n, (int(c) + 1) * chunk_rows)
+                    acc = spmv_rows(B, Y[gk - 1], r0, r1)
+                    if kind is None:
+                        Y[gk, r0:r1] = acc
+                    else:
+                        prev2 = Y[gk - 2, r0:r1] if gk >= 2 else None
+                        Y[gk, r0:r1] = kind(gk, acc, Y[gk - 1, r0:r1], prev2)
+                    done[c] = k
                 remaining -= 1
                 progress = True
                 if k == qb:
-                    st[1], st[2] = pos + wk[part], 1
+                    st[1], st[2] = pos + workers, 1
                 else:
                     st[2] = k + 1
             if not progress:

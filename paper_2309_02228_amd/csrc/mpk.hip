@@ -1,0 +1,948 @@
+// MI355X (gfx950) kernels and C ABI of the matrix power kernel library.
+//
+// Device layout of a plan (one caller-owned buffer, 256-byte aligned pieces):
+//   SELL-64 values (f64) and columns (i32, -1 = padding) of P A P^T,
+//   chunk slot offsets (i64), perm / iperm (i32), per-XCD chunk sequences,
+//   dependency lists, per-chunk completion words (u32) and a status block.
+//
+// Two kernels compute powers:
+//   * spmv_kernel: one launch per power (Alg. 1), waves stride over the
+//     chunks of their XCD partition.  It is the plain comparator.
+//   * mpk_block_kernel: one persistent launch per block of q powers.  Each
+//     wave takes a chunk, keeps its SELL slots in registers and advances it
+//     through the q powers; before power k it waits until every dependency
+//     chunk has published power k-1.  The matrix therefore streams from HBM
+//     once per block instead of once per power (Sec. 3, temporal blocking
+//     along the level structure).
+// Vectors written inside the blocked kernel use device-coherent (sc1)
+// stores and loads: the L2 of one XCD is not kept coherent with plain
+// write-back stores of another XCD, and agent-scope fences cost far more
+// than the work they would guard.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mpk.h"
+#include "planner.h"
+
+#define MPK_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+using mpk::kChunkRows;
+using mpk::kParts;
+
+constexpr int kWaves = 4;                 // waves per workgroup
+constexpr int kBlockThreads = kWaves * 64;
+constexpr int kMaxQ = mpk::kMaxBlock;      // powers per blocked launch
+constexpr int kSpinLimit = 1 << 20;        // watchdog polls per dependency wait
+constexpr uint32_t kEpochLimit = 1u << 27; // done words hold epoch * 16 + power
+// Completion words sit one per 128-byte line: neighbouring chunks publish from
+// different waves (and XCDs); sharing a line makes every write-through
+// invalidate the line under the other chunks' pollers.
+constexpr int kFlagStride = 32;
+
+enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2 };
+
+// ------------------------------------------------------------------ device
+struct DevPlan {
+    const double* val;
+    const int32_t* col;
+    const int64_t* off;
+    const int32_t* seq;
+    const int32_t* seq_ptr;
+    const int32_t* dep_ptr;
+    const int32_t* dep_idx;
+    uint32_t* done;
+    int32_t* status;  // [0] code, [1] chunk, [2] power
+    int32_t n;
+};
+
+// Per-launch operator coefficients, indexed by the local power 0..q-1.
+struct Coefs {
+    double lam[kMaxQ];  // Newton shift
+    double sig[kMaxQ];  // Newton column scaling
+    double c[kMaxQ];    // polynomial coefficient of the power
+    double theta, delta;
+};
+
+__device__ __forceinline__ double load_coherent(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void store_coherent(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint32_t load_word(const uint32_t* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Operator kind applied to s = (A y_{k-1})_i with the row's own y_{k-1}, y_{k-2}.
+template <int KIND>
+__device__ __forceinline__ double finish(double s, double prev, double prev2, int gk, int kl,
+                                         const Coefs& C) {
+    if (KIND == KIND_MONO) return s;
+    if (KIND == KIND_NEWTON) return fma(-C.lam[kl], prev, s) / C.sig[kl];
+    const double t = fma(-C.theta, prev, s);
+    return gk == 1 ? t / C.delta : (2.0 * t) / C.delta - prev2;
+}
+
+// ---- plain comparator: one power per launch --------------------------------
+struct SpmvArgs {
+    DevPlan P;
+    const double* in;     // y_{k-1}
+    const double* prev2;  // y_{k-2} (Chebyshev), may be null
+    double* out;          // y_k
+    const double* acc_in; // polynomial accumulator before this power (null: c0 * x)
+    double* acc_out;      // polynomial accumulator after this power (null: none)
+    double c0;
+    int gk;               // global power index of this launch
+    Coefs C;              // entry 0 describes this power
+};
+
+// Row sum over the chunk's slots j = 0..width-1, in this order, as one FMA
+// chain.  Slots are fetched in batches of 8 (columns and values first, then
+// the gathers) so that a batch costs two memory round trips.
+__device__ __forceinline__ double row_sum_mem(const DevPlan& P, const double* in, int64_t off,
+                                              int width, int lane) {
+    double s = 0.0;
+    for (int j0 = 0; j0 < width; j0 += 8) {
+        int cj[8];
+        double vj[8], xj[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            cj[t] = -1;
+            vj[t] = 0.0;
+            if (j0 + t < width) {
+                const int64_t slot = off + (int64_t)(j0 + t) * kChunkRows + lane;
+                cj[t] = __builtin_nontemporal_load(P.col + slot);
+                vj[t] = __builtin_nontemporal_load(P.val + slot);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) xj[t] = cj[t] >= 0 ? in[cj[t]] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t)
+            if (cj[t] >= 0) s = fma(vj[t], xj[t], s);
+    }
+    return s;
+}
+
+// Waves take chunks c = wave, wave + W, ... (a streaming pass; the matrix is
+// not reused within a launch, so no XCD partition is needed).
+template <int KIND, bool POLY>
+__global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int W = gridDim.x * kWaves;
+    const int nchunks = (a.P.n + kChunkRows - 1) / kChunkRows;
+    for (int c = blockIdx.x * kWaves + (threadIdx.x >> 6); c < nchunks; c += W) {
+        const int row = c * kChunkRows + lane;
+        const int64_t off = a.P.off[c];
+        const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
+        const double s = row_sum_mem(a.P, a.in, off, width, lane);
+        if (row < a.P.n) {
+            const double prev = (KIND != KIND_MONO || POLY) ? a.in[row] : 0.0;
+            const double prev2 = (KIND == KIND_CHEB && a.prev2) ? a.prev2[row] : 0.0;
+            const double y = finish<KIND>(s, prev, prev2, a.gk, 0, a.C);
+            a.out[row] = y;
+            if (POLY) {
+                const double acc = a.acc_in ? a.acc_in[row] : a.c0 * prev;
+                a.acc_out[row] = fma(a.C.c[0], y, acc);
+            }
+        }
+    }
+}
+
+// ---- blocked kernel: q powers per persistent launch -------------------------
+struct BlockArgs {
+    DevPlan P;
+    const double* in;     // y_base (block input; written before the launch)
+    const double* prev2;  // y_{base-1} (Chebyshev only), may be null
+    double* out0;         // destination of y_{base+1}
+    int64_t out_ld;       // distance between consecutive destinations
+    int out_mod;          // destinations cycle every out_mod powers (ring), else large
+    int base_slot;        // slot of y_{base+1} inside the cycle
+    double* copy0;        // if set: copy0[row] = in[row] (basis column 0)
+    const double* acc_in; // polynomial accumulator before the block (null: c0 * x)
+    double* acc_out;      // polynomial accumulator after the block (null: none)
+    double c0;
+    int base;             // powers finished before this launch
+    int q;                // powers in this launch
+    int workers;          // waves per partition
+    int spin_limit;       // watchdog polls; negative: give up at once
+    uint32_t epoch;
+    Coefs C;
+};
+
+__device__ __forceinline__ double* dest(const BlockArgs& a, int kl) {
+    return a.out0 + (int64_t)((a.base_slot + kl) % a.out_mod) * a.out_ld;
+}
+
+// Raises the device status (first failure wins) and returns false.
+__device__ bool give_up(const BlockArgs& a, int c, int kl) {
+    if ((threadIdx.x & 63) == 0 && atomicCAS(a.P.status, 0, (int)MPK_ERR_DEVICE) == 0) {
+        __hip_atomic_store(a.P.status + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.P.status + 2, a.base + kl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return false;
+}
+
+// Polls completion words until each lane's word has reached `target`.
+// Returns false if the watchdog fired or another wave already gave up.
+template <int G>
+__device__ bool poll_until(const BlockArgs& a, const uint32_t* const (&w)[G], bool (&ok)[G],
+                           uint32_t target, int c_report, int kl) {
+    for (int spin = 0;; ++spin) {
+        bool all = true;
+        if (a.spin_limit >= 0) {
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (!ok[g]) ok[g] = (int32_t)(load_word(w[g]) - target) >= 0;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) all = all && ok[g];
+        if (__all(all)) return true;
+        if ((spin & 255) == 255 || a.spin_limit < 0) {
+            if (__hip_atomic_load(a.P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+                return false;
+            if (spin >= a.spin_limit) return give_up(a, c_report, kl);
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+// Unit = G consecutive chunks of a partition's sequence, carried together
+// through the q powers of a block; its SELL slots stay in registers.
+template <int REG, int G, int KIND, bool POLY>
+__global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int part = blockIdx.x % kParts;
+    const int worker = (blockIdx.x / kParts) * kWaves + (threadIdx.x >> 6);
+    const int s0 = a.P.seq_ptr[part], s1 = a.P.seq_ptr[part + 1];
+    const int nunits = (s1 - s0 + G - 1) / G;
+    for (int u = worker; u < nunits; u += a.workers) {
+        int c[G], width[G], d0[G], d1[G], row[G];
+        int64_t off[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int pos = s0 + u * G + g;
+            c[g] = pos < s1 ? a.P.seq[pos] : -1;
+        }
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            off[g] = 0;
+            width[g] = 0;
+            d0[g] = d1[g] = 0;
+            row[g] = c[g] * kChunkRows + lane;
+            if (c[g] >= 0) {
+                off[g] = a.P.off[c[g]];
+                width[g] = (int)((a.P.off[c[g] + 1] - off[g]) / kChunkRows);
+                d0[g] = a.P.dep_ptr[c[g]];
+                d1[g] = a.P.dep_ptr[c[g] + 1];
+            }
+        }
+        // first batch of each dependency list: one lane per dependency
+        const uint32_t* w[G];
+        bool need[G];
+        bool long_list = false;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int i = d0[g] + lane;
+            need[g] = i < d1[g];
+            w[g] = a.P.done + kFlagStride * (need[g] ? a.P.dep_idx[i] : 0);
+            long_list = long_list || (d1[g] - d0[g] > 64);
+        }
+        double rv[G][REG];
+        int rc[G][REG];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int j = 0; j < REG; ++j) {
+                rc[g][j] = -1;
+                rv[g][j] = 0.0;
+                if (j < width[g]) {
+                    const int64_t slot = off[g] + (int64_t)j * kChunkRows + lane;
+                    rc[g][j] = __builtin_nontemporal_load(a.P.col + slot);
+                    rv[g][j] = __builtin_nontemporal_load(a.P.val + slot);
+                }
+            }
+        // the row's own previous value is needed by the shifted kinds, the
+        // polynomial accumulator and the basis copy only
+        const bool need_prev = KIND != KIND_MONO || POLY || a.copy0 != nullptr;
+        double prev[G], prev2[G], acc[G];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const bool act = c[g] >= 0 && row[g] < a.P.n;
+            prev[g] = (act && need_prev) ? a.in[row[g]] : 0.0;
+            prev2[g] = (KIND == KIND_CHEB && act && a.prev2) ? a.prev2[row[g]] : 0.0;
+            if (a.copy0 && act) a.copy0[row[g]] = prev[g];
+            acc[g] = 0.0;
+            if (POLY && act) acc[g] = a.acc_in ? a.acc_in[row[g]] : a.c0 * prev[g];
+        }
+        for (int kl = 0; kl < a.q; ++kl) {
+            const double* src = kl == 0 ? a.in : dest(a, kl - 1);
+            if (kl > 0) {
+                const uint32_t target = a.epoch * 16u + (uint32_t)kl;
+                bool ok[G];
+#pragma unroll
+                for (int g = 0; g < G; ++g) ok[g] = !need[g];
+                if (!poll_until<G>(a, w, ok, target, c[0], kl)) return;
+                if (long_list) {  // dependency lists longer than one wave
+#pragma unroll
+                    for (int g = 0; g < G; ++g)
+                        for (int b = d0[g] + 64; b < d1[g]; b += 64) {
+                            const int i = b + lane;
+                            const uint32_t* wx[1] = {a.P.done + kFlagStride * (i < d1[g] ? a.P.dep_idx[i] : 0)};
+                            bool okx[1] = {!(i < d1[g])};
+                            if (!poll_until<1>(a, wx, okx, target, c[g], kl)) return;
+                        }
+                }
+                asm volatile("" ::: "memory");
+            }
+            double s[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                s[g] = 0.0;
+                double xv[REG];
+#pragma unroll
+                for (int j = 0; j < REG; ++j)
+                    xv[j] = rc[g][j] < 0 ? 0.0 : (kl == 0 ? src[rc[g][j]] : load_coherent(src + rc[g][j]));
+#pragma unroll
+                for (int j = 0; j < REG; ++j)
+                    if (rc[g][j] >= 0) s[g] = fma(rv[g][j], xv[j], s[g]);
+            }
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                for (int j = REG; j < width[g]; ++j) {  // slots beyond the register cache
+                    const int64_t slot = off[g] + (int64_t)j * kChunkRows + lane;
+                    const int cj = a.P.col[slot];
+                    if (cj >= 0) s[g] = fma(a.P.val[slot], kl == 0 ? src[cj] : load_coherent(src + cj), s[g]);
+                }
+            double* dst = dest(a, kl);
+            const bool last = kl + 1 == a.q;
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                const double y = finish<KIND>(s[g], prev[g], prev2[g], a.base + kl + 1, kl, a.C);
+                if (c[g] >= 0 && row[g] < a.P.n) {
+                    if (!last) store_coherent(dst + row[g], y);
+                    else dst[row[g]] = y;  // nobody reads the last power in this launch
+                }
+                if (POLY) acc[g] = fma(a.C.c[kl], y, acc[g]);
+                prev2[g] = prev[g];
+                prev[g] = y;
+            }
+            if (!last) {
+                // publish power kl+1 of the unit's chunks once their stores completed
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+                    if (lane == g && c[g] >= 0)
+                        __hip_atomic_store(a.P.done + kFlagStride * c[g], a.epoch * 16u + (uint32_t)(kl + 1),
+                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
+        }
+        if (POLY) {
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+                if (c[g] >= 0 && row[g] < a.P.n) a.acc_out[row[g]] = acc[g];
+        }
+    }
+}
+
+__global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// dir 0: out[i] = in[perm[i]]; dir 1: out[perm[i]] = in[i]; `nvec` vectors
+__global__ void permute_kernel(const double* in, int64_t ld_in, double* out, int64_t ld_out,
+                               const int32_t* perm, int32_t n, int dir) {
+    const double* src = in + blockIdx.y * ld_in;
+    double* dst = out + blockIdx.y * ld_out;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (dir == 0) dst[i] = src[perm[i]];
+        else dst[perm[i]] = src[i];
+    }
+}
+
+__global__ void scale_kernel(const double* x, double* out, double a, int32_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = a * x[i];
+}
+
+// ------------------------------------------------------------------ host
+thread_local std::string g_err;
+
+mpk_status fail(mpk_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                   \
+    do {                                                                                \
+        hipError_t e_ = (expr);                                                         \
+        if (e_ != hipSuccess) return fail(MPK_ERR_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t val, col, off, perm, iperm, seq, seq_ptr, dep_ptr, dep_idx, done, status, total;
+};
+
+Layout make_layout(const mpk::HostPlan& H) {
+    Layout L{};
+    size_t o = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = o;
+        o = align256(o + bytes);
+        return at;
+    };
+    const size_t slots = H.sell_val.size();
+    L.val = take(slots * 8);
+    L.col = take(slots * 4);
+    L.off = take((H.nchunks + 1) * 8);
+    L.perm = take((size_t)H.n * 4);
+    L.iperm = take((size_t)H.n * 4);
+    L.seq = take((size_t)H.nchunks * 4);
+    L.seq_ptr = take((kParts + 1) * 4);
+    L.dep_ptr = take((H.nchunks + 1) * 4);
+    L.dep_idx = take(std::max<size_t>(1, H.dep_idx.size()) * 4);
+    L.done = take(std::max<size_t>(1, H.nchunks) * 4 * kFlagStride);
+    L.status = take(16);
+    L.total = o;
+    return L;
+}
+
+}  // namespace
+
+struct mpk_plan_s {
+    mpk::HostPlan H;
+    Layout L{};
+    char* dev = nullptr;  // caller-owned device buffer once uploaded
+    DevPlan D{};
+    uint32_t epoch = 0;
+    int workers = 0;       // waves per partition of the blocked kernel
+    int grid_block = 0;    // workgroups of the blocked launch
+    int grid_spmv = 0;     // workgroups of a plain launch
+    int q_eff = 1;         // powers per blocked launch actually used
+};
+
+namespace {
+
+using BlockFn = void (*)(BlockArgs);
+using SpmvFn = void (*)(SpmvArgs);
+
+template <int G, int KIND, bool POLY>
+BlockFn block_fn(int reg) {
+    switch (reg) {
+        case 8: return mpk_block_kernel<8, G, KIND, POLY>;
+        case 16: return mpk_block_kernel<16, G, KIND, POLY>;
+        case 32: return mpk_block_kernel<32, G, KIND, POLY>;
+        default: return mpk_block_kernel<48, G, KIND, POLY>;
+    }
+}
+
+template <int G>
+BlockFn pick_block_g(int reg, int kind, bool poly) {
+    if (kind == KIND_MONO) return poly ? block_fn<G, KIND_MONO, true>(reg) : block_fn<G, KIND_MONO, false>(reg);
+    if (kind == KIND_NEWTON) return poly ? block_fn<G, KIND_NEWTON, true>(reg) : block_fn<G, KIND_NEWTON, false>(reg);
+    return poly ? block_fn<G, KIND_CHEB, true>(reg) : block_fn<G, KIND_CHEB, false>(reg);
+}
+
+// The planner keeps one chunk per worker when rows need 32 or more slots.
+BlockFn pick_block(int reg, int group, int kind, bool poly) {
+    if (reg >= 32 || group == 1) return pick_block_g<1>(reg, kind, poly);
+    if (group == 2) return pick_block_g<2>(reg, kind, poly);
+    return pick_block_g<4>(reg, kind, poly);
+}
+
+SpmvFn pick_spmv(int kind, bool poly) {
+    if (kind == KIND_MONO) return poly ? spmv_kernel<KIND_MONO, true> : spmv_kernel<KIND_MONO, false>;
+    if (kind == KIND_NEWTON) return poly ? spmv_kernel<KIND_NEWTON, true> : spmv_kernel<KIND_NEWTON, false>;
+    return poly ? spmv_kernel<KIND_CHEB, true> : spmv_kernel<KIND_CHEB, false>;
+}
+
+int grid_1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256)); }
+
+mpk_status check_uploaded(mpk_plan_t p) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (!p->dev) return fail(MPK_ERR_STATE, "plan has no device buffer: call mpk_upload first");
+    return MPK_OK;
+}
+
+// Launches the blocked kernel for powers base+1 .. base+q.
+mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, BlockArgs a) {
+    if (p->epoch + 1 >= kEpochLimit) {  // restart the done words from zero
+        const int64_t nc = (int64_t)std::max<int32_t>(1, p->H.nchunks) * kFlagStride;
+        fill_u32_kernel<<<grid_1d(nc), 256, 0, st>>>(p->D.done, nc, 0u);
+        HIP_TRY(hipGetLastError());
+        p->epoch = 0;
+    }
+    a.P = p->D;
+    a.epoch = ++p->epoch;
+    a.workers = p->workers;
+    a.spin_limit = p->H.watchdog == 0 ? kSpinLimit : p->H.watchdog;
+    hipLaunchKernelGGL(pick_block(p->H.reg_slots, p->H.group, kind, poly), dim3(p->grid_block),
+                       dim3(kBlockThreads), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+mpk_status launch_spmv(mpk_plan_t p, hipStream_t st, int kind, bool poly, SpmvArgs a) {
+    a.P = p->D;
+    hipLaunchKernelGGL(pick_spmv(kind, poly), dim3(p->grid_spmv), dim3(kBlockThreads), 0, st, a);
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+mpk_status permute_vecs(mpk_plan_t p, hipStream_t st, const double* in, int64_t ld_in, double* out,
+                        int64_t ld_out, int nvec, int dir) {
+    if (p->H.n == 0 || nvec == 0) return MPK_OK;
+    const int32_t* perm = (const int32_t*)(p->dev + p->L.perm);
+    permute_kernel<<<dim3(grid_1d(p->H.n), nvec), 256, 0, st>>>(in, ld_in, out, ld_out, perm, p->H.n, dir);
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
+
+// Runs the p powers of one operator kind.  dest_k(k) gives the destination of
+// y_k (k >= 1).  For POLY the accumulator `acc` (n) receives sum c_k y_k.
+struct PowerJob {
+    int kind = KIND_MONO;
+    bool poly = false;
+    int p = 0;
+    const double* x = nullptr;  // y_0
+    double* out0 = nullptr;     // destinations: out0 + ((k-1) % mod) * ld
+    int64_t ld = 0;
+    int mod = 1 << 30;
+    double* copy0 = nullptr;
+    double* acc = nullptr;
+    std::vector<double> lam, sig, c;  // per global power k (index k-1); c[0] = c_0
+    double theta = 0, delta = 1;
+};
+
+double* job_dest(const PowerJob& j, int k) { return j.out0 + (int64_t)((k - 1) % j.mod) * j.ld; }
+const double* job_vec(const PowerJob& j, int k) { return k == 0 ? j.x : job_dest(j, k); }
+
+mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plain) {
+    if (j.p == 0) return MPK_OK;
+    if (p->H.n == 0) return MPK_OK;
+    if (plain) {
+        for (int k = 1; k <= j.p; ++k) {
+            SpmvArgs a{};
+            a.in = job_vec(j, k - 1);
+            a.prev2 = (j.kind == KIND_CHEB && k >= 2) ? job_vec(j, k - 2) : nullptr;
+            a.out = job_dest(j, k);
+            a.acc_in = (j.poly && k >= 2) ? j.acc : nullptr;
+            a.acc_out = j.poly ? j.acc : nullptr;
+            a.c0 = j.poly ? j.c[0] : 0.0;
+            a.gk = k;
+            a.C.lam[0] = j.lam.empty() ? 0.0 : j.lam[k - 1];
+            a.C.sig[0] = j.sig.empty() ? 1.0 : j.sig[k - 1];
+            a.C.c[0] = j.poly ? j.c[k] : 0.0;
+            a.C.theta = j.theta;
+            a.C.delta = j.delta;
+            if (k == 1 && j.copy0) {
+                HIP_TRY(hipMemcpyAsync(j.copy0, j.x, sizeof(double) * p->H.n, hipMemcpyDeviceToDevice, st));
+            }
+            mpk_status s = launch_spmv(p, st, j.kind, j.poly, a);
+            if (s != MPK_OK) return s;
+        }
+        return MPK_OK;
+    }
+    for (int base = 0; base < j.p; base += p->q_eff) {
+        const int q = std::min(p->q_eff, j.p - base);
+        BlockArgs a{};
+        a.in = job_vec(j, base);
+        a.prev2 = (j.kind == KIND_CHEB && base >= 1) ? job_vec(j, base - 1) : nullptr;
+        a.out0 = j.out0;
+        a.out_ld = j.ld;
+        a.out_mod = j.mod;
+        a.base_slot = base % j.mod;
+        a.copy0 = base == 0 ? j.copy0 : nullptr;
+        a.acc_in = (j.poly && base > 0) ? j.acc : nullptr;
+        a.acc_out = j.poly ? j.acc : nullptr;
+        a.c0 = j.poly ? j.c[0] : 0.0;
+        a.base = base;
+        a.q = q;
+        for (int kl = 0; kl < q; ++kl) {
+            a.C.lam[kl] = j.lam.empty() ? 0.0 : j.lam[base + kl];
+            a.C.sig[kl] = j.sig.empty() ? 1.0 : j.sig[base + kl];
+            a.C.c[kl] = j.poly ? j.c[base + kl + 1] : 0.0;
+        }
+        a.C.theta = j.theta;
+        a.C.delta = j.delta;
+        mpk_status s = launch_block(p, st, j.kind, j.poly, a);
+        if (s != MPK_OK) return s;
+    }
+    return MPK_OK;
+}
+
+}  // namespace
+
+// =================================================================== C ABI
+MPK_API void mpk_options_default(mpk_options* opt) {
+    if (opt) memset(opt, 0, sizeof *opt);
+}
+
+MPK_API const char* mpk_version(void) { return "mpk-mi355x 0.1 (gfx950)"; }
+
+MPK_API const char* mpk_last_error(void) { return g_err.c_str(); }
+
+MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int32_t* col,
+                                    const double* val, const mpk_options* opt,
+                                    mpk_plan_t* plan_out, size_t* device_bytes_out) {
+    if (!plan_out) return fail(MPK_ERR_ARG, "plan_out is null");
+    *plan_out = nullptr;
+    if (n < 0) return fail(MPK_ERR_ARG, "n must be >= 0 (got %d)", n);
+    if (!rowptr) return fail(MPK_ERR_ARG, "rowptr is null");
+    if (n > 0 && rowptr[n] > 0 && (!col || !val)) return fail(MPK_ERR_ARG, "col or val is null");
+    mpk_options o{};
+    if (opt) o = *opt;
+    for (int i = 0; i < 10; ++i)
+        if (o.reserved[i] != 0) return fail(MPK_ERR_ARG, "mpk_options.reserved must be zero");
+    if (o.root_mode != 0 && o.root_mode != 1) return fail(MPK_ERR_ARG, "root_mode must be 0 or 1");
+    if (o.root_mode == 1 && (o.root < 0 || o.root >= n)) return fail(MPK_ERR_ARG, "root out of range");
+    if (o.p_block < 0 || o.p_block > mpk::kMaxBlock)
+        return fail(MPK_ERR_ARG, "p_block must be in 0..%d", mpk::kMaxBlock);
+    if (o.workers_per_xcd < 0) return fail(MPK_ERR_ARG, "workers_per_xcd must be >= 0");
+    if (o.chunks_per_worker != 0 && o.chunks_per_worker != 1 && o.chunks_per_worker != 2 &&
+        o.chunks_per_worker != 4)
+        return fail(MPK_ERR_ARG, "chunks_per_worker must be 0, 1, 2 or 4");
+    std::string why = mpk::validate_csr(n, rowptr, col);
+    if (!why.empty()) return fail(MPK_ERR_CSR, "%s", why.c_str());
+    mpk_plan_s* p = new (std::nothrow) mpk_plan_s;
+    if (!p) return fail(MPK_ERR_NOMEM, "out of host memory");
+    try {
+        p->H.root_mode = o.root_mode;
+        p->H.root = o.root;
+        p->H.p_block = o.p_block ? o.p_block : 4;
+        p->H.workers_req = o.workers_per_xcd;
+        p->H.watchdog = o.watchdog_polls;
+        p->H.group = o.chunks_per_worker ? o.chunks_per_worker : 2;
+        mpk::build_plan(p->H, n, rowptr, col, val);
+        p->L = make_layout(p->H);
+    } catch (const std::bad_alloc&) {
+        delete p;
+        return fail(MPK_ERR_NOMEM, "out of host memory while planning");
+    }
+    if (device_bytes_out) *device_bytes_out = p->L.total;
+    *plan_out = p;
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_get_levels(mpk_plan_t p, int32_t* nlevels, int32_t* level_ptr,
+                                  int32_t* level_of_row, int32_t* perm, int32_t* iperm) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    const auto& H = p->H;
+    if (nlevels) *nlevels = H.nlevels;
+    if (level_ptr) std::copy(H.level_ptr.begin(), H.level_ptr.end(), level_ptr);
+    if (level_of_row) std::copy(H.level_of_row.begin(), H.level_of_row.end(), level_of_row);
+    if (perm) std::copy(H.perm.begin(), H.perm.end(), perm);
+    if (iperm) std::copy(H.iperm.begin(), H.iperm.end(), iperm);
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_get_partition(mpk_plan_t p, int32_t* nchunks, int32_t* chunk_rows,
+                                     int32_t* nparts, int32_t* owner) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (nchunks) *nchunks = p->H.nchunks;
+    if (chunk_rows) *chunk_rows = kChunkRows;
+    if (nparts) *nparts = kParts;
+    if (owner) std::copy(p->H.owner.begin(), p->H.owner.end(), owner);
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_get_deps(mpk_plan_t p, int64_t* ndeps, int32_t* dep_ptr, int32_t* dep_idx) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (ndeps) *ndeps = (int64_t)p->H.dep_idx.size();
+    if (dep_ptr) std::copy(p->H.dep_ptr.begin(), p->H.dep_ptr.end(), dep_ptr);
+    if (dep_idx) std::copy(p->H.dep_idx.begin(), p->H.dep_idx.end(), dep_idx);
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_min_workers(mpk_plan_t p, int32_t q, int32_t* w) {
+    if (!p || !w) return fail(MPK_ERR_ARG, "null argument");
+    if (q < 1 || q > p->H.p_block) return fail(MPK_ERR_ARG, "q must be in 1..p_block (%d)", p->H.p_block);
+    *w = p->H.min_workers[q];
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_plan_info(mpk_plan_t p, int64_t* n, int64_t* nnz, int32_t* nlevels,
+                                 int32_t* nchunks, int64_t* sell_slots, int32_t* reg_slots,
+                                 int32_t* workers_per_xcd, int32_t* p_block) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (n) *n = p->H.n;
+    if (nnz) *nnz = p->H.nnz;
+    if (nlevels) *nlevels = p->H.nlevels;
+    if (nchunks) *nchunks = p->H.nchunks;
+    if (sell_slots) *sell_slots = (int64_t)p->H.sell_val.size();
+    if (reg_slots) *reg_slots = p->H.reg_slots;
+    if (workers_per_xcd) *workers_per_xcd = p->workers;
+    if (p_block) *p_block = p->dev ? p->q_eff : p->H.p_block;
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (!dev_buf) return fail(MPK_ERR_ARG, "dev_buf is null");
+    if (((uintptr_t)dev_buf & 255) != 0) return fail(MPK_ERR_ARG, "dev_buf must be 256-byte aligned");
+    if (bytes < p->L.total)
+        return fail(MPK_ERR_NOMEM, "device buffer too small: %zu < %zu bytes", bytes, p->L.total);
+    hipStream_t st = (hipStream_t)stream;
+    const auto& H = p->H;
+    const auto& L = p->L;
+    char* d = (char*)dev_buf;
+    auto put = [&](size_t at, const void* src, size_t nb) -> hipError_t {
+        if (nb == 0) return hipSuccess;
+        return hipMemcpyAsync(d + at, src, nb, hipMemcpyHostToDevice, st);
+    };
+    HIP_TRY(put(L.val, H.sell_val.data(), H.sell_val.size() * 8));
+    HIP_TRY(put(L.col, H.sell_col.data(), H.sell_col.size() * 4));
+    HIP_TRY(put(L.off, H.chunk_off.data(), H.chunk_off.size() * 8));
+    HIP_TRY(put(L.perm, H.perm.data(), H.perm.size() * 4));
+    HIP_TRY(put(L.iperm, H.iperm.data(), H.iperm.size() * 4));
+    HIP_TRY(put(L.seq, H.seq.data(), H.seq.size() * 4));
+    HIP_TRY(put(L.seq_ptr, H.seq_ptr.data(), H.seq_ptr.size() * 4));
+    HIP_TRY(put(L.dep_ptr, H.dep_ptr.data(), H.dep_ptr.size() * 4));
+    HIP_TRY(put(L.dep_idx, H.dep_idx.data(), H.dep_idx.size() * 4));
+    const int64_t nd = (int64_t)std::max<int32_t>(1, H.nchunks) * kFlagStride;
+    fill_u32_kernel<<<grid_1d(nd), 256, 0, st>>>((uint32_t*)(d + L.done), nd, 0u);
+    HIP_TRY(hipGetLastError());
+    fill_u32_kernel<<<1, 64, 0, st>>>((uint32_t*)(d + L.status), 4, 0u);
+    HIP_TRY(hipGetLastError());
+    // the host vectors must outlive the asynchronous copies
+    HIP_TRY(hipStreamSynchronize(st));
+
+    DevPlan D{};
+    D.val = (const double*)(d + L.val);
+    D.col = (const int32_t*)(d + L.col);
+    D.off = (const int64_t*)(d + L.off);
+    D.seq = (const int32_t*)(d + L.seq);
+    D.seq_ptr = (const int32_t*)(d + L.seq_ptr);
+    D.dep_ptr = (const int32_t*)(d + L.dep_ptr);
+    D.dep_idx = (const int32_t*)(d + L.dep_idx);
+    D.done = (uint32_t*)(d + L.done);
+    D.status = (int32_t*)(d + L.status);
+    D.n = H.n;
+    p->D = D;
+    p->dev = d;
+    p->epoch = 0;
+
+    // launch shapes: every workgroup of the blocked kernel must be resident at
+    // once (waves wait on each other), so its grid is the occupancy limit
+    int dev_id = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev_id));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &occ, (const void*)pick_block(H.reg_slots, H.group, KIND_CHEB, true), kBlockThreads, 0));
+    int maxlen = 0;
+    for (int x = 0; x < kParts; ++x) maxlen = std::max(maxlen, H.seq_ptr[x + 1] - H.seq_ptr[x]);
+    const int maxunits = (maxlen + H.group - 1) / H.group;
+    int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
+    wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
+    if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));
+    p->grid_block = wg_per_part * kParts;
+    p->workers = wg_per_part * kWaves;
+    p->q_eff = 1;
+    for (int q = H.p_block; q >= 1; --q)
+        if (H.min_workers[q] <= p->workers) {
+            p->q_eff = q;
+            break;
+        }
+    p->grid_spmv = std::max(1, std::min(cus * 8, (H.nchunks + kWaves - 1) / kWaves));
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_work_bytes(mpk_plan_t p, int32_t call, int32_t pw, uint32_t flags, size_t* bytes) {
+    if (!p || !bytes) return fail(MPK_ERR_ARG, "null argument");
+    if (pw < 0) return fail(MPK_ERR_ARG, "p must be >= 0");
+    const size_t v = (size_t)p->H.n * 8;
+    const bool perm = flags & MPK_IO_PERMUTED;
+    switch (call) {
+        case MPK_CALL_APPLY: *bytes = perm ? 0 : v * (1 + (size_t)pw); break;
+        case MPK_CALL_POLY: *bytes = v * (perm ? 2 : 4); break;
+        case MPK_CALL_SSTEP: *bytes = perm ? 0 : v * (1 + (size_t)pw); break;
+        default: return fail(MPK_ERR_ARG, "unknown call kind %d", call);
+    }
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_apply(mpk_plan_t p, const double* x, double* Y, int64_t ldy, int32_t pw,
+                             uint32_t flags, void* work, size_t work_bytes, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (pw < 1) return fail(MPK_ERR_ARG, "p must be >= 1 (got %d)", pw);
+    if (ldy < p->H.n) return fail(MPK_ERR_ARG, "ldy (%lld) < n (%d)", (long long)ldy, p->H.n);
+    if (p->H.n > 0 && (!x || !Y)) return fail(MPK_ERR_ARG, "x or Y is null");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    size_t need = 0;
+    mpk_work_bytes(p, MPK_CALL_APPLY, pw, flags, &need);
+    if (need > 0 && (!work || work_bytes < need))
+        return fail(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const bool permuted = flags & MPK_IO_PERMUTED;
+    PowerJob j;
+    j.p = pw;
+    if (permuted) {
+        j.x = x;
+        j.out0 = Y;
+        j.ld = ldy;
+    } else {
+        double* xw = (double*)work;
+        s = permute_vecs(p, st, x, 0, xw, 0, 1, 0);
+        if (s != MPK_OK) return s;
+        j.x = xw;
+        j.out0 = xw + p->H.n;
+        j.ld = p->H.n;
+    }
+    s = run_powers(p, st, j, flags & MPK_PLAIN);
+    if (s != MPK_OK) return s;
+    if (!permuted) s = permute_vecs(p, st, j.out0, p->H.n, Y, ldy, pw, 1);
+    return s;
+}
+
+MPK_API mpk_status poly_apply(mpk_plan_t p, int32_t kind, int32_t d, const double* c,
+                              const double* params, const double* x, double* out, uint32_t flags,
+                              void* work, size_t work_bytes, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (d < 0) return fail(MPK_ERR_ARG, "degree must be >= 0 (got %d)", d);
+    if (kind < MPK_POLY_MONOMIAL || kind > MPK_POLY_CHEBYSHEV) return fail(MPK_ERR_ARG, "unknown kind %d", kind);
+    if (!c) return fail(MPK_ERR_ARG, "coefficients are null");
+    if (kind != MPK_POLY_MONOMIAL && d > 0 && !params) return fail(MPK_ERR_ARG, "params are null");
+    if (kind == MPK_POLY_CHEBYSHEV && d > 0 && params[1] == 0.0) return fail(MPK_ERR_ARG, "delta must be nonzero");
+    if (p->H.n > 0 && (!x || !out)) return fail(MPK_ERR_ARG, "x or out is null");
+    if (x == out && p->H.n > 0) return fail(MPK_ERR_ARG, "out must not alias x");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    size_t need = 0;
+    mpk_work_bytes(p, MPK_CALL_POLY, d, flags, &need);
+    if (!work || work_bytes < need)
+        return fail(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n = p->H.n;
+    if (n == 0) return MPK_OK;
+    const bool permuted = flags & MPK_IO_PERMUTED;
+    double* w = (double*)work;
+    const double* xin = x;
+    double* acc = out;
+    if (!permuted) {
+        s = permute_vecs(p, st, x, 0, w + 2 * (size_t)n, 0, 1, 0);
+        if (s != MPK_OK) return s;
+        xin = w + 2 * (size_t)n;
+        acc = w + 3 * (size_t)n;
+    }
+    if (d == 0) {
+        scale_kernel<<<grid_1d(n), 256, 0, st>>>(xin, acc, c[0], n);
+        HIP_TRY(hipGetLastError());
+    } else {
+        PowerJob j;
+        j.kind = kind == MPK_POLY_MONOMIAL ? KIND_MONO : kind == MPK_POLY_NEWTON ? KIND_NEWTON : KIND_CHEB;
+        j.poly = true;
+        j.p = d;
+        j.x = xin;
+        j.out0 = w;  // ring of two vectors: t_k in slot (k-1) % 2
+        j.ld = n;
+        j.mod = 2;
+        j.acc = acc;
+        j.c.assign(c, c + d + 1);
+        if (j.kind == KIND_NEWTON) j.lam.assign(params, params + d);
+        if (j.kind == KIND_CHEB) {
+            j.theta = params[0];
+            j.delta = params[1];
+        }
+        s = run_powers(p, st, j, flags & MPK_PLAIN);
+        if (s != MPK_OK) return s;
+    }
+    if (!permuted) s = permute_vecs(p, st, acc, 0, out, 0, 1, 1);
+    return s;
+}
+
+MPK_API mpk_status sstep_basis(mpk_plan_t p, int32_t sdeg, const double* lambda, const double* sigma,
+                               const double* v, double* V, int64_t ldv, uint32_t flags, void* work,
+                               size_t work_bytes, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (sdeg < 1) return fail(MPK_ERR_ARG, "s must be >= 1 (got %d)", sdeg);
+    if (ldv < p->H.n) return fail(MPK_ERR_ARG, "ldv (%lld) < n (%d)", (long long)ldv, p->H.n);
+    if (!lambda) return fail(MPK_ERR_ARG, "lambda is null");
+    if (sigma)
+        for (int k = 0; k < sdeg; ++k)
+            if (sigma[k] == 0.0) return fail(MPK_ERR_ARG, "sigma[%d] is zero", k);
+    if (p->H.n > 0 && (!v || !V)) return fail(MPK_ERR_ARG, "v or V is null");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    size_t need = 0;
+    mpk_work_bytes(p, MPK_CALL_SSTEP, sdeg, flags, &need);
+    if (need > 0 && (!work || work_bytes < need))
+        return fail(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t n = p->H.n;
+    if (n == 0) return MPK_OK;
+    const bool permuted = flags & MPK_IO_PERMUTED;
+    PowerJob j;
+    j.kind = KIND_NEWTON;
+    j.p = sdeg;
+    j.lam.assign(lambda, lambda + sdeg);
+    j.sig = sigma ? std::vector<double>(sigma, sigma + sdeg) : std::vector<double>(sdeg, 1.0);
+    double* Vp = V;
+    int64_t ld = ldv;
+    if (!permuted) {
+        Vp = (double*)work;
+        ld = n;
+        s = permute_vecs(p, st, v, 0, Vp, 0, 1, 0);
+        if (s != MPK_OK) return s;
+        j.x = Vp;
+    } else {
+        j.x = v;
+        if (v != V) j.copy0 = V;
+    }
+    j.out0 = Vp + ld;
+    j.ld = ld;
+    s = run_powers(p, st, j, flags & MPK_PLAIN);
+    if (s != MPK_OK) return s;
+    if (!permuted) s = permute_vecs(p, st, Vp, ld, V, ldv, sdeg + 1, 1);
+    return s;
+}
+
+MPK_API mpk_status mpk_permute(mpk_plan_t p, const double* in, double* out, int32_t direction, void* stream) {
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    if (direction != 0 && direction != 1) return fail(MPK_ERR_ARG, "direction must be 0 or 1");
+    if (p->H.n > 0 && (!in || !out)) return fail(MPK_ERR_ARG, "null vector");
+    if (in == out && p->H.n > 0) return fail(MPK_ERR_ARG, "in and out must not alias");
+    return permute_vecs(p, (hipStream_t)stream, in, 0, out, 0, 1, direction);
+}
+
+MPK_API mpk_status mpk_check_device(mpk_plan_t p, void* stream) {
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    int32_t h[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpy(h, p->D.status, sizeof h, hipMemcpyDeviceToHost));
+    if (h[0] == 0) return MPK_OK;
+    fill_u32_kernel<<<1, 64, 0, (hipStream_t)stream>>>((uint32_t*)p->D.status, 4, 0u);
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    return fail(MPK_ERR_DEVICE,
+                "blocked kernel watchdog: chunk %d waited too long before power %d "
+                "(not every worker was resident, or a dependency never completed)",
+                h[1], h[2]);
+}
+
+MPK_API void mpk_destroy(mpk_plan_t p) { delete p; }

@@ -1,0 +1,54 @@
+// Host-side planner of the MPK library: BFS level structure, level-order
+// permutation, SELL-64 layout of the permuted matrix, chunk-to-XCD partition
+// and chunk dependency lists.  Plain C++17, no HIP.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace mpk {
+
+constexpr int kChunkRows = 64;  // rows per chunk = lanes per wavefront
+constexpr int kParts = 8;       // XCD partitions of the MI355X
+constexpr int kMaxBlock = 15;   // largest p_block (4 bits of the done counters)
+
+struct HostPlan {
+    int32_t n = 0;
+    int64_t nnz = 0;
+    // options
+    int32_t root_mode = 0, root = 0, p_block = 4, workers_req = 0, watchdog = 0;
+    int32_t group = 2;  // chunks a worker carries together (G)
+
+    // Sec. 3 level structure
+    int32_t nlevels = 0;
+    std::vector<int32_t> level_ptr;     // nlevels + 1, permuted row offsets
+    std::vector<int32_t> level_of_row;  // n, by original row
+    std::vector<int32_t> perm, iperm;   // perm[new] = old, iperm[old] = new
+    std::vector<int32_t> roots;         // BFS root of each component
+
+    // SELL-64 layout of P A P^T
+    int32_t nchunks = 0;
+    std::vector<int64_t> chunk_off;  // nchunks + 1, slot offsets (multiples of 64)
+    std::vector<double> sell_val;    // slots
+    std::vector<int32_t> sell_col;   // slots, -1 = padding
+    int32_t max_width = 0;
+    int32_t reg_slots = 8;  // slots per row the blocked kernel keeps in registers
+
+    // partition and dependencies
+    std::vector<int32_t> owner;          // nchunks
+    std::vector<int32_t> seq, seq_ptr;   // chunks of each partition, ascending; kParts + 1
+    std::vector<int32_t> dep_ptr;        // nchunks + 1
+    std::vector<int32_t> dep_idx;        // dependency chunk ids
+    std::vector<int32_t> min_workers;    // index q = 0..p_block (entry 0 unused), in units
+                                         // of G chunks per worker
+};
+
+// Validates the CSR input; returns an empty string or an error message.
+std::string validate_csr(int32_t n, const int32_t* rowptr, const int32_t* col);
+
+// Builds every host table of the plan.  Input must be valid (validate_csr).
+void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* col,
+                const double* val);
+
+}  // namespace mpk

@@ -1,0 +1,262 @@
+"""Thin Python binding of libmpk.so (argument marshalling only).
+
+Every step of the matrix power kernel runs in the library: the host planner
+(C++) and the HIP kernels for gfx950.  PyTorch provides device memory and the
+current stream.  There is no fallback: if the library is missing or fails to
+load, importing this module raises.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmpk.so")
+
+MPK_IO_PERMUTED = 1
+MPK_PLAIN = 2
+POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
+CALL_APPLY, CALL_POLY, CALL_SSTEP = 0, 1, 2
+
+STATUS = {0: "MPK_OK", -1: "MPK_ERR_ARG", -2: "MPK_ERR_CSR", -3: "MPK_ERR_NOMEM",
+          -4: "MPK_ERR_HIP", -5: "MPK_ERR_UNSUPPORTED", -6: "MPK_ERR_STATE",
+          -7: "MPK_ERR_DEVICE"}
+
+# every entry point declared in include/mpk.h
+EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_levels",
+           "mpk_get_levels", "mpk_get_partition", "mpk_get_deps", "mpk_min_workers",
+           "mpk_upload", "mpk_work_bytes", "mpk_apply", "poly_apply", "sstep_basis",
+           "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy"]
+
+
+class MPKError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("root_mode", ctypes.c_int32), ("root", ctypes.c_int32),
+                ("p_block", ctypes.c_int32), ("workers_per_xcd", ctypes.c_int32),
+                ("watchdog_polls", ctypes.c_int32), ("chunks_per_worker", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 10)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                          "or python paper_2309_02228_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I32, I64, SZ, U32, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
+                               ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p)
+    pI32, pI64, pSZ = (ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int64),
+                       ctypes.POINTER(ctypes.c_size_t))
+    sig = {
+        "mpk_options_default": (None, [ctypes.POINTER(Options)]),
+        "mpk_version": (ctypes.c_char_p, []),
+        "mpk_last_error": (ctypes.c_char_p, []),
+        "mpk_build_levels": (I32, [I32, P, P, P, ctypes.POINTER(Options), ctypes.POINTER(P), pSZ]),
+        "mpk_get_levels": (I32, [P, pI32, P, P, P, P]),
+        "mpk_get_partition": (I32, [P, pI32, pI32, pI32, P]),
+        "mpk_get_deps": (I32, [P, pI64, P, P]),
+        "mpk_min_workers": (I32, [P, I32, pI32]),
+        "mpk_upload": (I32, [P, P, SZ, P]),
+        "mpk_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
+        "mpk_apply": (I32, [P, D, D, I64, I32, U32, P, SZ, P]),
+        "poly_apply": (I32, [P, I32, I32, P, P, D, D, U32, P, SZ, P]),
+        "sstep_basis": (I32, [P, I32, P, P, D, D, I64, U32, P, SZ, P]),
+        "mpk_permute": (I32, [P, D, D, I32, P]),
+        "mpk_check_device": (I32, [P, P]),
+        "mpk_plan_info": (I32, [P, pI64, pI64, pI32, pI32, pI64, pI32, pI32, pI32]),
+        "mpk_destroy": (None, [P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def version():
+    return _lib.mpk_version().decode()
+
+
+def _check(code):
+    if code != 0:
+        raise MPKError(code, _lib.mpk_last_error().decode())
+
+
+def _ptr(a):
+    return a.ctypes.data_as(ctypes.c_void_p) if a is not None else None
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class Plan:
+    """A matrix prepared for the blocked MPK (levels, permutation, layout, schedule).
+
+    ``Plan(n, rowptr, col, val)`` runs the host planner (``mpk_build_levels``);
+    ``upload()`` places it in device memory owned by a torch tensor.
+    """
+
+    def __init__(self, n, rowptr, col, val, root=None, p_block=0, workers_per_xcd=0,
+                 watchdog_polls=0, chunks_per_worker=0):
+        self._h = None
+        self.n = int(n)
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        opt = Options()
+        _lib.mpk_options_default(ctypes.byref(opt))
+        if root is not None:
+            opt.root_mode, opt.root = 1, int(root)
+        opt.p_block = int(p_block)
+        opt.workers_per_xcd = int(workers_per_xcd)
+        opt.watchdog_polls = int(watchdog_polls)
+        opt.chunks_per_worker = int(chunks_per_worker)
+        h = ctypes.c_void_p()
+        nbytes = ctypes.c_size_t()
+        _check(_lib.mpk_build_levels(self.n, _ptr(rowptr), _ptr(col), _ptr(val), ctypes.byref(opt),
+                                     ctypes.byref(h), ctypes.byref(nbytes)))
+        self._h = h
+        self.device_bytes = nbytes.value
+        self.buffer = None
+
+    @classmethod
+    def from_csr(cls, A, **kw):
+        return cls(A[0], A[1], A[2], A[3], **kw)
+
+    def __del__(self):
+        if getattr(self, "_h", None):
+            _lib.mpk_destroy(self._h)
+            self._h = None
+
+    # ---------------------------------------------------------- host tables
+    def levels(self):
+        nl = ctypes.c_int32()
+        _check(_lib.mpk_get_levels(self._h, ctypes.byref(nl), None, None, None, None))
+        lp = np.empty(nl.value + 1, np.int32)
+        lv, perm, iperm = (np.empty(self.n, np.int32) for _ in range(3))
+        _check(_lib.mpk_get_levels(self._h, ctypes.byref(nl), _ptr(lp), _ptr(lv), _ptr(perm), _ptr(iperm)))
+        return {"nlevels": nl.value, "level_ptr": lp, "level_of_row": lv, "perm": perm, "iperm": iperm}
+
+    def partition(self):
+        nc, cr, npart = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.mpk_get_partition(self._h, ctypes.byref(nc), ctypes.byref(cr), ctypes.byref(npart), None))
+        owner = np.empty(nc.value, np.int32)
+        _check(_lib.mpk_get_partition(self._h, ctypes.byref(nc), ctypes.byref(cr), ctypes.byref(npart), _ptr(owner)))
+        return {"nchunks": nc.value, "chunk_rows": cr.value, "nparts": npart.value, "owner": owner}
+
+    def deps(self):
+        nd = ctypes.c_int64()
+        _check(_lib.mpk_get_deps(self._h, ctypes.byref(nd), None, None))
+        nc = self.partition()["nchunks"]
+        ptr = np.empty(nc + 1, np.int32)
+        idx = np.empty(max(1, nd.value), np.int32)
+        _check(_lib.mpk_get_deps(self._h, ctypes.byref(nd), _ptr(ptr), _ptr(idx)))
+        return ptr, idx[:nd.value]
+
+    def min_workers(self, q):
+        w = ctypes.c_int32()
+        _check(_lib.mpk_min_workers(self._h, int(q), ctypes.byref(w)))
+        return w.value
+
+    def info(self):
+        n, nnz, slots = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        nl, nc, reg, wk, pb = (ctypes.c_int32() for _ in range(5))
+        _check(_lib.mpk_plan_info(self._h, ctypes.byref(n), ctypes.byref(nnz), ctypes.byref(nl),
+                                  ctypes.byref(nc), ctypes.byref(slots), ctypes.byref(reg),
+                                  ctypes.byref(wk), ctypes.byref(pb)))
+        return {"n": n.value, "nnz": nnz.value, "nlevels": nl.value, "nchunks": nc.value,
+                "sell_slots": slots.value, "reg_slots": reg.value, "workers_per_xcd": wk.value,
+                "p_block": pb.value}
+
+    # --------------------------------------------------------------- device
+    def upload(self, device="cuda", stream=None):
+        import torch
+        self.buffer = torch.empty(max(256, self.device_bytes), dtype=torch.uint8, device=device)
+        _check(_lib.mpk_upload(self._h, _dptr(self.buffer), self.buffer.numel(), _stream(stream)))
+        return self
+
+    def work_bytes(self, call, p, flags):
+        b = ctypes.c_size_t()
+        _check(_lib.mpk_work_bytes(self._h, int(call), int(p), int(flags), ctypes.byref(b)))
+        return b.value
+
+    def _work(self, call, p, flags, device):
+        import torch
+        nb = self.work_bytes(call, p, flags)
+        if nb == 0:
+            return None, 0
+        w = torch.empty(nb // 8 + 1, dtype=torch.float64, device=device)
+        return w, nb
+
+    @staticmethod
+    def _flags(permuted, plain):
+        return (MPK_IO_PERMUTED if permuted else 0) | (MPK_PLAIN if plain else 0)
+
+    def apply(self, x, p, Y=None, permuted=True, plain=False, stream=None):
+        """Y[k-1] = A^k x for k = 1..p (a (p, n) float64 tensor)."""
+        import torch
+        if Y is None:
+            Y = torch.empty((p, self.n), dtype=torch.float64, device=x.device)
+        flags = self._flags(permuted, plain)
+        w, nb = self._work(CALL_APPLY, p, flags, x.device)
+        ldy = Y.stride(0) if Y.dim() == 2 else self.n
+        _check(_lib.mpk_apply(self._h, _dptr(x), _dptr(Y), ldy, int(p), flags, _dptr(w), nb,
+                              _stream(stream)))
+        return Y
+
+    def poly(self, kind, c, x, params=None, out=None, permuted=True, plain=False, stream=None):
+        """out = sum_k c[k] phi_k(A) x (kind: monomial, newton, chebyshev)."""
+        import torch
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        flags = self._flags(permuted, plain)
+        d = c.size - 1
+        w, nb = self._work(CALL_POLY, d, flags, x.device)
+        _check(_lib.poly_apply(self._h, POLY_KINDS[kind], d, _ptr(c), _ptr(pr), _dptr(x), _dptr(out),
+                               flags, _dptr(w), nb, _stream(stream)))
+        return out
+
+    def sstep(self, v, lambdas, sigmas=None, V=None, permuted=True, plain=False, stream=None):
+        """(s+1, n) Newton basis: V[0] = v, V[k] = (A - lambda_k I) V[k-1] / sigma_k."""
+        import torch
+        lam = np.ascontiguousarray(lambdas, dtype=np.float64)
+        sig = None if sigmas is None else np.ascontiguousarray(sigmas, dtype=np.float64)
+        s = lam.size
+        if V is None:
+            V = torch.empty((s + 1, self.n), dtype=torch.float64, device=v.device)
+        flags = self._flags(permuted, plain)
+        w, nb = self._work(CALL_SSTEP, s, flags, v.device)
+        _check(_lib.sstep_basis(self._h, s, _ptr(lam), _ptr(sig), _dptr(v), _dptr(V), V.stride(0),
+                                flags, _dptr(w), nb, _stream(stream)))
+        return V
+
+    def permute(self, x, direction=0, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        _check(_lib.mpk_permute(self._h, _dptr(x), _dptr(out), int(direction), _stream(stream)))
+        return out
+
+    def check(self, stream=None):
+        """Synchronises and raises MPKError if a blocked launch reported a failure."""
+        _check(_lib.mpk_check_device(self._h, _stream(stream)))

@@ -1,0 +1,185 @@
+"""Host-side checks of the C ABI (no GPU): the library loads and exports every
+declared entry point; the host planner's level sets, permutation, chunk
+partition, dependency lists and deadlock bound are bit-exact to the oracle;
+malformed input is rejected with the documented status codes."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+from paper_2309_02228_amd import mpk as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "mpk.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:mpk_status|void|const char\s*\*)\s*(\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 15
+    assert sorted(M.EXPORTS) == names
+    lib = ctypes.CDLL(M.LIB_PATH)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert "gfx950" in M.version()
+
+
+MATRICES = {
+    "lap1d": lambda: S.laplacian_1d(300),
+    "lap2d_64": lambda: S.laplacian_2d(64),
+    "lap2d_ragged": lambda: S.laplacian_2d(37, 29),
+    "lap3d": lambda: S.laplacian_3d(17, 13, 11),
+    "rand_nonsym": lambda: S.random_pattern(3000, 3, 1),
+    "rand_sparse_disconnected": lambda: S.random_pattern(2000, 0.8, 2),
+    "rand_sym": lambda: S.random_pattern(1500, 5, 3, symmetric=True),
+    "blocks": lambda: S.block_diagonal(S.laplacian_2d(9, 7), S.identity(70), S.laplacian_1d(130),
+                                       S.random_pattern(200, 2, 9)),
+    "knn": lambda: S.knn_graph_laplacian(3000, k=26, seed=1),
+    "identity": lambda: S.identity(200),
+    "shift": lambda: S.cyclic_shift(257),
+    "single": lambda: S.from_dense([[2.0]]),
+    "long_entry": lambda: S.from_dense(np.eye(130) + np.diag([0.0] * 129 + [0.0]) +
+                                       np.pad(np.array([[0.0] * 129 + [4.0]]), ((0, 129), (0, 0)))),
+}
+
+
+def oracle_plan(A, root=None, chunk_rows=64, parts=8):
+    level, nl, roots = O.bfs_levels(A, root)
+    perm, iperm, level_ptr = O.level_permutation(level, nl)
+    B = O.permute_symmetric(A, perm, iperm)
+    owner = O.chunk_owner(level_ptr, level[perm], A.n, chunk_rows, parts)
+    deps = O.chunk_dependencies(B, chunk_rows)
+    return dict(level=level, nl=nl, perm=perm, iperm=iperm, level_ptr=level_ptr, owner=owner, deps=deps)
+
+
+@pytest.mark.parametrize("name", sorted(MATRICES))
+def test_planner_bit_exact_to_oracle(name):
+    A = MATRICES[name]()
+    plan = M.Plan.from_csr(A, p_block=6)
+    got = plan.levels()
+    ref = oracle_plan(A)
+    assert got["nlevels"] == ref["nl"]
+    assert np.array_equal(got["level_of_row"], ref["level"])
+    assert np.array_equal(got["perm"], ref["perm"])
+    assert np.array_equal(got["iperm"], ref["iperm"])
+    assert np.array_equal(got["level_ptr"], ref["level_ptr"])
+    part = plan.partition()
+    assert part["chunk_rows"] == 64 and part["nparts"] == 8
+    assert np.array_equal(part["owner"], ref["owner"])
+    ptr, idx = plan.deps()
+    assert ptr.size == len(ref["deps"]) + 1
+    for c, d in enumerate(ref["deps"]):
+        assert np.array_equal(idx[ptr[c]:ptr[c + 1]], d), c
+    # the deadlock bound is the smallest worker count meeting the oracle's condition
+    G = 1 if plan.info()["reg_slots"] >= 32 else 2
+    for q in range(1, 7):
+        assert plan.min_workers(q) == O.min_workers(ref["owner"], ref["deps"], G, q), q
+
+
+@pytest.mark.parametrize("G", [1, 2, 4])
+def test_planner_unit_bound_by_group(G):
+    A = S.laplacian_3d(14, 12, 10)
+    plan = M.Plan.from_csr(A, p_block=5, chunks_per_worker=G)
+    ref = oracle_plan(A)
+    for q in range(1, 6):
+        assert plan.min_workers(q) == O.min_workers(ref["owner"], ref["deps"], G, q)
+
+
+def test_planner_explicit_root():
+    A = S.laplacian_2d(40, 33)
+    plan = M.Plan.from_csr(A, root=700)
+    got = plan.levels()
+    ref = oracle_plan(A, root=700)
+    assert np.array_equal(got["level_of_row"], ref["level"])
+    assert np.array_equal(got["perm"], ref["perm"])
+
+
+def test_planner_info_and_layout():
+    A = S.laplacian_3d(20)
+    plan = M.Plan.from_csr(A)
+    info = plan.info()
+    assert info["n"] == 8000 and info["nnz"] == A.col.size
+    assert info["nlevels"] == 58 and info["nchunks"] == 125
+    assert info["reg_slots"] == 8 and info["p_block"] == 4
+    # SELL-64 pads each chunk to its widest row: at most 64 * 7 slots per chunk
+    assert A.col.size <= info["sell_slots"] <= 125 * 64 * 7
+    assert plan.device_bytes > info["sell_slots"] * 12
+
+
+def test_work_bytes():
+    plan = M.Plan.from_csr(S.laplacian_2d(10))
+    assert plan.work_bytes(M.CALL_APPLY, 4, M.MPK_IO_PERMUTED) == 0
+    assert plan.work_bytes(M.CALL_APPLY, 4, 0) == 100 * 8 * 5
+    assert plan.work_bytes(M.CALL_POLY, 8, M.MPK_IO_PERMUTED) == 100 * 8 * 2
+    assert plan.work_bytes(M.CALL_SSTEP, 3, 0) == 100 * 8 * 4
+
+
+def _build(n, rowptr, col, val, **opt):
+    o = M.Options()
+    for k, v in opt.items():
+        setattr(o, k, v)
+    h = ctypes.c_void_p()
+    nb = ctypes.c_size_t()
+    rp = np.ascontiguousarray(rowptr, np.int32)
+    c = np.ascontiguousarray(col, np.int32)
+    v = np.ascontiguousarray(val, np.float64)
+    lib = M.lib()
+    code = lib.mpk_build_levels(n, rp.ctypes.data_as(ctypes.c_void_p), c.ctypes.data_as(ctypes.c_void_p),
+                                v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(o), ctypes.byref(h),
+                                ctypes.byref(nb))
+    if code == 0:
+        lib.mpk_destroy(h)
+    return code, lib.mpk_last_error().decode()
+
+
+def test_malformed_csr_rejected():
+    ok = _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0, 1.0, 1.0])
+    assert ok[0] == 0
+    assert _build(3, [0, 2, 1, 3], [0, 1, 2], [1.0] * 3)[0] == -2          # rowptr not monotone
+    assert _build(3, [1, 2, 3, 3], [0, 1, 2], [1.0] * 3)[0] == -2          # rowptr[0] != 0
+    assert _build(3, [0, 1, 2, 3], [0, 3, 2], [1.0] * 3)[0] == -2          # column out of range
+    assert _build(3, [0, 1, 2, 3], [0, -1, 2], [1.0] * 3)[0] == -2         # negative column
+    code, msg = _build(2, [0, 2, 3], [1, 0, 1], [1.0] * 3)                  # unsorted
+    assert code == -2 and "ascending" in msg
+    assert _build(2, [0, 2, 3], [1, 1, 1], [1.0] * 3)[0] == -2             # duplicate
+    assert _build(-1, [0], [], [])[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, p_block=16)[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, root_mode=1, root=3)[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, root_mode=2)[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, chunks_per_worker=3)[0] == -1
+    assert _build(0, [0], [], [])[0] == 0                                  # empty matrix
+
+
+def test_apply_argument_errors_without_gpu():
+    lib = M.lib()
+    plan = M.Plan.from_csr(S.laplacian_2d(8))
+    dummy = ctypes.c_void_p(0x1000)
+    assert lib.mpk_apply(plan._h, dummy, dummy, 64, 0, 1, None, 0, None) == -1   # p = 0
+    assert lib.mpk_apply(plan._h, dummy, dummy, 63, 2, 1, None, 0, None) == -1   # ldy < n
+    assert lib.mpk_apply(plan._h, dummy, dummy, 64, 2, 0, None, 0, None) == -1   # no work buffer
+    assert lib.mpk_apply(plan._h, dummy, dummy, 64, 2, 1, None, 0, None) == -6   # not uploaded
+    c = np.ones(3)
+    assert lib.poly_apply(plan._h, 7, 2, c.ctypes.data_as(ctypes.c_void_p), None, dummy,
+                          ctypes.c_void_p(0x2000), 1, dummy, 1 << 20, None) == -1  # unknown kind
+    assert lib.poly_apply(plan._h, 0, -1, c.ctypes.data_as(ctypes.c_void_p), None, dummy,
+                          ctypes.c_void_p(0x2000), 1, dummy, 1 << 20, None) == -1  # d < 0
+    prm = np.array([1.0, 0.0])
+    assert lib.poly_apply(plan._h, 2, 2, c.ctypes.data_as(ctypes.c_void_p),
+                          prm.ctypes.data_as(ctypes.c_void_p), dummy, ctypes.c_void_p(0x2000), 1,
+                          dummy, 1 << 20, None) == -1  # delta == 0
+    lam = np.zeros(2)
+    sig = np.array([1.0, 0.0])
+    assert lib.sstep_basis(plan._h, 2, lam.ctypes.data_as(ctypes.c_void_p),
+                           sig.ctypes.data_as(ctypes.c_void_p), dummy, dummy, 64, 1, None, 0,
+                           None) == -1  # zero sigma
+    assert lib.sstep_basis(plan._h, 0, lam.ctypes.data_as(ctypes.c_void_p), None, dummy, dummy,
+                           64, 1, None, 0, None) == -1  # s = 0
+    assert lib.mpk_check_device(plan._h, None) == -6

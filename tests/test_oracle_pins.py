@@ -355,7 +355,7 @@ def test_chunk_owner_and_deps_on_grid():
     B, perm, owner, deps, clev = _schedule(A, 8, 4)
     assert owner.min() >= 0 and owner.max() <= 3
     # one hop from every chunk reaches the level before it
-    b1 = O.hop_min(deps, 1)
+    b1 = O.hop_min(deps, np.arange(len(deps)), 1)
     assert np.all(b1[1:] < np.arange(1, len(deps)))
     # brute force: chunk c waits on c' iff some row of c touches a row of c'
     Bd = dense(B) != 0
@@ -384,31 +384,34 @@ def test_chunk_owner_fraction_rule():
     assert list(own) == [0, 0] + [(8 * i) // 15 for i in range(15)]
 
 
-def _min_workers(owner, deps, parts, q):
-    bmin = O.hop_min(deps, q - 1)
-    seqs = [np.nonzero(owner == part)[0] for part in range(parts)]
-    for w in range(1, len(owner) + 1):
-        if all(O.window_ok(sq, w, bmin) for sq in seqs):
-            return w
-    return len(owner)
-
-
+@pytest.mark.parametrize("group", [1, 2, 4])
 @pytest.mark.parametrize("mk,cr,parts,q,p", [
     (lambda: S.laplacian_2d(16, 16), 8, 4, 3, 7),
     (lambda: S.laplacian_3d(6, 6, 6), 16, 8, 4, 4),
     (lambda: S.random_pattern(200, 3, 5), 8, 2, 2, 5),
     (lambda: S.block_diagonal(S.laplacian_2d(9, 7), S.identity(5), S.laplacian_1d(30)), 4, 8, 4, 9),
 ])
-def test_blocked_schedule_equals_plain_mpk(mk, cr, parts, q, p):
+def test_blocked_schedule_equals_plain_mpk(mk, cr, parts, q, p, group):
     # with the fewest workers that meet the window condition, the blocked order
     # completes and gives bitwise the plain powers of the permuted matrix
     A = mk()
     B, perm, owner, deps, clev = _schedule(A, cr, parts)
     x = S.uniform_vector(A.n, 3)
-    w = _min_workers(owner, deps, parts, q)
-    Y = O.simulate_blocked_mpk(B, x[perm], p, q, cr, owner, deps, w)
+    w = O.min_workers(owner, deps, group, q)
+    Y = O.simulate_blocked_mpk(B, x[perm], p, q, cr, owner, deps, w, group=group)
     assert not np.isnan(Y).any()
     assert np.array_equal(Y, O.mpk(B, x[perm], p))
+
+
+def test_units_reduce_to_chunks_for_group_one():
+    A = S.laplacian_2d(14, 11)
+    B, perm, owner, deps, clev = _schedule(A, 4, 3)
+    units, upart = O.worker_units(owner, 1)
+    assert [int(u[0]) for u in units] == [int(c) for x in range(3) for c in np.nonzero(owner == x)[0]]
+    udeps = O.unit_dependencies(units, deps, len(deps))
+    unit_of = {int(u[0]): i for i, u in enumerate(units)}
+    for c in range(len(deps)):
+        assert sorted(int(units[v][0]) for v in udeps[unit_of[c]]) == list(deps[c])
 
 
 def test_blocked_schedule_deadlocks_when_window_too_small():
@@ -416,14 +419,21 @@ def test_blocked_schedule_deadlocks_when_window_too_small():
     # chunk 1, which that same worker only starts after finishing chunk 0
     A = S.laplacian_1d(12)
     B, perm, owner, deps, clev = _schedule(A, 1, 1)
-    bmin = O.hop_min(deps, 2)
+    first = np.arange(12)
+    bmin = O.hop_min(deps, first, 2)
     assert list(bmin) == [max(0, c - 2) for c in range(12)]
-    seq = np.arange(12)
-    assert not O.window_ok(seq, 1, bmin)
+    assert not O.window_ok(first, 1, bmin)
     with pytest.raises(RuntimeError):
         O.simulate_blocked_mpk(B, np.ones(12), 3, 3, 1, owner, deps, 1)
-    assert not O.window_ok(seq, 2, bmin) and O.window_ok(seq, 3, bmin)
+    assert not O.window_ok(first, 2, bmin) and O.window_ok(first, 3, bmin)
+    assert O.min_workers(owner, deps, 1, 3) == 3
     Y = O.simulate_blocked_mpk(B, np.ones(12), 3, 3, 1, owner, deps, 3)
+    assert np.array_equal(Y, O.mpk(B, np.ones(12), 3))
+    # units of two chunks: unit j waits on units j-1, j+1; two hops reach unit j-2
+    assert O.min_workers(owner, deps, 2, 3) == 3
+    with pytest.raises(RuntimeError):
+        O.simulate_blocked_mpk(B, np.ones(12), 3, 3, 1, owner, deps, 2, group=2)
+    Y = O.simulate_blocked_mpk(B, np.ones(12), 3, 3, 1, owner, deps, 3, group=2)
     assert np.array_equal(Y, O.mpk(B, np.ones(12), 3))
 
 
@@ -433,8 +443,9 @@ def test_window_condition_is_sufficient(seed):
     A = S.laplacian_2d(int(rng.integers(8, 20)), int(rng.integers(8, 20)))
     B, perm, owner, deps, clev = _schedule(A, 4, 2)
     q = int(rng.integers(2, 5))
-    w = _min_workers(owner, deps, 2, q)
-    Y = O.simulate_blocked_mpk(B, np.ones(A.n), q, q, 4, owner, deps, w)
+    g = int(rng.choice([1, 2, 4]))
+    w = O.min_workers(owner, deps, g, q)
+    Y = O.simulate_blocked_mpk(B, np.ones(A.n), q, q, 4, owner, deps, w, group=g)
     assert np.array_equal(Y, O.mpk(B, np.ones(A.n), q))
 
 
@@ -444,7 +455,7 @@ def test_blocked_schedule_operator_kinds():
     x = S.uniform_vector(A.n, 9)[perm]
     lam = [0.5, 1.0, 1.5, 2.0, 2.5]
     newton = lambda k, acc, prev, prev2: acc - lam[k - 1] * prev
-    Y = O.simulate_blocked_mpk(B, x, 5, 3, 8, owner, deps, 4, kind=newton)
+    Y = O.simulate_blocked_mpk(B, x, 5, 3, 8, owner, deps, 4, kind=newton, group=2)
     assert np.array_equal(Y, O.newton_basis(B, x, lam)[1:])
     th, de = 4.0, 4.0
     cheb = lambda k, acc, prev, prev2: ((acc - th * prev) / de if k == 1
