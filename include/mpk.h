@@ -154,11 +154,14 @@ mpk_status mpk_get_partition(mpk_plan_t plan, int32_t* nchunks, int32_t* chunk_r
 mpk_status mpk_get_deps(mpk_plan_t plan, int64_t* ndeps, int32_t* dep_ptr, int32_t* dep_idx);
 
 /*
- * Smallest number of workers (waves) per XCD partition for which the blocked
- * kernel cannot deadlock with blocks of q powers: for every partition and
- * every position i >= W in its chunk sequence, the chunk at position i - W
- * has a smaller index than every chunk within q-1 dependency hops of the
- * chunk at position i.  1 <= q <= p_block.
+ * Smallest number of resident workers (waves) per XCD partition for which the
+ * blocked kernel cannot deadlock with blocks of q powers.  Units of
+ * chunks_per_worker consecutive chunks of a partition's sequence are handed
+ * out in sequence order; the bound W is the smallest value such that, for
+ * every partition and unit position j >= W, the first chunk of unit j - W has
+ * a smaller index than the first chunk of every unit within q-1 dependency
+ * hops of unit j.  mpk_upload picks the largest q <= p_block whose bound is at
+ * most half of the waves it launches.  1 <= q <= p_block.
  */
 mpk_status mpk_min_workers(mpk_plan_t plan, int32_t q, int32_t* workers_per_xcd);
 

@@ -50,12 +50,13 @@ READINGS = {
           "level of r0; each partition processes its chunks in ascending order.",
     "R7": "Chunk c may compute power k once every chunk holding a row adjacent to c's "
           "rows in the symmetrised pattern has finished power k-1. Each partition's "
-          "ascending chunk sequence is cut into units of G consecutive chunks; the "
-          "partition runs W_x workers, worker i takes units i, i+W_x, ... and carries "
-          "all chunks of a unit together through the q powers of a block before taking "
-          "the next. This order cannot deadlock when, for every partition and every "
-          "unit position j >= W_x, the first chunk of unit j - W_x has a smaller index "
-          "than the first chunk of every unit within q-1 unit-dependency hops of unit j.",
+          "ascending chunk sequence is cut into units of G consecutive chunks; a worker "
+          "takes the partition's next unit in sequence order, carries all its chunks "
+          "together through the q powers of a block, then takes the next. With at "
+          "least W_x >= W "
+          "active workers per partition this cannot deadlock when, for every unit "
+          "position j >= W, the first chunk of unit j - W has a smaller index than the "
+          "first chunk of every unit within q-1 unit-dependency hops of unit j.",
     "R8": "Newton basis: V_k = (A - lambda_k I) V_{k-1} / sigma_k, the product of distinct "
           "shifted factors (the printed powers (A - lambda_2 I)^2 ... are read as this "
           "product).",
@@ -414,11 +415,15 @@ def window_ok(first, workers, bmin):
     first-chunk indices of the partition's units in order, ``bmin`` their values of
     ``hop_min(..., q - 1)``.
 
-    Proof sketch: in a deadlock take the waiting unit whose first chunk c is
-    smallest.  Each unit on its chain of waits lies within q-1 hops (powers drop
-    by one per hop and power 1 never waits).  A worker that has not reached such a
-    unit u is at least W_x units behind it, hence on a unit whose first chunk is
-    below bmin[u] <= c, and is itself waiting: a contradiction with the choice of c.
+    Proof sketch: in a deadlock every started unit waits; take the one whose
+    first chunk c is smallest.  Its chain of waits has at most q-1 hops (powers
+    drop by one per hop and power 1 never waits) and ends at a unit u that has
+    not started.  If nobody holds u, units start in order, so the W busy
+    workers of u's partition hold units at positions below u's, one of them at
+    pos(u) - W or earlier, whose first chunk is below bmin[u] <= c.  If a worker
+    claimed u early, it did so while on a unit at position <= pos(u) - W, whose
+    first chunk is again below bmin[u] <= c.  Either way a waiting unit with a
+    smaller first chunk exists: a contradiction.
     """
     first = np.asarray(first, dtype=np.int64)
     if first.size <= workers:
@@ -439,19 +444,27 @@ def min_workers(owner, deps, group, q):
     return max(1, len(units))
 
 
-def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None, group=1):
+def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None, group=1,
+                         active=None, early=None):
     """Execute the blocked MPK on permuted matrix B sequentially, in the worker
     order of reading R7, and return Y (p, n) in permuted space.
 
-    ``workers`` is the number of workers per partition.  A worker repeatedly
-    tries to advance its current (unit, power): power k of all chunks of the unit
-    is computed only when every chunk they wait on, outside the unit, has
-    finished power k-1.  Values not yet computed are NaN, so a wrong order
-    shows up as NaN in the result; a full sweep without progress raises
-    (deadlock).  Powers are done in blocks of q (R10).  ``kind`` is None for
-    plain powers, or a callable (k, acc, prev, prev2) -> y_k for the shifted
-    and three-term forms, where acc = (A y_{k-1}) on the chunk's rows and
-    prev/prev2 are y_{k-1}/y_{k-2} on the same rows.
+    Each partition hands out its units in sequence order to ``workers`` workers
+    (``active`` of them actually run, default all).  A worker repeatedly tries to
+    advance its current (unit, power): power k of all chunks of the unit is
+    computed only when every chunk they wait on, outside the unit, has finished
+    power k-1; an idle worker takes the partition's next unit.  ``early`` = W
+    models a variant that the GPU kernel does not use: a worker about to compute
+    the last power of the unit at position j first claims its next unit if the
+    partition's next position is >= j + W (safe by the same condition, but a
+    unit claimed this way cannot start until its holder finishes, which delays
+    everything that waits on it).
+    Values not yet computed are NaN, so a wrong order shows up as NaN in the
+    result; a full sweep without progress raises (deadlock).  Powers are done
+    in blocks of q (R10).  ``kind`` is None for plain powers, or a callable
+    (k, acc, prev, prev2) -> y_k for the shifted and three-term forms, where
+    acc = (A y_{k-1}) on the chunk's rows and prev/prev2 are y_{k-1}/y_{k-2} on
+    the same rows.
     """
     n = int(B[0])
     nchunks = len(deps)
@@ -461,19 +474,37 @@ def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None
     nparts = int(upart.max()) + 1 if upart.size else 0
     pu = [np.nonzero(upart == part)[0] for part in range(nparts)]
     inside = [set(u.tolist()) for u in units]
+    nact = workers if active is None else active
     base = 0
     while base < p:
         qb = min(q, p - base)
         done = np.zeros(nchunks, dtype=np.int64)  # powers finished in this block
-        state = [[part, w, 1] for part in range(nparts) for w in range(workers)]
+        ticket = [0] * nparts
+        # worker: [partition, position of current unit or -1, power, claimed next position or -1]
+        state = [[part, -1, 0, -1] for part in range(nparts) for _ in range(nact)]
         remaining = len(units) * qb
         while remaining:
             progress = False
             for st in state:
-                part, pos, k = st
-                if pos >= pu[part].size:
-                    continue
+                part, pos, k, nxt = st
+                if pos < 0:
+                    if nxt >= 0:
+                        pos, nxt = nxt, -1
+                    elif ticket[part] < pu[part].size:
+                        pos = ticket[part]
+                        ticket[part] += 1
+                    else:
+                        continue
+                    k = 1
+                    st[1], st[2], st[3] = pos, k, nxt
+                    progress = True
                 u = int(pu[part][pos])
+                if (early is not None and k == qb and nxt < 0 and ticket[part] < pu[part].size
+                        and ticket[part] >= pos + early):
+                    nxt = ticket[part]
+                    ticket[part] += 1
+                    st[3] = nxt
+                    progress = True
                 if k > 1 and any(done[d] < k - 1 for c in units[u] for d in deps[c]
                                  if int(d) not in inside[u]):
                     continue
@@ -490,7 +521,7 @@ def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None
                 remaining -= 1
                 progress = True
                 if k == qb:
-                    st[1], st[2] = pos + workers, 1
+                    st[1], st[2] = -1, 0
                 else:
                     st[2] = k + 1
             if not progress:

@@ -59,7 +59,8 @@ struct DevPlan {
     const int32_t* dep_ptr;
     const int32_t* dep_idx;
     uint32_t* done;
-    int32_t* status;  // [0] code, [1] chunk, [2] power
+    uint32_t* tickets;  // [4 launch slots][kParts], one per 128-byte line
+    int32_t* status;    // [0] code, [1] chunk, [2] power
     int32_t n;
 };
 
@@ -192,16 +193,20 @@ __device__ bool give_up(const BlockArgs& a, int c, int kl) {
 }
 
 // Polls completion words until each lane's word has reached `target`.
-// Returns false if the watchdog fired or another wave already gave up.
+// `wo` are byte offsets into the completion-word array `done` (buffer
+// resource `dr`), read with device-coherent loads.  Returns false if the
+// watchdog fired or another wave already gave up.
 template <int G>
-__device__ bool poll_until(const BlockArgs& a, const uint32_t* const (&w)[G], bool (&ok)[G],
-                           uint32_t target, int c_report, int kl) {
+__device__ bool poll_until(const BlockArgs& a, __amdgpu_buffer_rsrc_t dr, const uint32_t (&wo)[G],
+                           bool (&ok)[G], uint32_t target, int c_report, int kl) {
     for (int spin = 0;; ++spin) {
         bool all = true;
         if (a.spin_limit >= 0) {
 #pragma unroll
             for (int g = 0; g < G; ++g)
-                if (!ok[g]) ok[g] = (int32_t)(load_word(w[g]) - target) >= 0;
+                if (!ok[g])
+                    ok[g] = (int32_t)((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(dr, (int)wo[g], 0, 16) -
+                                      target) >= 0;
         }
 #pragma unroll
         for (int g = 0; g < G; ++g) all = all && ok[g];
@@ -221,10 +226,22 @@ template <int REG, int G, int KIND, bool POLY>
 __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
     const int lane = threadIdx.x & 63;
     const int part = blockIdx.x % kParts;
-    const int worker = (blockIdx.x / kParts) * kWaves + (threadIdx.x >> 6);
     const int s0 = a.P.seq_ptr[part], s1 = a.P.seq_ptr[part + 1];
     const int nunits = (s1 - s0 + G - 1) / G;
-    for (int u = worker; u < nunits; u += a.workers) {
+    const int nchunks = (a.P.n + kChunkRows - 1) / kChunkRows;
+    const __amdgpu_buffer_rsrc_t dr =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.P.done, 0, nchunks * 4 * kFlagStride, 0x00020000);
+    // Units are handed out in sequence order from a per-partition counter, so
+    // only waves that are actually resident take work.  This launch uses slot
+    // epoch % 4 and clears the slot of the launch after next.
+    uint32_t* tick = a.P.tickets + ((a.epoch & 3u) * kParts + part) * kFlagStride;
+    if (blockIdx.x < kParts && threadIdx.x == 0)
+        a.P.tickets[(((a.epoch + 2u) & 3u) * kParts + blockIdx.x) * kFlagStride] = 0u;
+    for (;;) {
+        uint32_t t = 0;
+        if (lane == 0) t = atomicAdd(tick, 1u);
+        const int u = (int)__builtin_amdgcn_readfirstlane(t);
+        if (u >= nunits) break;
         int c[G], width[G], d0[G], d1[G], row[G];
         int64_t off[G];
 #pragma unroll
@@ -246,14 +263,14 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
             }
         }
         // first batch of each dependency list: one lane per dependency
-        const uint32_t* w[G];
+        uint32_t wo[G];
         bool need[G];
         bool long_list = false;
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const int i = d0[g] + lane;
             need[g] = i < d1[g];
-            w[g] = a.P.done + kFlagStride * (need[g] ? a.P.dep_idx[i] : 0);
+            wo[g] = (uint32_t)(need[g] ? a.P.dep_idx[i] : 0) * (4u * kFlagStride);
             long_list = long_list || (d1[g] - d0[g] > 64);
         }
         double rv[G][REG];
@@ -290,15 +307,16 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                 bool ok[G];
 #pragma unroll
                 for (int g = 0; g < G; ++g) ok[g] = !need[g];
-                if (!poll_until<G>(a, w, ok, target, c[0], kl)) return;
+                if (!poll_until<G>(a, dr, wo, ok, target, c[0], kl)) return;
                 if (long_list) {  // dependency lists longer than one wave
 #pragma unroll
                     for (int g = 0; g < G; ++g)
                         for (int b = d0[g] + 64; b < d1[g]; b += 64) {
                             const int i = b + lane;
-                            const uint32_t* wx[1] = {a.P.done + kFlagStride * (i < d1[g] ? a.P.dep_idx[i] : 0)};
+                            const uint32_t wx[1] = {(uint32_t)(i < d1[g] ? a.P.dep_idx[i] : 0) *
+                                                    (4u * kFlagStride)};
                             bool okx[1] = {!(i < d1[g])};
-                            if (!poll_until<1>(a, wx, okx, target, c[g], kl)) return;
+                            if (!poll_until<1>(a, dr, wx, okx, target, c[g], kl)) return;
                         }
                 }
                 asm volatile("" ::: "memory");
@@ -399,7 +417,7 @@ mpk_status fail(mpk_status s, const char* fmt, ...) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t val, col, off, perm, iperm, seq, seq_ptr, dep_ptr, dep_idx, done, status, total;
+    size_t val, col, off, perm, iperm, seq, seq_ptr, dep_ptr, dep_idx, done, tickets, status, total;
 };
 
 Layout make_layout(const mpk::HostPlan& H) {
@@ -421,6 +439,7 @@ Layout make_layout(const mpk::HostPlan& H) {
     L.dep_ptr = take((H.nchunks + 1) * 4);
     L.dep_idx = take(std::max<size_t>(1, H.dep_idx.size()) * 4);
     L.done = take(std::max<size_t>(1, H.nchunks) * 4 * kFlagStride);
+    L.tickets = take(4 * kParts * 4 * kFlagStride);
     L.status = take(16);
     L.total = o;
     return L;
@@ -434,10 +453,12 @@ struct mpk_plan_s {
     char* dev = nullptr;  // caller-owned device buffer once uploaded
     DevPlan D{};
     uint32_t epoch = 0;
-    int workers = 0;       // waves per partition of the blocked kernel
-    int grid_block = 0;    // workgroups of the blocked launch
-    int grid_spmv = 0;     // workgroups of a plain launch
-    int q_eff = 1;         // powers per blocked launch actually used
+    // blocked launch shape per operator variant [kind][poly]: every workgroup
+    // must be resident at once, so the grid is the variant's occupancy limit
+    int workers[3][2] = {};  // waves per partition
+    int grid_block[3][2] = {};
+    int q_eff[3][2] = {};    // powers per launch meeting the deadlock bound
+    int grid_spmv = 0;       // workgroups of a plain launch
 };
 
 namespace {
@@ -448,6 +469,8 @@ using SpmvFn = void (*)(SpmvArgs);
 template <int G, int KIND, bool POLY>
 BlockFn block_fn(int reg) {
     switch (reg) {
+        case 4: return mpk_block_kernel<4, G, KIND, POLY>;
+        case 7: return mpk_block_kernel<7, G, KIND, POLY>;
         case 8: return mpk_block_kernel<8, G, KIND, POLY>;
         case 16: return mpk_block_kernel<16, G, KIND, POLY>;
         case 32: return mpk_block_kernel<32, G, KIND, POLY>;
@@ -489,13 +512,15 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
         const int64_t nc = (int64_t)std::max<int32_t>(1, p->H.nchunks) * kFlagStride;
         fill_u32_kernel<<<grid_1d(nc), 256, 0, st>>>(p->D.done, nc, 0u);
         HIP_TRY(hipGetLastError());
+        fill_u32_kernel<<<8, 256, 0, st>>>(p->D.tickets, 4 * kParts * kFlagStride, 0u);
+        HIP_TRY(hipGetLastError());
         p->epoch = 0;
     }
     a.P = p->D;
     a.epoch = ++p->epoch;
-    a.workers = p->workers;
+    a.workers = p->workers[kind][poly];
     a.spin_limit = p->H.watchdog == 0 ? kSpinLimit : p->H.watchdog;
-    hipLaunchKernelGGL(pick_block(p->H.reg_slots, p->H.group, kind, poly), dim3(p->grid_block),
+    hipLaunchKernelGGL(pick_block(p->H.reg_slots, p->H.group, kind, poly), dim3(p->grid_block[kind][poly]),
                        dim3(kBlockThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
     return MPK_OK;
@@ -562,8 +587,9 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
         }
         return MPK_OK;
     }
-    for (int base = 0; base < j.p; base += p->q_eff) {
-        const int q = std::min(p->q_eff, j.p - base);
+    const int qe = p->q_eff[j.kind][j.poly];
+    for (int base = 0; base < j.p; base += qe) {
+        const int q = std::min(qe, j.p - base);
         BlockArgs a{};
         a.in = job_vec(j, base);
         a.prev2 = (j.kind == KIND_CHEB && base >= 1) ? job_vec(j, base - 1) : nullptr;
@@ -690,8 +716,9 @@ MPK_API mpk_status mpk_plan_info(mpk_plan_t p, int64_t* n, int64_t* nnz, int32_t
     if (nchunks) *nchunks = p->H.nchunks;
     if (sell_slots) *sell_slots = (int64_t)p->H.sell_val.size();
     if (reg_slots) *reg_slots = p->H.reg_slots;
-    if (workers_per_xcd) *workers_per_xcd = p->workers;
-    if (p_block) *p_block = p->dev ? p->q_eff : p->H.p_block;
+    // reported for the plain matrix powers (mpk_apply's blocked kernel)
+    if (workers_per_xcd) *workers_per_xcd = p->workers[KIND_MONO][0];
+    if (p_block) *p_block = p->dev ? p->q_eff[KIND_MONO][0] : p->H.p_block;
     return MPK_OK;
 }
 
@@ -723,6 +750,8 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     HIP_TRY(hipGetLastError());
     fill_u32_kernel<<<1, 64, 0, st>>>((uint32_t*)(d + L.status), 4, 0u);
     HIP_TRY(hipGetLastError());
+    fill_u32_kernel<<<8, 256, 0, st>>>((uint32_t*)(d + L.tickets), 4 * kParts * kFlagStride, 0u);
+    HIP_TRY(hipGetLastError());
     // the host vectors must outlive the asynchronous copies
     HIP_TRY(hipStreamSynchronize(st));
 
@@ -735,6 +764,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     D.dep_ptr = (const int32_t*)(d + L.dep_ptr);
     D.dep_idx = (const int32_t*)(d + L.dep_idx);
     D.done = (uint32_t*)(d + L.done);
+    D.tickets = (uint32_t*)(d + L.tickets);
     D.status = (int32_t*)(d + L.status);
     D.n = H.n;
     p->D = D;
@@ -746,24 +776,32 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     int dev_id = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev_id));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
-    int occ = 0;
-    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, (const void*)pick_block(H.reg_slots, H.group, KIND_CHEB, true), kBlockThreads, 0));
     int maxlen = 0;
     for (int x = 0; x < kParts; ++x) maxlen = std::max(maxlen, H.seq_ptr[x + 1] - H.seq_ptr[x]);
     const int maxunits = (maxlen + H.group - 1) / H.group;
-    int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
-    wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
-    if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));
-    p->grid_block = wg_per_part * kParts;
-    p->workers = wg_per_part * kWaves;
-    p->q_eff = 1;
-    for (int q = H.p_block; q >= 1; --q)
-        if (H.min_workers[q] <= p->workers) {
-            p->q_eff = q;
-            break;
+    for (int kind = 0; kind < 3; ++kind)
+        for (int poly = 0; poly < 2; ++poly) {
+            int occ = 0;
+            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &occ, (const void*)pick_block(H.reg_slots, H.group, kind, poly), kBlockThreads, 0));
+            int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
+            wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
+            if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));
+            p->grid_block[kind][poly] = wg_per_part * kParts;
+            p->workers[kind][poly] = wg_per_part * kWaves;
+            // units come from in-order tickets, so the deadlock bound counts resident
+            // waves only; keep it within half of the launched waves as a margin
+            // against workgroups that the GPU does not make resident
+            p->q_eff[kind][poly] = 1;
+            for (int q = H.p_block; q >= 1; --q)
+                if (2 * H.min_workers[q] <= p->workers[kind][poly]) {
+                    p->q_eff[kind][poly] = q;
+                    break;
+                }
         }
-    p->grid_spmv = std::max(1, std::min(cus * 8, (H.nchunks + kWaves - 1) / kWaves));
+    // plain launches: up to 32 workgroups per CU (128 waves), a few chunks per
+    // wave; this measured faster than 8 per CU at the 160^3 Laplacian
+    p->grid_spmv = std::max(1, std::min(cus * 32, (H.nchunks + kWaves - 1) / kWaves));
     return MPK_OK;
 }
 

@@ -220,7 +220,8 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
         }
     }
     // register slots: the smallest supported width covering every chunk, capped
-    P.reg_slots = P.max_width <= 8 ? 8 : P.max_width <= 16 ? 16 : P.max_width <= 32 ? 32 : 48;
+    P.reg_slots = P.max_width <= 4 ? 4 : P.max_width <= 7 ? 7 : P.max_width <= 8 ? 8
+                : P.max_width <= 16 ? 16 : P.max_width <= 32 ? 32 : 48;
     // wide rows leave registers for one chunk per worker only
     if (P.reg_slots >= 32) P.group = 1;
 

@@ -46,6 +46,12 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
                           "or python paper_2309_02228_amd/build.py")
+    # PyTorch's HIP libraries ask for "libamdhip64.so" while the runtime's
+    # soname is "libamdhip64.so.7".  Loading libmpk.so first would map the
+    # system runtime under that soname and make torch map a second HIP and HSA
+    # runtime; only one of the two then sees the GPU.  Importing torch first
+    # lets libmpk.so bind to torch's runtime: one runtime per process.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I32, I64, SZ, U32, D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64,
                                ctypes.c_size_t, ctypes.c_uint32, ctypes.c_void_p)

@@ -108,7 +108,7 @@ def test_planner_info_and_layout():
     info = plan.info()
     assert info["n"] == 8000 and info["nnz"] == A.col.size
     assert info["nlevels"] == 58 and info["nchunks"] == 125
-    assert info["reg_slots"] == 8 and info["p_block"] == 4
+    assert info["reg_slots"] == 7 and info["p_block"] == 4  # widest row: 7 entries
     # SELL-64 pads each chunk to its widest row: at most 64 * 7 slots per chunk
     assert A.col.size <= info["sell_slots"] <= 125 * 64 * 7
     assert plan.device_bytes > info["sell_slots"] * 12
@@ -183,3 +183,15 @@ def test_apply_argument_errors_without_gpu():
     assert lib.sstep_basis(plan._h, 0, lam.ctypes.data_as(ctypes.c_void_p), None, dummy, dummy,
                            64, 1, None, 0, None) == -1  # s = 0
     assert lib.mpk_check_device(plan._h, None) == -6
+
+
+def test_one_hip_runtime_per_process():
+    """Importing the package before torch must not map a second HIP or HSA runtime."""
+    import subprocess
+    import sys
+    code = ("import paper_2309_02228_amd, torch\n"
+            "maps = {l.split()[-1] for l in open('/proc/self/maps')}\n"
+            "print(sum('libamdhip64' in m for m in maps), sum('libhsa-runtime64' in m for m in maps))\n")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
+                         timeout=300, check=True).stdout.split()
+    assert out == ["1", "1"], out

@@ -437,6 +437,50 @@ def test_blocked_schedule_deadlocks_when_window_too_small():
     assert np.array_equal(Y, O.mpk(B, np.ones(12), 3))
 
 
+@pytest.mark.parametrize("seed", range(6))
+def test_window_condition_holds_with_fewer_active_workers(seed):
+    # units are handed out in order, so workers that never run cannot stall the
+    # others: launching many but running only the bound's number still completes
+    rng = np.random.default_rng(100 + seed)
+    A = S.random_pattern(int(rng.integers(300, 700)), 2.5, seed) if seed % 2 else \
+        S.laplacian_3d(7, 6, int(rng.integers(4, 8)))
+    B, perm, owner, deps, clev = _schedule(A, 4, 3)
+    q = int(rng.integers(2, 5))
+    g = int(rng.choice([1, 2]))
+    w = O.min_workers(owner, deps, g, q)
+    Y = O.simulate_blocked_mpk(B, np.ones(A.n), 2 * q, q, 4, owner, deps, 3 * w, group=g, active=w)
+    assert np.array_equal(Y, O.mpk(B, np.ones(A.n), 2 * q))
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_early_claim_keeps_the_window_condition_sufficient(seed):
+    # claiming the next unit during the last power, only once the partition's
+    # next position is at least W beyond the current one, never deadlocks
+    rng = np.random.default_rng(200 + seed)
+    A = S.random_pattern(int(rng.integers(300, 800)), 2.5, seed) if seed % 2 else \
+        S.laplacian_2d(int(rng.integers(12, 24)), int(rng.integers(12, 24)))
+    B, perm, owner, deps, clev = _schedule(A, 4, 2)
+    q = int(rng.integers(2, 5))
+    g = int(rng.choice([1, 2]))
+    w = O.min_workers(owner, deps, g, q)
+    for active in (w, 2 * w):
+        Y = O.simulate_blocked_mpk(B, np.ones(A.n), 2 * q + 1, q, 4, owner, deps, active, group=g,
+                                   early=w)
+        assert np.array_equal(Y, O.mpk(B, np.ones(A.n), 2 * q + 1))
+
+
+def test_unrestricted_early_claim_can_deadlock():
+    # without the distance rule, a worker may claim a unit that its own current
+    # unit still waits on: a 1D chain, one worker, units of one chunk
+    A = S.laplacian_1d(10)
+    B, perm, owner, deps, clev = _schedule(A, 1, 1)
+    with pytest.raises(RuntimeError):
+        O.simulate_blocked_mpk(B, np.ones(10), 2, 2, 1, owner, deps, 1, early=0)
+    w = O.min_workers(owner, deps, 1, 2)
+    Y = O.simulate_blocked_mpk(B, np.ones(10), 2, 2, 1, owner, deps, w, early=w)
+    assert np.array_equal(Y, O.mpk(B, np.ones(10), 2))
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_window_condition_is_sufficient(seed):
     rng = np.random.default_rng(seed)
