@@ -11,16 +11,21 @@ Everything is written from the paper's statement of the method
 sparse iterative solvers on multi-core CPUs"):
 
 * ``spmv``, ``mpk``                 -- Sec. 3, Alg. 1 and Alg. 2
+* ``round_values``                  -- reduced-precision storage of the matrix
+  values (reading R11; the paper itself works in FP64)
 * ``newton_basis``                  -- Sec. 4 (Newton basis of the s-step method)
 * ``poly_monomial``/``poly_newton``  -- Sec. 5.2, Eq. (3)
 * ``poly_chebyshev``                -- Sec. 5.3 (Chebyshev smoother; the
   three-term recurrence itself is not printed in the paper)
 * ``pattern_graph``, ``bfs_levels``,
-  ``level_permutation``             -- Sec. 3 (BFS level structure of the
+  ``level_permutation``,
+  ``permute_symmetric``             -- Sec. 3 (BFS level structure of the
   matrix graph) and Sec. 5.1.2 (levels come from A alone)
-* ``group_levels``, ``wavefront_schedule``, ``validate_schedule``,
-  ``blocked_mpk``                   -- Sec. 3 (execution order from the level
-  structure and the cache size; p_opt and the remainder loop)
+* ``chunk_owner``, ``chunk_dependencies``, ``worker_units``,
+  ``unit_dependencies``, ``hop_min``, ``window_ok``, ``min_workers``,
+  ``simulate_blocked_mpk``          -- Sec. 3 (an execution order derived
+  from the level structure; p_opt and the remainder loop), in the readings
+  R5-R7 and R10
 
 Parity status of each function is stated in its docstring.  The readings
 taken where the paper is silent are listed in ``mpk_oracle.READINGS``.

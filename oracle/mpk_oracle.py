@@ -9,7 +9,7 @@ and unique within a row), vectors are float64 NumPy arrays.
 
 Parity status
 -------------
-pinned   spmv, mpk, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
+pinned   spmv, mpk, round_values, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
          hop_min, window_ok, min_workers,
@@ -66,6 +66,10 @@ READINGS = {
     "R10": "Powers beyond one block of q are computed as consecutive blocks of q powers "
            "and a last block of the remaining r < q powers, each seeded with the last "
            "vector of the previous block (Sec. 3, p_opt and the remainder loop).",
+    "R11": "Reduced-precision matrix storage (the paper works in FP64 only): each stored "
+           "value is rounded once to the nearest FP32 value (ties to even); vectors, "
+           "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
+           "matrix.",
 }
 
 
@@ -112,6 +116,14 @@ def spmv_rows(A, x, r0, r1):
     prod = val[a:b] * np.asarray(x, dtype=np.float64)[col[a:b]]
     rows = np.repeat(np.arange(r1 - r0, dtype=np.int64), np.diff(rowptr[r0:r1 + 1]))
     return np.bincount(rows, weights=prod, minlength=r1 - r0)
+
+
+def round_values(A, dtype=np.float32):
+    """Reading R11: the matrix with every stored value rounded once to ``dtype``
+    (round to nearest, ties to even, by NumPy's conversion) and widened back to
+    FP64 exactly.  ``mpk(round_values(A), x, p)`` is the reduced-precision MPK."""
+    n, rowptr, col, val = A
+    return type(A)(n, rowptr, col, np.asarray(val, dtype=np.float64).astype(dtype).astype(np.float64))
 
 
 def mpk(A, x, p):

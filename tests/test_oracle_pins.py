@@ -56,6 +56,46 @@ def test_mpk_exact_against_integer_dense_powers(mk, p):
         assert np.array_equal(Y[k], y.astype(np.float64)), k
 
 
+# ------------------------------------------- reduced-precision values (R11)
+def test_round_values_known_constants():
+    # catches: rounding to the wrong precision, truncation instead of nearest,
+    # or values that are not widened back exactly
+    from fractions import Fraction
+    A = S.from_dense([[0.1, 1.0 / 3.0], [2.0 ** -30, -6.0]])
+    got = [Fraction(float(v)) for v in O.round_values(A).val]
+    # 0.1 = 1.6 * 2^-4 and 1.6 * 2^23 = 13421772.8, so the nearest FP32 is 13421773 * 2^-27
+    assert got[0] == Fraction(13421773, 2 ** 27)
+    # 1/3 lies in [2^-2, 2^-1), where FP32 spacing is 2^-25: 2^25 / 3 = 11184810.67
+    # rounds up to 11184811
+    assert got[1] == Fraction(11184811, 2 ** 25)
+    assert got[2] == Fraction(1, 2 ** 30) and got[3] == -6
+    assert O.round_values(A).col is A.col and O.round_values(A).rowptr is A.rowptr
+
+
+def test_reduced_precision_mpk_exact_for_representable_values():
+    # catches: a reduced-precision path that changes anything but the values
+    A = S.laplacian_3d(6, 5, 4)
+    x = S.integer_vector(A.n, 3, bound=1 << 16)
+    assert np.array_equal(O.mpk(O.round_values(A), x, 6), O.mpk(A, x, 6))
+
+
+@pytest.mark.parametrize("p", [1, 4, 8])
+def test_reduced_precision_mpk_within_perturbation_bound(p):
+    # |A~ - A| <= u |A| elementwise with u = 2^-24 gives, in exact arithmetic,
+    # |A~^p x - A^p x| <= ((1 + u)^p - 1) |A|^p |x|; FP64 rounding adds far less
+    # than the 1e-12 slack.  catches: errors beyond single rounding of A, e.g. a
+    # rounded vector or FP32 accumulation
+    A = S.knn_graph_laplacian(2000, k=26, seed=4)
+    x = S.uniform_vector(A.n, 5)
+    u = 2.0 ** -24
+    absA = A._replace(val=np.abs(A.val))
+    bound = O.mpk(absA, np.abs(x), p)
+    err = np.abs(O.mpk(O.round_values(A), x, p) - O.mpk(A, x, p))
+    for k in range(p):
+        assert np.all(err[k] <= ((1 + u) ** (k + 1) - 1) * bound[k] * (1 + 1e-12) + 1e-300), k
+    assert err.max() > 0  # the 0.1 shift is not representable: rounding did happen
+
+
 def test_mpk_hand_worked_grid3x3(golden_dir):
     rows = {}
     with open(os.path.join(golden_dir, "grid3x3_power2.txt")) as f:
