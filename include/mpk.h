@@ -63,6 +63,10 @@ typedef enum {
 #define MPK_POLY_NEWTON 1    /* phi_k = prod_{i<=k} (A - lambda_i I)            */
 #define MPK_POLY_CHEBYSHEV 2 /* phi_k = T_k((A - theta I) / delta)             */
 
+/* value storage for mpk_options.value_type */
+#define MPK_VALUES_F64 0
+#define MPK_VALUES_F32 1
+
 /* call kinds for mpk_work_bytes */
 #define MPK_CALL_APPLY 0
 #define MPK_CALL_POLY 1
@@ -86,7 +90,14 @@ typedef struct {
     int32_t chunks_per_worker; /* chunks a wave of the blocked kernel carries
                                 together through a block (1, 2 or 4; 0 = 2;
                                 1 when rows need more than 16 register slots) */
-    int32_t reserved[10];    /* must be zero                                  */
+    int32_t value_type;      /* storage of the matrix values on the device:
+                                MPK_VALUES_F64 (0) or MPK_VALUES_F32 (1).  FP32
+                                rounds each value once to nearest at upload;
+                                vectors, products and sums stay FP64, so every
+                                call returns the FP64 MPK of the rounded matrix
+                                (the paper works in FP64 only; this halves the
+                                value bytes)                                  */
+    int32_t reserved[9];     /* must be zero                                  */
 } mpk_options;
 
 /* Fills *opt with the defaults (all zero). */

@@ -51,11 +51,14 @@ enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2 };
 
 // ------------------------------------------------------------------ device
 struct DevPlan {
-    const double* val;
+    const void* val;           // SELL values: double, or float for FP32 storage
     const int32_t* col;
     const int64_t* off;
     const int32_t* seq;
     const int32_t* seq_ptr;
+    const int32_t* unit_ptr;  // kParts + 1
+    const int32_t* unit_rec;  // one record of unit_stride ints per unit
+    int32_t ndeps;            // length of dep_idx
     const int32_t* dep_ptr;
     const int32_t* dep_idx;
     uint32_t* done;
@@ -108,8 +111,10 @@ struct SpmvArgs {
 // Row sum over the chunk's slots j = 0..width-1, in this order, as one FMA
 // chain.  Slots are fetched in batches of 8 (columns and values first, then
 // the gathers) so that a batch costs two memory round trips.
+template <typename VT>
 __device__ __forceinline__ double row_sum_mem(const DevPlan& P, const double* in, int64_t off,
                                               int width, int lane) {
+    const VT* val = (const VT*)P.val;
     double s = 0.0;
     for (int j0 = 0; j0 < width; j0 += 8) {
         int cj[8];
@@ -121,7 +126,7 @@ __device__ __forceinline__ double row_sum_mem(const DevPlan& P, const double* in
             if (j0 + t < width) {
                 const int64_t slot = off + (int64_t)(j0 + t) * kChunkRows + lane;
                 cj[t] = __builtin_nontemporal_load(P.col + slot);
-                vj[t] = __builtin_nontemporal_load(P.val + slot);
+                vj[t] = (double)__builtin_nontemporal_load(val + slot);
             }
         }
 #pragma unroll
@@ -135,7 +140,7 @@ __device__ __forceinline__ double row_sum_mem(const DevPlan& P, const double* in
 
 // Waves take chunks c = wave, wave + W, ... (a streaming pass; the matrix is
 // not reused within a launch, so no XCD partition is needed).
-template <int KIND, bool POLY>
+template <int KIND, bool POLY, typename VT>
 __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
     const int lane = threadIdx.x & 63;
     const int W = gridDim.x * kWaves;
@@ -144,7 +149,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
         const int row = c * kChunkRows + lane;
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
-        const double s = row_sum_mem(a.P, a.in, off, width, lane);
+        const double s = row_sum_mem<VT>(a.P, a.in, off, width, lane);
         if (row < a.P.n) {
             const double prev = (KIND != KIND_MONO || POLY) ? a.in[row] : 0.0;
             const double prev2 = (KIND == KIND_CHEB && a.prev2) ? a.prev2[row] : 0.0;
@@ -175,6 +180,7 @@ struct BlockArgs {
     int q;                // powers in this launch
     int workers;          // waves per partition
     int spin_limit;       // watchdog polls; negative: give up at once
+    int plain_gather;     // 1: powers written in this launch may be read with plain loads
     uint32_t epoch;
     Coefs C;
 };
@@ -202,6 +208,8 @@ __device__ bool poll_until(const BlockArgs& a, __amdgpu_buffer_rsrc_t dr, const 
     for (int spin = 0;; ++spin) {
         bool all = true;
         if (a.spin_limit >= 0) {
+            // chunk by chunk, only lanes still waiting (issuing the loads of all
+            // chunks before waiting on any measured slower)
 #pragma unroll
             for (int g = 0; g < G; ++g)
                 if (!ok[g])
@@ -222,15 +230,23 @@ __device__ bool poll_until(const BlockArgs& a, __amdgpu_buffer_rsrc_t dr, const 
 
 // Unit = G consecutive chunks of a partition's sequence, carried together
 // through the q powers of a block; its SELL slots stay in registers.
-template <int REG, int G, int KIND, bool POLY>
+template <int REG, int G, int KIND, bool POLY, typename VT>
 __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
+    const VT* val = (const VT*)a.P.val;
     const int lane = threadIdx.x & 63;
     const int part = blockIdx.x % kParts;
-    const int s0 = a.P.seq_ptr[part], s1 = a.P.seq_ptr[part + 1];
-    const int nunits = (s1 - s0 + G - 1) / G;
+    // plan tables are constant during the launch: reading them through the
+    // constant address space turns the wave-uniform reads into scalar loads
+    typedef const int32_t __attribute__((address_space(4))) kint;
+    kint* unit_ptr = (kint*)a.P.unit_ptr;
+    const int ub = unit_ptr[part];
+    const int nunits = unit_ptr[part + 1] - ub;
+    constexpr int kStride = G <= 1 ? 8 : (G == 2 ? 16 : 32);
     const int nchunks = (a.P.n + kChunkRows - 1) / kChunkRows;
     const __amdgpu_buffer_rsrc_t dr =
         __builtin_amdgcn_make_buffer_rsrc((void*)a.P.done, 0, nchunks * 4 * kFlagStride, 0x00020000);
+    const __amdgpu_buffer_rsrc_t depr =
+        __builtin_amdgcn_make_buffer_rsrc((void*)a.P.dep_idx, 0, a.P.ndeps * 4, 0x00020000);
     // Units are handed out in sequence order from a per-partition counter, so
     // only waves that are actually resident take work.  This launch uses slot
     // epoch % 4 and clears the slot of the launch after next.
@@ -242,27 +258,22 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
         if (lane == 0) t = atomicAdd(tick, 1u);
         const int u = (int)__builtin_amdgcn_readfirstlane(t);
         if (u >= nunits) break;
+        // the unit's record: chunk, slot offset / 64, width and dependency
+        // range of each of its chunks, in one scalar load
+        kint* rec = (kint*)a.P.unit_rec + (int64_t)(ub + u) * kStride;
         int c[G], width[G], d0[G], d1[G], row[G];
         int64_t off[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
-            const int pos = s0 + u * G + g;
-            c[g] = pos < s1 ? a.P.seq[pos] : -1;
-        }
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            off[g] = 0;
-            width[g] = 0;
-            d0[g] = d1[g] = 0;
+            c[g] = rec[5 * g];
+            off[g] = (int64_t)rec[5 * g + 1] * kChunkRows;
+            width[g] = rec[5 * g + 2];
+            d0[g] = rec[5 * g + 3];
+            d1[g] = rec[5 * g + 4];
             row[g] = c[g] * kChunkRows + lane;
-            if (c[g] >= 0) {
-                off[g] = a.P.off[c[g]];
-                width[g] = (int)((a.P.off[c[g] + 1] - off[g]) / kChunkRows);
-                d0[g] = a.P.dep_ptr[c[g]];
-                d1[g] = a.P.dep_ptr[c[g] + 1];
-            }
         }
-        // first batch of each dependency list: one lane per dependency
+        // first batch of each dependency list: one lane per dependency; lanes
+        // past the list read out of range and get 0
         uint32_t wo[G];
         bool need[G];
         bool long_list = false;
@@ -270,21 +281,22 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
         for (int g = 0; g < G; ++g) {
             const int i = d0[g] + lane;
             need[g] = i < d1[g];
-            wo[g] = (uint32_t)(need[g] ? a.P.dep_idx[i] : 0) * (4u * kFlagStride);
+            wo[g] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(depr, need[g] ? i * 4 : -1, 0, 0) *
+                    (4u * kFlagStride);
             long_list = long_list || (d1[g] - d0[g] > 64);
         }
-        double rv[G][REG];
+        VT rv[G][REG];
         int rc[G][REG];
 #pragma unroll
         for (int g = 0; g < G; ++g)
 #pragma unroll
             for (int j = 0; j < REG; ++j) {
                 rc[g][j] = -1;
-                rv[g][j] = 0.0;
+                rv[g][j] = (VT)0;
                 if (j < width[g]) {
                     const int64_t slot = off[g] + (int64_t)j * kChunkRows + lane;
                     rc[g][j] = __builtin_nontemporal_load(a.P.col + slot);
-                    rv[g][j] = __builtin_nontemporal_load(a.P.val + slot);
+                    rv[g][j] = __builtin_nontemporal_load(val + slot);
                 }
             }
         // the row's own previous value is needed by the shifted kinds, the
@@ -328,17 +340,26 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                 double xv[REG];
 #pragma unroll
                 for (int j = 0; j < REG; ++j)
-                    xv[j] = rc[g][j] < 0 ? 0.0 : (kl == 0 ? src[rc[g][j]] : load_coherent(src + rc[g][j]));
+                    xv[j] = rc[g][j] < 0 ? 0.0
+                            : (kl == 0 || a.plain_gather ? src[rc[g][j]] : load_coherent(src + rc[g][j]));
 #pragma unroll
                 for (int j = 0; j < REG; ++j)
-                    if (rc[g][j] >= 0) s[g] = fma(rv[g][j], xv[j], s[g]);
+                    if (rc[g][j] >= 0) {
+                        VT r = rv[g][j];
+                        // keep FP32 values narrow in registers: convert at each use
+                        // instead of letting the compiler hoist a widened copy
+                        if constexpr (sizeof(VT) == 4) asm volatile("" : "+v"(r));
+                        s[g] = fma((double)r, xv[j], s[g]);
+                    }
             }
 #pragma unroll
             for (int g = 0; g < G; ++g)
                 for (int j = REG; j < width[g]; ++j) {  // slots beyond the register cache
                     const int64_t slot = off[g] + (int64_t)j * kChunkRows + lane;
                     const int cj = a.P.col[slot];
-                    if (cj >= 0) s[g] = fma(a.P.val[slot], kl == 0 ? src[cj] : load_coherent(src + cj), s[g]);
+                    if (cj >= 0)
+                        s[g] = fma((double)val[slot], kl == 0 || a.plain_gather ? src[cj] : load_coherent(src + cj),
+                                   s[g]);
                 }
             double* dst = dest(a, kl);
             const bool last = kl + 1 == a.q;
@@ -417,7 +438,8 @@ mpk_status fail(mpk_status s, const char* fmt, ...) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t val, col, off, perm, iperm, seq, seq_ptr, dep_ptr, dep_idx, done, tickets, status, total;
+    size_t val, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, dep_ptr, dep_idx, done, tickets, status,
+        total;
 };
 
 Layout make_layout(const mpk::HostPlan& H) {
@@ -429,13 +451,15 @@ Layout make_layout(const mpk::HostPlan& H) {
         return at;
     };
     const size_t slots = H.sell_val.size();
-    L.val = take(slots * 8);
+    L.val = take(slots * (H.value_type == 1 ? 4 : 8));
     L.col = take(slots * 4);
     L.off = take((H.nchunks + 1) * 8);
     L.perm = take((size_t)H.n * 4);
     L.iperm = take((size_t)H.n * 4);
     L.seq = take((size_t)H.nchunks * 4);
     L.seq_ptr = take((kParts + 1) * 4);
+    L.unit_ptr = take((kParts + 1) * 4);
+    L.unit_rec = take(std::max<size_t>(1, H.unit_rec.size()) * 4);
     L.dep_ptr = take((H.nchunks + 1) * 4);
     L.dep_idx = take(std::max<size_t>(1, H.dep_idx.size()) * 4);
     L.done = take(std::max<size_t>(1, H.nchunks) * 4 * kFlagStride);
@@ -466,36 +490,53 @@ namespace {
 using BlockFn = void (*)(BlockArgs);
 using SpmvFn = void (*)(SpmvArgs);
 
-template <int G, int KIND, bool POLY>
+template <int G, int KIND, bool POLY, typename VT>
 BlockFn block_fn(int reg) {
     switch (reg) {
-        case 4: return mpk_block_kernel<4, G, KIND, POLY>;
-        case 7: return mpk_block_kernel<7, G, KIND, POLY>;
-        case 8: return mpk_block_kernel<8, G, KIND, POLY>;
-        case 16: return mpk_block_kernel<16, G, KIND, POLY>;
-        case 32: return mpk_block_kernel<32, G, KIND, POLY>;
-        default: return mpk_block_kernel<48, G, KIND, POLY>;
+        case 4: return mpk_block_kernel<4, G, KIND, POLY, VT>;
+        case 7: return mpk_block_kernel<7, G, KIND, POLY, VT>;
+        case 8: return mpk_block_kernel<8, G, KIND, POLY, VT>;
+        case 16: return mpk_block_kernel<16, G, KIND, POLY, VT>;
+        default: break;
     }
+    // 32 and 48 register slots exist with one chunk per worker only (the
+    // planner sets G = 1 for such rows), so only G = 1 instantiates them
+    if constexpr (G == 1) return reg == 32 ? mpk_block_kernel<32, 1, KIND, POLY, VT>
+                                           : mpk_block_kernel<48, 1, KIND, POLY, VT>;
+    return nullptr;
 }
 
-template <int G>
+template <int G, typename VT>
 BlockFn pick_block_g(int reg, int kind, bool poly) {
-    if (kind == KIND_MONO) return poly ? block_fn<G, KIND_MONO, true>(reg) : block_fn<G, KIND_MONO, false>(reg);
-    if (kind == KIND_NEWTON) return poly ? block_fn<G, KIND_NEWTON, true>(reg) : block_fn<G, KIND_NEWTON, false>(reg);
-    return poly ? block_fn<G, KIND_CHEB, true>(reg) : block_fn<G, KIND_CHEB, false>(reg);
+    if (kind == KIND_MONO)
+        return poly ? block_fn<G, KIND_MONO, true, VT>(reg) : block_fn<G, KIND_MONO, false, VT>(reg);
+    if (kind == KIND_NEWTON)
+        return poly ? block_fn<G, KIND_NEWTON, true, VT>(reg) : block_fn<G, KIND_NEWTON, false, VT>(reg);
+    return poly ? block_fn<G, KIND_CHEB, true, VT>(reg) : block_fn<G, KIND_CHEB, false, VT>(reg);
+}
+
+template <typename VT>
+BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
+    if (reg >= 32 || group == 1) return pick_block_g<1, VT>(reg, kind, poly);
+    if (group == 2) return pick_block_g<2, VT>(reg, kind, poly);
+    return pick_block_g<4, VT>(reg, kind, poly);
 }
 
 // The planner keeps one chunk per worker when rows need 32 or more slots.
-BlockFn pick_block(int reg, int group, int kind, bool poly) {
-    if (reg >= 32 || group == 1) return pick_block_g<1>(reg, kind, poly);
-    if (group == 2) return pick_block_g<2>(reg, kind, poly);
-    return pick_block_g<4>(reg, kind, poly);
+BlockFn pick_block(const mpk::HostPlan& H, int kind, bool poly) {
+    return H.value_type == 1 ? pick_block_vt<float>(H.reg_slots, H.group, kind, poly)
+                             : pick_block_vt<double>(H.reg_slots, H.group, kind, poly);
 }
 
-SpmvFn pick_spmv(int kind, bool poly) {
-    if (kind == KIND_MONO) return poly ? spmv_kernel<KIND_MONO, true> : spmv_kernel<KIND_MONO, false>;
-    if (kind == KIND_NEWTON) return poly ? spmv_kernel<KIND_NEWTON, true> : spmv_kernel<KIND_NEWTON, false>;
-    return poly ? spmv_kernel<KIND_CHEB, true> : spmv_kernel<KIND_CHEB, false>;
+template <typename VT>
+SpmvFn pick_spmv_vt(int kind, bool poly) {
+    if (kind == KIND_MONO) return poly ? spmv_kernel<KIND_MONO, true, VT> : spmv_kernel<KIND_MONO, false, VT>;
+    if (kind == KIND_NEWTON) return poly ? spmv_kernel<KIND_NEWTON, true, VT> : spmv_kernel<KIND_NEWTON, false, VT>;
+    return poly ? spmv_kernel<KIND_CHEB, true, VT> : spmv_kernel<KIND_CHEB, false, VT>;
+}
+
+SpmvFn pick_spmv(const mpk::HostPlan& H, int kind, bool poly) {
+    return H.value_type == 1 ? pick_spmv_vt<float>(kind, poly) : pick_spmv_vt<double>(kind, poly);
 }
 
 int grid_1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256)); }
@@ -520,7 +561,9 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
     a.epoch = ++p->epoch;
     a.workers = p->workers[kind][poly];
     a.spin_limit = p->H.watchdog == 0 ? kSpinLimit : p->H.watchdog;
-    hipLaunchKernelGGL(pick_block(p->H.reg_slots, p->H.group, kind, poly), dim3(p->grid_block[kind][poly]),
+    const BlockFn fn = pick_block(p->H, kind, poly);
+    if (!fn) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this row width and group");
+    hipLaunchKernelGGL(fn, dim3(p->grid_block[kind][poly]),
                        dim3(kBlockThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
     return MPK_OK;
@@ -528,7 +571,7 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
 
 mpk_status launch_spmv(mpk_plan_t p, hipStream_t st, int kind, bool poly, SpmvArgs a) {
     a.P = p->D;
-    hipLaunchKernelGGL(pick_spmv(kind, poly), dim3(p->grid_spmv), dim3(kBlockThreads), 0, st, a);
+    hipLaunchKernelGGL(pick_spmv(p->H, kind, poly), dim3(p->grid_spmv), dim3(kBlockThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
     return MPK_OK;
 }
@@ -596,6 +639,13 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
         a.out0 = j.out0;
         a.out_ld = j.ld;
         a.out_mod = j.mod;
+        // Plain loads may read the powers written in this launch when no
+        // 128-byte line is read before its producer publishes it: every power
+        // of the job has a slot of its own (no ring reuse, so neither the input
+        // slot nor any output slot is rewritten) and chunks start on line
+        // boundaries.  A launch begins with clean caches and producers store
+        // through to memory before publishing.  Otherwise device-coherent loads.
+        a.plain_gather = j.mod >= j.p && ((uintptr_t)j.out0 & 127) == 0 && ((j.ld * 8) & 127) == 0;
         a.base_slot = base % j.mod;
         a.copy0 = base == 0 ? j.copy0 : nullptr;
         a.acc_in = (j.poly && base > 0) ? j.acc : nullptr;
@@ -637,8 +687,10 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
     if (n > 0 && rowptr[n] > 0 && (!col || !val)) return fail(MPK_ERR_ARG, "col or val is null");
     mpk_options o{};
     if (opt) o = *opt;
-    for (int i = 0; i < 10; ++i)
+    for (int i = 0; i < 9; ++i)
         if (o.reserved[i] != 0) return fail(MPK_ERR_ARG, "mpk_options.reserved must be zero");
+    if (o.value_type != MPK_VALUES_F64 && o.value_type != MPK_VALUES_F32)
+        return fail(MPK_ERR_ARG, "value_type must be MPK_VALUES_F64 (0) or MPK_VALUES_F32 (1)");
     if (o.root_mode != 0 && o.root_mode != 1) return fail(MPK_ERR_ARG, "root_mode must be 0 or 1");
     if (o.root_mode == 1 && (o.root < 0 || o.root >= n)) return fail(MPK_ERR_ARG, "root out of range");
     if (o.p_block < 0 || o.p_block > mpk::kMaxBlock)
@@ -658,6 +710,7 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
         p->H.workers_req = o.workers_per_xcd;
         p->H.watchdog = o.watchdog_polls;
         p->H.group = o.chunks_per_worker ? o.chunks_per_worker : 2;
+        p->H.value_type = o.value_type;
         mpk::build_plan(p->H, n, rowptr, col, val);
         p->L = make_layout(p->H);
     } catch (const std::bad_alloc&) {
@@ -736,13 +789,22 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
         if (nb == 0) return hipSuccess;
         return hipMemcpyAsync(d + at, src, nb, hipMemcpyHostToDevice, st);
     };
-    HIP_TRY(put(L.val, H.sell_val.data(), H.sell_val.size() * 8));
+    std::vector<float> val32;  // FP32 storage: each value rounded once to nearest
+    if (H.value_type == 1) {
+        val32.resize(H.sell_val.size());
+        for (size_t i = 0; i < val32.size(); ++i) val32[i] = (float)H.sell_val[i];
+        HIP_TRY(put(L.val, val32.data(), val32.size() * 4));
+    } else {
+        HIP_TRY(put(L.val, H.sell_val.data(), H.sell_val.size() * 8));
+    }
     HIP_TRY(put(L.col, H.sell_col.data(), H.sell_col.size() * 4));
     HIP_TRY(put(L.off, H.chunk_off.data(), H.chunk_off.size() * 8));
     HIP_TRY(put(L.perm, H.perm.data(), H.perm.size() * 4));
     HIP_TRY(put(L.iperm, H.iperm.data(), H.iperm.size() * 4));
     HIP_TRY(put(L.seq, H.seq.data(), H.seq.size() * 4));
     HIP_TRY(put(L.seq_ptr, H.seq_ptr.data(), H.seq_ptr.size() * 4));
+    HIP_TRY(put(L.unit_ptr, H.unit_ptr.data(), H.unit_ptr.size() * 4));
+    HIP_TRY(put(L.unit_rec, H.unit_rec.data(), H.unit_rec.size() * 4));
     HIP_TRY(put(L.dep_ptr, H.dep_ptr.data(), H.dep_ptr.size() * 4));
     HIP_TRY(put(L.dep_idx, H.dep_idx.data(), H.dep_idx.size() * 4));
     const int64_t nd = (int64_t)std::max<int32_t>(1, H.nchunks) * kFlagStride;
@@ -756,11 +818,14 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     HIP_TRY(hipStreamSynchronize(st));
 
     DevPlan D{};
-    D.val = (const double*)(d + L.val);
+    D.val = (const void*)(d + L.val);
     D.col = (const int32_t*)(d + L.col);
     D.off = (const int64_t*)(d + L.off);
     D.seq = (const int32_t*)(d + L.seq);
     D.seq_ptr = (const int32_t*)(d + L.seq_ptr);
+    D.unit_ptr = (const int32_t*)(d + L.unit_ptr);
+    D.unit_rec = (const int32_t*)(d + L.unit_rec);
+    D.ndeps = (int32_t)H.dep_idx.size();
     D.dep_ptr = (const int32_t*)(d + L.dep_ptr);
     D.dep_idx = (const int32_t*)(d + L.dep_idx);
     D.done = (uint32_t*)(d + L.done);
@@ -782,8 +847,9 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     for (int kind = 0; kind < 3; ++kind)
         for (int poly = 0; poly < 2; ++poly) {
             int occ = 0;
+            if (!pick_block(H, kind, poly)) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this plan");
             HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, (const void*)pick_block(H.reg_slots, H.group, kind, poly), kBlockThreads, 0));
+                &occ, (const void*)pick_block(H, kind, poly), kBlockThreads, 0));
             int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
             wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
             if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));

@@ -272,7 +272,9 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
     // condition for W workers holds iff W > max over unit positions j of
     // (j - first position whose first chunk is >= bmin[unit j]), per partition.
     const int32_t G = std::max(1, P.group);
-    std::vector<int32_t> unit_ptr(kParts + 1, 0), first, unit_of(P.nchunks);
+    P.unit_ptr.assign(kParts + 1, 0);
+    std::vector<int32_t>& unit_ptr = P.unit_ptr;
+    std::vector<int32_t> first, unit_of(P.nchunks);
     for (int x = 0; x < kParts; ++x) {
         const int32_t len = P.seq_ptr[x + 1] - P.seq_ptr[x];
         for (int32_t j = 0; j < len; j += G) {
@@ -283,6 +285,28 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
         unit_ptr[x + 1] = (int32_t)first.size();
     }
     const int32_t nunits = (int32_t)first.size();
+    // one record per unit, read by the blocked kernel in a single scalar load
+    P.unit_stride = G <= 1 ? 8 : (G == 2 ? 16 : 32);
+    P.unit_rec.assign((size_t)nunits * P.unit_stride, 0);
+    for (int x = 0; x < kParts; ++x) {
+        const int32_t len = P.seq_ptr[x + 1] - P.seq_ptr[x];
+        for (int32_t u = unit_ptr[x]; u < unit_ptr[x + 1]; ++u) {
+            int32_t* r = P.unit_rec.data() + (size_t)u * P.unit_stride;
+            for (int32_t g = 0; g < G; ++g) {
+                const int32_t t = (u - unit_ptr[x]) * G + g;
+                if (t >= len) {
+                    r[5 * g] = -1;
+                    continue;
+                }
+                const int32_t c = P.seq[P.seq_ptr[x] + t];
+                r[5 * g + 0] = c;
+                r[5 * g + 1] = (int32_t)(P.chunk_off[c] / kChunkRows);
+                r[5 * g + 2] = (int32_t)((P.chunk_off[c + 1] - P.chunk_off[c]) / kChunkRows);
+                r[5 * g + 3] = P.dep_ptr[c];
+                r[5 * g + 4] = P.dep_ptr[c + 1];
+            }
+        }
+    }
     std::vector<int32_t> udep_ptr(nunits + 1, 0), udep;
     {
         std::vector<int32_t> stamp(nunits, -1), list;

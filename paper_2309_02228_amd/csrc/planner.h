@@ -19,6 +19,7 @@ struct HostPlan {
     // options
     int32_t root_mode = 0, root = 0, p_block = 4, workers_req = 0, watchdog = 0;
     int32_t group = 2;  // chunks a worker carries together (G)
+    int32_t value_type = 0;  // 0: FP64 values on the device, 1: FP32 (rounded at upload)
 
     // Sec. 3 level structure
     int32_t nlevels = 0;
@@ -40,6 +41,13 @@ struct HostPlan {
     std::vector<int32_t> seq, seq_ptr;   // chunks of each partition, ascending; kParts + 1
     std::vector<int32_t> dep_ptr;        // nchunks + 1
     std::vector<int32_t> dep_idx;        // dependency chunk ids
+    // work units of G consecutive chunks of a partition's sequence: units of
+    // partition x are unit_ptr[x] .. unit_ptr[x + 1) - 1; unit u's record is
+    // unit_rec[u * unit_stride + 5 g + {0: chunk (-1 past the end), 1: slot
+    // offset / 64, 2: width, 3: first dependency, 4: end of dependencies}]
+    std::vector<int32_t> unit_ptr;       // kParts + 1
+    std::vector<int32_t> unit_rec;
+    int32_t unit_stride = 0;             // ints per record: 8, 16 or 32 for G = 1, 2, 4
     std::vector<int32_t> min_workers;    // index q = 0..p_block (entry 0 unused), in units
                                          // of G chunks per worker
 };

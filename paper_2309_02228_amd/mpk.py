@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmpk.so")
 
 MPK_IO_PERMUTED = 1
 MPK_PLAIN = 2
+VALUE_TYPES = {"f64": 0, "f32": 1}
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
 CALL_APPLY, CALL_POLY, CALL_SSTEP = 0, 1, 2
 
@@ -39,7 +40,7 @@ class Options(ctypes.Structure):
     _fields_ = [("root_mode", ctypes.c_int32), ("root", ctypes.c_int32),
                 ("p_block", ctypes.c_int32), ("workers_per_xcd", ctypes.c_int32),
                 ("watchdog_polls", ctypes.c_int32), ("chunks_per_worker", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 10)]
+                ("value_type", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
 
 
 def _load():
@@ -121,7 +122,7 @@ class Plan:
     """
 
     def __init__(self, n, rowptr, col, val, root=None, p_block=0, workers_per_xcd=0,
-                 watchdog_polls=0, chunks_per_worker=0):
+                 watchdog_polls=0, chunks_per_worker=0, values="f64"):
         self._h = None
         self.n = int(n)
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
@@ -135,6 +136,10 @@ class Plan:
         opt.workers_per_xcd = int(workers_per_xcd)
         opt.watchdog_polls = int(watchdog_polls)
         opt.chunks_per_worker = int(chunks_per_worker)
+        if values not in VALUE_TYPES:
+            raise ValueError(f"values must be one of {sorted(VALUE_TYPES)}")
+        opt.value_type = VALUE_TYPES[values]
+        self.values = values
         h = ctypes.c_void_p()
         nbytes = ctypes.c_size_t()
         _check(_lib.mpk_build_levels(self.n, _ptr(rowptr), _ptr(col), _ptr(val), ctypes.byref(opt),
@@ -190,7 +195,7 @@ class Plan:
                                   ctypes.byref(wk), ctypes.byref(pb)))
         return {"n": n.value, "nnz": nnz.value, "nlevels": nl.value, "nchunks": nc.value,
                 "sell_slots": slots.value, "reg_slots": reg.value, "workers_per_xcd": wk.value,
-                "p_block": pb.value}
+                "p_block": pb.value, "values": self.values}
 
     # --------------------------------------------------------------- device
     def upload(self, device="cuda", stream=None):

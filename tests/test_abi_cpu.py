@@ -155,6 +155,8 @@ def test_malformed_csr_rejected():
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, root_mode=1, root=3)[0] == -1
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, root_mode=2)[0] == -1
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, chunks_per_worker=3)[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, value_type=2)[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, value_type=1)[0] == 0
     assert _build(0, [0], [], [])[0] == 0                                  # empty matrix
 
 
@@ -195,3 +197,14 @@ def test_one_hip_runtime_per_process():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True,
                          timeout=300, check=True).stdout.split()
     assert out == ["1", "1"], out
+
+
+def test_f32_values_shrink_the_device_buffer():
+    A = S.laplacian_3d(20)
+    p64 = M.Plan.from_csr(A)
+    p32 = M.Plan.from_csr(A, values="f32")
+    slots = p64.info()["sell_slots"]
+    assert p32.info()["values"] == "f32" and p64.info()["values"] == "f64"
+    assert p64.device_bytes - p32.device_bytes >= 4 * slots - 512  # 4 bytes per slot, alignment aside
+    with pytest.raises(ValueError):
+        M.Plan.from_csr(A, values="bf16")
