@@ -88,8 +88,10 @@ typedef struct {
                                 negative value makes every wait give up at
                                 once (forces the failure path in tests)      */
     int32_t chunks_per_worker; /* chunks a wave of the blocked kernel carries
-                                together through a block (1, 2 or 4; 0 = 2;
-                                1 when rows need more than 16 register slots) */
+                                together through a block (1, 2 or 4); 0 lets
+                                the planner choose: 4 for FP32 values of rows
+                                with at most 8 slots, else 2; always 1 when
+                                rows need more than 16 register slots        */
     int32_t value_type;      /* storage of the matrix values on the device:
                                 MPK_VALUES_F64 (0) or MPK_VALUES_F32 (1).  FP32
                                 rounds each value once to nearest at upload;

@@ -709,7 +709,7 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
         p->H.p_block = o.p_block ? o.p_block : 4;
         p->H.workers_req = o.workers_per_xcd;
         p->H.watchdog = o.watchdog_polls;
-        p->H.group = o.chunks_per_worker ? o.chunks_per_worker : 2;
+        p->H.group = o.chunks_per_worker;  // 0: the planner chooses
         p->H.value_type = o.value_type;
         mpk::build_plan(p->H, n, rowptr, col, val);
         p->L = make_layout(p->H);

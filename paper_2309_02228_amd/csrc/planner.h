@@ -18,7 +18,7 @@ struct HostPlan {
     int64_t nnz = 0;
     // options
     int32_t root_mode = 0, root = 0, p_block = 4, workers_req = 0, watchdog = 0;
-    int32_t group = 2;  // chunks a worker carries together (G)
+    int32_t group = 2;  // chunks a worker carries together (G); 0 = chosen by the planner
     int32_t value_type = 0;  // 0: FP64 values on the device, 1: FP32 (rounded at upload)
 
     // Sec. 3 level structure
