@@ -13,6 +13,10 @@ sparse iterative solvers on multi-core CPUs"):
 * ``spmv``, ``mpk``                 -- Sec. 3, Alg. 1 and Alg. 2
 * ``round_values``                  -- reduced-precision storage of the matrix
   values (reading R11; the paper itself works in FP64)
+* ``chebyshev_inverse_coeffs``      -- the degree-d Chebyshev polynomial
+  preconditioner (Sec. 5; reading R12)
+* ``refine_solve``                  -- FP64 iterative refinement around it, with
+  FP32-stored values for the corrections (reading R13; beyond the paper)
 * ``newton_basis``                  -- Sec. 4 (Newton basis of the s-step method)
 * ``poly_monomial``/``poly_newton``  -- Sec. 5.2, Eq. (3)
 * ``poly_chebyshev``                -- Sec. 5.3 (Chebyshev smoother; the

@@ -9,7 +9,7 @@ and unique within a row), vectors are float64 NumPy arrays.
 
 Parity status
 -------------
-pinned   spmv, mpk, round_values, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
+pinned   spmv, mpk, round_values, chebyshev_inverse_coeffs, refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
          hop_min, window_ok, min_workers,
@@ -66,6 +66,15 @@ READINGS = {
     "R10": "Powers beyond one block of q are computed as consecutive blocks of q powers "
            "and a last block of the remaining r < q powers, each seeded with the last "
            "vector of the previous block (Sec. 3, p_opt and the remainder loop).",
+    "R12": "Chebyshev polynomial preconditioner of degree d on [lmin, lmax] (the degree-d "
+           "Chebyshev preconditioner of Sec. 5; the paper gives no formula): the "
+           "polynomial s of degree d-1 with 1 - lam s(lam) = T_d((theta - lam)/delta) / "
+           "T_d(theta/delta), theta = (lmax + lmin)/2, delta = (lmax - lmin)/2, expanded "
+           "as sum_k c_k T_k((lam - theta)/delta) and applied with the recurrence of R9.",
+    "R13": "Iterative refinement (beyond the paper, which is FP64 throughout): "
+           "r_i = b - A x_i in FP64 with the unrounded matrix; stop when ||r_i|| <= tol "
+           "||b||; else x_{i+1} = x_i + s(A~) r_i with s of R12 applied to the matrix "
+           "whose values are stored in FP32 (R11).",
     "R11": "Reduced-precision matrix storage (the paper works in FP64 only): each stored "
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
@@ -195,6 +204,43 @@ def poly_chebyshev(A, x, c, theta, delta):
         out = out + c[k] * t_next
         t_prev, t = t, t_next
     return out
+
+
+def chebyshev_inverse_coeffs(d, lmin, lmax):
+    """Reading R12.  1 - lam s(lam) vanishes where T_d((theta - lam)/delta) does, i.e. at
+    the d Chebyshev points lam_j = theta + delta u_j, u_j = cos(pi (j + 1/2) / d), so s
+    (degree d - 1) is the interpolant of 1/lam at those points.  Its coefficients in the
+    basis T_k(u) follow from the discrete orthogonality of T_k at the u_j:
+    c_k = (2 - [k = 0]) / d * sum_j T_k(u_j) / lam_j.  Returns (c, theta, delta)."""
+    if d < 1 or not (0 < lmin < lmax):
+        raise ValueError("need d >= 1 and 0 < lmin < lmax")
+    theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    j = np.arange(d)
+    u = np.cos(np.pi * (j + 0.5) / d)
+    lam = theta + delta * u
+    k = np.arange(d)[:, None]
+    Tk = np.cos(k * np.arccos(u)[None, :])
+    c = (2.0 / d) * (Tk / lam[None, :]).sum(axis=1)
+    c[0] *= 0.5
+    return c, theta, delta
+
+
+def refine_solve(A, b, x0, d, lmin, lmax, tol, max_iter, values=np.float32):
+    """Reading R13: FP64 residuals with A, corrections s(A~) r with A~ = round_values(A)
+    (or A itself when ``values`` is None).  Returns (x, relative residual history)."""
+    Alo = A if values is None else round_values(A, values)
+    c, theta, delta = chebyshev_inverse_coeffs(d, lmin, lmax)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64)
+    nb = np.linalg.norm(b)
+    hist = []
+    for it in range(max_iter + 1):
+        r = b - spmv(A, x)
+        hist.append(np.linalg.norm(r) / nb)
+        if hist[-1] <= tol or it == max_iter:
+            break
+        x = x + poly_chebyshev(Alo, r, c, theta, delta)
+    return x, hist
 
 
 def chebyshev_basis(A, x, d, theta, delta):

@@ -96,6 +96,59 @@ def test_reduced_precision_mpk_within_perturbation_bound(p):
     assert err.max() > 0  # the 0.1 shift is not representable: rounding did happen
 
 
+# ------------------------------- Chebyshev preconditioner and refinement (R12, R13)
+def _cheb_T(d, u):
+    """T_d(u) in closed form: cos(d arccos u) inside [-1, 1], cosh outside."""
+    u = np.asarray(u, dtype=np.float64)
+    inside = np.abs(u) <= 1
+    out = np.empty_like(u)
+    out[inside] = np.cos(d * np.arccos(u[inside]))
+    uo = u[~inside]
+    out[~inside] = np.sign(uo) ** d * np.cosh(d * np.arccosh(np.abs(uo)))
+    return out
+
+
+@pytest.mark.parametrize("d", [1, 2, 5, 8, 16])
+def test_chebyshev_inverse_residual_polynomial(d):
+    # 1 - lam s(lam) must equal T_d((theta - lam)/delta) / T_d(theta/delta) everywhere.
+    # catches: wrong nodes, a missing halving of c_0, a sign flip of the argument
+    lmin, lmax = 0.1, 24.0
+    c, theta, delta = O.chebyshev_inverse_coeffs(d, lmin, lmax)
+    lam = np.concatenate([np.random.default_rng(d).uniform(lmin, lmax, 50), [lmin, lmax, 0.05, 30.0]])
+    u = (lam - theta) / delta
+    s_val = sum(ck * _cheb_T(k, u) for k, ck in enumerate(c))
+    want = _cheb_T(d, (theta - lam) / delta) / _cheb_T(d, np.array([theta / delta]))[0]
+    assert np.allclose(1 - lam * s_val, want, rtol=0, atol=1e-12 * np.maximum(1, np.abs(want)))
+
+
+def test_refinement_step_on_diagonal_contracts_by_residual_polynomial():
+    # with A = diag(lam) (FP32-exact values), e_{i+1} = (1 - lam s(lam)) e_i componentwise.
+    # catches: a wrong sign in the update, residuals taken with the rounded matrix
+    lam = np.array([0.25, 0.5, 1.0, 3.0, 7.5, 12.0])
+    A = S.diagonal(lam)
+    xs = np.array([1.0, -2.0, 0.5, 3.0, -1.0, 2.0])
+    b = lam * xs
+    x1, hist = O.refine_solve(A, b, np.zeros(6), 4, 0.25, 12.0, 0.0, 1)
+    c, theta, delta = O.chebyshev_inverse_coeffs(4, 0.25, 12.0)
+    rho = _cheb_T(4, (theta - lam) / delta) / _cheb_T(4, np.array([theta / delta]))[0]
+    assert np.allclose(x1 - xs, rho * (0 - xs), atol=1e-13)
+    assert len(hist) == 2 and hist[0] == 1.0
+
+
+def test_refine_solve_reaches_direct_solution():
+    # catches: an update that stalls or converges to the wrong vector
+    from scipy.sparse import csr_matrix
+    from scipy.sparse.linalg import spsolve
+    A = S.knn_graph_laplacian(1500, k=26, seed=2)
+    b = S.uniform_vector(A.n, 9)
+    lmax = 2.0 * np.max(np.diff(A.rowptr)) + 0.1  # Gershgorin bound
+    x, hist = O.refine_solve(A, b, np.zeros(A.n), 16, 0.1, lmax, 1e-10, 300)
+    assert hist[-1] <= 1e-10 and len(hist) < 300
+    xs = spsolve(csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n)).tocsc(), b)
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    assert all(h1 < h0 for h0, h1 in zip(hist, hist[1:]))  # each step contracts
+
+
 def test_mpk_hand_worked_grid3x3(golden_dir):
     rows = {}
     with open(os.path.join(golden_dir, "grid3x3_power2.txt")) as f:
