@@ -82,6 +82,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 matrix-value measurement")
+    ap.add_argument("--no-solve", action="store_true", help="skip the refinement-solve latency measurement")
+    ap.add_argument("--solve-reps", type=int, default=10)
+    ap.add_argument("--solve-degree", type=int, default=128)
     ap.add_argument("--only", choices=["both", "blocked", "plain"], default="both",
                     help="restrict the launches (for profiler runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -234,7 +237,45 @@ def main():
         }
         log(f"f32 values: blocked {wb32 / args.steps * 1e6:.1f} us/step, plain {wp32 / args.steps * 1e6:.1f} "
             f"us/step, max rel err vs FP64 {err.max():.2e}")
-    out["solve_latency_ms"] = {"p50": None, "p99": None, "note": "served solve not built"}
+    out["solve_latency_ms"] = {"p50": None, "p99": None, "note": "not measured"}
+    if not args.no_f32 and not args.no_solve and args.only == "both":
+        # A x = b to 1e-10 by FP64 iterative refinement around a Chebyshev polynomial
+        # preconditioner on the exact spectrum bounds of the Dirichlet stencil
+        cg = np.cos(np.pi / (g + 1))
+        lmin, lmax = 3 * (2 - 2 * cg), 3 * (2 + 2 * cg)
+        bvec = plan.permute(torch.tensor(synth.uniform_vector(n, 1), device=dev), 0)
+        d = args.solve_degree
+
+        def solves(lo, plain):
+            lat, res = [], None
+            for r in range(args.solve_reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = plan.refine_solve(lo, bvec, d, lmin, lmax, tol=1e-10, max_iter=2000, plain=plain)
+                torch.cuda.synchronize()
+                if r > 0:  # first solve is a warm-up
+                    lat.append(time.perf_counter() - t0)
+            lat = np.array(lat) * 1e3
+            return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                    "corrections": res[1], "final_rel_residual": res[2],
+                    "powers_per_solve": res[1] * (d - 1)}
+        mixed = solves(plan32, False)
+        fp64_plain = solves(plan, True)
+        out["solve"] = {
+            "workload": f"A x = b, 3D 7-point Laplacian {g}^3, b uniform[-1,1] seed 1 (level order), x0 = 0, "
+                        f"tol 1e-10 relative residual; FP64 iterative refinement around a degree-{d} Chebyshev "
+                        f"polynomial preconditioner on [{lmin:.6g}, {lmax:.6g}] (the exact spectrum bounds)",
+            "mixed_f32_blocked": mixed,
+            "fp64_plain": fp64_plain,
+            "speedup_p50": round(fp64_plain["p50_ms"] / mixed["p50_ms"], 3),
+            "note": f"{args.solve_reps} sequential solves of one system after one warm-up (no serving or batching)",
+        }
+        out["solve_latency_ms"] = {"p50": mixed["p50_ms"], "p99": mixed["p99_ms"],
+                                   "note": "sequential mixed-precision solves of one system; the served "
+                                           "(continuously batched) solve is not built"}
+        log(f"solve: mixed {mixed['p50_ms']:.1f} ms p50 ({mixed['corrections']} corrections), fp64 plain "
+            f"{fp64_plain['p50_ms']:.1f} ms p50")
     if not args.no_cpu_baseline and args.only == "both":
         log("cpu baseline: FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(A, x, p, args.cpu_budget)

@@ -53,7 +53,7 @@ typedef enum {
     MPK_ERR_DEVICE = -7       /* device-side failure reported by the kernel   */
 } mpk_status;
 
-/* flags for mpk_apply / poly_apply / sstep_basis */
+/* flags for mpk_apply / poly_apply / sstep_basis / mpk_refine_solve */
 #define MPK_IO_PERMUTED 1u /* x and outputs are in the plan's level order (perm space) */
 #define MPK_PLAIN 2u       /* comparator: one full SpMV launch per power (Alg. 1),
                               same layout and same per-row arithmetic            */
@@ -71,6 +71,7 @@ typedef enum {
 #define MPK_CALL_APPLY 0
 #define MPK_CALL_POLY 1
 #define MPK_CALL_SSTEP 2
+#define MPK_CALL_SOLVE 3
 
 typedef struct {
     int32_t root_mode;       /* 0: per connected component, the George-Liu
@@ -190,8 +191,9 @@ mpk_status mpk_upload(mpk_plan_t plan, void* dev_buf, size_t bytes, void* stream
 
 /*
  * Device work-buffer size (bytes) that mpk_apply (call = MPK_CALL_APPLY),
- * poly_apply (MPK_CALL_POLY, p = degree d) or sstep_basis (MPK_CALL_SSTEP,
- * p = s) needs with the given flags.  Zero when none is needed.
+ * poly_apply (MPK_CALL_POLY, p = degree d), sstep_basis (MPK_CALL_SSTEP,
+ * p = s) or mpk_refine_solve (MPK_CALL_SOLVE, p = degree, asked of the `lo`
+ * plan) needs with the given flags.  Zero when none is needed.
  */
 mpk_status mpk_work_bytes(mpk_plan_t plan, int32_t call, int32_t p, uint32_t flags,
                           size_t* bytes);
@@ -240,6 +242,37 @@ mpk_status poly_apply(mpk_plan_t plan, int32_t kind, int32_t d, const double* c,
  * `work`.  Errors: MPK_ERR_ARG (s < 1, ldv < n, zero sigma, null pointers,
  * work too small), MPK_ERR_STATE, MPK_ERR_HIP.
  */
+/*
+ * Solve A x = b by FP64 iterative refinement around the degree-d Chebyshev
+ * polynomial preconditioner (the polynomial preconditioner of Sec. 5; the
+ * refinement goes beyond the paper, which works in FP64 throughout):
+ *   r_i = b - A x_i, computed in FP64 with `hi` (FP64 values);
+ *   stop when ||r_i||_2 <= tol ||b||_2 or i == max_iter;
+ *   x_{i+1} = x_i + s(A) r_i, with s of degree d - 1 such that
+ *   1 - lam s(lam) = T_d((theta - lam)/delta) / T_d(theta/delta),
+ *   theta = (lmax + lmin)/2, delta = (lmax - lmin)/2 (the interpolant of
+ *   1/lam at the d zeros of T_d on [lmin, lmax]), applied through the
+ *   Chebyshev recurrence of poly_apply on `lo` (FP32 values for the mixed-
+ *   precision solve, or FP64), blocked unless MPK_PLAIN.
+ * The iteration contracts when [lmin, lmax] holds the spectrum of an SPD A
+ * (for example lmin a known shift and lmax a Gershgorin bound).
+ * hi and lo must be uploaded plans of the same matrix with the same level
+ * order (checked).  b and x are device vectors of n entries (perm space
+ * with MPK_IO_PERMUTED); x holds the initial guess on entry and the result
+ * on return; b must not alias x.  work: mpk_work_bytes(lo, MPK_CALL_SOLVE,
+ * d, flags) bytes.  iters_out (corrections applied) and relres_out (the
+ * last ||r||/||b||, or ||r|| when b = 0) are host pointers and may be NULL.
+ * The call synchronises `stream` once per step to read the residual norm;
+ * norms are reduced in a fixed order, so repeated calls give identical
+ * results.  Errors: MPK_ERR_ARG (hi not FP64, plans of different matrices,
+ * d outside 1..4096, lmin/lmax not 0 < lmin < lmax, tol < 0, max_iter < 0,
+ * null pointers, work too small), MPK_ERR_STATE, MPK_ERR_HIP, MPK_ERR_DEVICE.
+ */
+mpk_status mpk_refine_solve(mpk_plan_t hi, mpk_plan_t lo, int32_t degree, double lmin, double lmax,
+                            const double* b, double* x, double tol, int32_t max_iter, uint32_t flags,
+                            void* work, size_t work_bytes, int32_t* iters_out, double* relres_out,
+                            void* stream);
+
 mpk_status sstep_basis(mpk_plan_t plan, int32_t s, const double* lambda, const double* sigma,
                        const double* v, double* V, int64_t ldv, uint32_t flags, void* work,
                        size_t work_bytes, void* stream);

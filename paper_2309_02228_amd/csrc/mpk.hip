@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -414,6 +415,69 @@ __global__ void scale_kernel(const double* x, double* out, double a, int32_t n) 
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
         out[i] = a * x[i];
+}
+
+// ---- iterative refinement helpers ------------------------------------------
+constexpr int kRedParts = 2048;  // workgroups of the reduction kernels (fixed: deterministic sums)
+
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Sum of the four waves' values, left by thread 0 in part[blockIdx.x].
+__device__ __forceinline__ void block_partial(double v, double* part) {
+    __shared__ double red[kWaves];
+    v = wave_sum(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// r = b - A x with the SpMV kernel's row arithmetic (FP64 sums); each
+// workgroup leaves the sum of r_i^2 over its rows in part[blockIdx.x].
+template <typename VT>
+__global__ __launch_bounds__(kBlockThreads) void residual_kernel(DevPlan P, const double* b, const double* x,
+                                                                 double* r, double* part) {
+    const int lane = threadIdx.x & 63;
+    const int W = gridDim.x * kWaves;
+    const int nchunks = (P.n + kChunkRows - 1) / kChunkRows;
+    double acc = 0.0;
+    for (int c = blockIdx.x * kWaves + (threadIdx.x >> 6); c < nchunks; c += W) {
+        const int row = c * kChunkRows + lane;
+        const int64_t off = P.off[c];
+        const int width = (int)((P.off[c + 1] - off) / kChunkRows);
+        const double s = row_sum_mem<VT>(P, x, off, width, lane);
+        if (row < P.n) {
+            const double ri = b[row] - s;
+            r[row] = ri;
+            acc = fma(ri, ri, acc);
+        }
+    }
+    block_partial(acc, part);
+}
+
+__global__ __launch_bounds__(kBlockThreads) void sumsq_kernel(const double* v, int64_t n, double* part) {
+    double acc = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        acc = fma(v[i], v[i], acc);
+    block_partial(acc, part);
+}
+
+// One workgroup adds the m partial sums in a fixed order into out[0].
+__global__ __launch_bounds__(kBlockThreads) void reduce_kernel(const double* part, int m, double* out) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < m; i += blockDim.x) acc += part[i];
+    __shared__ double red[kWaves];
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) out[0] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void axpy_kernel(double* x, const double* z, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] += z[i];
 }
 
 // ------------------------------------------------------------------ host
@@ -880,6 +944,7 @@ MPK_API mpk_status mpk_work_bytes(mpk_plan_t p, int32_t call, int32_t pw, uint32
         case MPK_CALL_APPLY: *bytes = perm ? 0 : v * (1 + (size_t)pw); break;
         case MPK_CALL_POLY: *bytes = v * (perm ? 2 : 4); break;
         case MPK_CALL_SSTEP: *bytes = perm ? 0 : v * (1 + (size_t)pw); break;
+        case MPK_CALL_SOLVE: *bytes = v * (perm ? 4 : 6) + 8 * (size_t)(kRedParts + 8); break;
         default: return fail(MPK_ERR_ARG, "unknown call kind %d", call);
     }
     return MPK_OK;
@@ -975,6 +1040,116 @@ MPK_API mpk_status poly_apply(mpk_plan_t p, int32_t kind, int32_t d, const doubl
     }
     if (!permuted) s = permute_vecs(p, st, acc, 0, out, 0, 1, 1);
     return s;
+}
+
+MPK_API mpk_status mpk_refine_solve(mpk_plan_t hi, mpk_plan_t lo, int32_t degree, double lmin, double lmax,
+                                    const double* b, double* x, double tol, int32_t max_iter, uint32_t flags,
+                                    void* work, size_t work_bytes, int32_t* iters_out, double* relres_out,
+                                    void* stream) {
+    if (iters_out) *iters_out = 0;
+    if (relres_out) *relres_out = 0.0;
+    if (!hi || !lo) return fail(MPK_ERR_ARG, "null plan");
+    if (hi->H.value_type != MPK_VALUES_F64) return fail(MPK_ERR_ARG, "hi must store FP64 values");
+    if (hi->H.n != lo->H.n || hi->H.nnz != lo->H.nnz || hi->H.perm != lo->H.perm)
+        return fail(MPK_ERR_ARG, "hi and lo must be plans of the same matrix with the same level order");
+    if (degree < 1 || degree > 4096) return fail(MPK_ERR_ARG, "degree must be in 1..4096 (got %d)", degree);
+    if (!(lmin > 0.0) || !(lmax > lmin)) return fail(MPK_ERR_ARG, "need 0 < lmin < lmax");
+    if (!(tol >= 0.0)) return fail(MPK_ERR_ARG, "tol must be >= 0");
+    if (max_iter < 0) return fail(MPK_ERR_ARG, "max_iter must be >= 0");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    const int32_t n = hi->H.n;
+    if (n > 0 && (!b || !x)) return fail(MPK_ERR_ARG, "b or x is null");
+    size_t need = 0;
+    mpk_work_bytes(lo, MPK_CALL_SOLVE, degree, flags, &need);
+    if (!work || work_bytes < need) return fail(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    mpk_status s = check_uploaded(hi);
+    if (s == MPK_OK) s = check_uploaded(lo);
+    if (s != MPK_OK) return s;
+    if (n == 0) return MPK_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const bool permuted = flags & MPK_IO_PERMUTED;
+    const size_t nn = (size_t)n;
+    double* w = (double*)work;
+    double* r = w;                // residual
+    double* z = w + nn;           // correction
+    double* ring = w + 2 * nn;    // two Chebyshev vectors
+    double* part = w + 4 * nn;    // partial sums, then two scalars
+    double* sc = part + kRedParts;
+    double* bp = (double*)b;
+    double* xp = x;
+    if (!permuted) {  // level-order copies after the scalars
+        bp = sc + 8;
+        xp = bp + nn;
+        s = permute_vecs(hi, st, b, 0, bp, 0, 1, 0);
+        if (s == MPK_OK) s = permute_vecs(hi, st, x, 0, xp, 0, 1, 0);
+        if (s != MPK_OK) return s;
+    }
+    auto norm2 = [&](bool residual, double* out) -> mpk_status {
+        if (residual) {
+            hipLaunchKernelGGL(hi->H.value_type == MPK_VALUES_F32 ? residual_kernel<float> : residual_kernel<double>,
+                               dim3(kRedParts), dim3(kBlockThreads), 0, st, hi->D, (const double*)bp,
+                               (const double*)xp, r, part);
+        } else {
+            sumsq_kernel<<<kRedParts, kBlockThreads, 0, st>>>(bp, n, part);
+        }
+        HIP_TRY(hipGetLastError());
+        reduce_kernel<<<1, kBlockThreads, 0, st>>>(part, kRedParts, sc);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(out, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        return MPK_OK;
+    };
+    // Chebyshev interpolant of 1/lam at the d zeros of T_d on [lmin, lmax]: its
+    // residual polynomial is T_d((theta - lam)/delta) / T_d(theta/delta)
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    std::vector<double> coef(degree, 0.0);
+    for (int j = 0; j < degree; ++j) {
+        const double ang = 3.14159265358979323846 * (j + 0.5) / degree;
+        const double inv = 1.0 / (theta + delta * std::cos(ang));
+        for (int k = 0; k < degree; ++k) coef[k] += std::cos(k * ang) * inv;
+    }
+    for (int k = 0; k < degree; ++k) coef[k] *= (k == 0 ? 1.0 : 2.0) / degree;
+    double nb2 = 0.0;
+    s = norm2(false, &nb2);
+    if (s != MPK_OK) return s;
+    const double nb = std::sqrt(nb2);
+    int it = 0;
+    double rel = 0.0;
+    for (;; ++it) {
+        double rr = 0.0;
+        s = norm2(true, &rr);
+        if (s != MPK_OK) return s;
+        rel = nb > 0.0 ? std::sqrt(rr) / nb : std::sqrt(rr);
+        if (rel <= tol || it == max_iter) break;
+        if (degree == 1) {
+            scale_kernel<<<grid_1d(n), 256, 0, st>>>(r, z, coef[0], n);
+            HIP_TRY(hipGetLastError());
+        } else {
+            PowerJob j;
+            j.kind = KIND_CHEB;
+            j.poly = true;
+            j.p = degree - 1;
+            j.x = r;
+            j.out0 = ring;
+            j.ld = n;
+            j.mod = 2;
+            j.acc = z;
+            j.c = coef;
+            j.theta = theta;
+            j.delta = delta;
+            s = run_powers(lo, st, j, flags & MPK_PLAIN);
+            if (s != MPK_OK) return s;
+        }
+        axpy_kernel<<<grid_1d(n), 256, 0, st>>>(xp, z, n);
+        HIP_TRY(hipGetLastError());
+    }
+    if (!permuted) {
+        s = permute_vecs(hi, st, xp, 0, x, 0, 1, 1);
+        if (s != MPK_OK) return s;
+    }
+    if (iters_out) *iters_out = it;
+    if (relres_out) *relres_out = rel;
+    return MPK_OK;
 }
 
 MPK_API mpk_status sstep_basis(mpk_plan_t p, int32_t sdeg, const double* lambda, const double* sigma,

@@ -17,7 +17,7 @@ MPK_IO_PERMUTED = 1
 MPK_PLAIN = 2
 VALUE_TYPES = {"f64": 0, "f32": 1}
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
-CALL_APPLY, CALL_POLY, CALL_SSTEP = 0, 1, 2
+CALL_APPLY, CALL_POLY, CALL_SSTEP, CALL_SOLVE = 0, 1, 2, 3
 
 STATUS = {0: "MPK_OK", -1: "MPK_ERR_ARG", -2: "MPK_ERR_CSR", -3: "MPK_ERR_NOMEM",
           -4: "MPK_ERR_HIP", -5: "MPK_ERR_UNSUPPORTED", -6: "MPK_ERR_STATE",
@@ -26,7 +26,7 @@ STATUS = {0: "MPK_OK", -1: "MPK_ERR_ARG", -2: "MPK_ERR_CSR", -3: "MPK_ERR_NOMEM"
 # every entry point declared in include/mpk.h
 EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_levels",
            "mpk_get_levels", "mpk_get_partition", "mpk_get_deps", "mpk_min_workers",
-           "mpk_upload", "mpk_work_bytes", "mpk_apply", "poly_apply", "sstep_basis",
+           "mpk_upload", "mpk_work_bytes", "mpk_apply", "poly_apply", "sstep_basis", "mpk_refine_solve",
            "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy"]
 
 
@@ -72,6 +72,8 @@ def _load():
         "mpk_apply": (I32, [P, D, D, I64, I32, U32, P, SZ, P]),
         "poly_apply": (I32, [P, I32, I32, P, P, D, D, U32, P, SZ, P]),
         "sstep_basis": (I32, [P, I32, P, P, D, D, I64, U32, P, SZ, P]),
+        "mpk_refine_solve": (I32, [P, P, I32, ctypes.c_double, ctypes.c_double, D, D, ctypes.c_double, I32,
+                                   U32, P, SZ, pI32, ctypes.POINTER(ctypes.c_double), P]),
         "mpk_permute": (I32, [P, D, D, I32, P]),
         "mpk_check_device": (I32, [P, P]),
         "mpk_plan_info": (I32, [P, pI64, pI64, pI32, pI32, pI64, pI32, pI32, pI32]),
@@ -260,6 +262,23 @@ class Plan:
         _check(_lib.sstep_basis(self._h, s, _ptr(lam), _ptr(sig), _dptr(v), _dptr(V), V.stride(0),
                                 flags, _dptr(w), nb, _stream(stream)))
         return V
+
+    def refine_solve(self, lo, b, degree, lmin, lmax, tol=1e-10, max_iter=1000, x=None, permuted=True,
+                     plain=False, stream=None):
+        """Solve A x = b: FP64 residuals with this plan (FP64 values), corrections with
+        the degree-``degree`` Chebyshev polynomial of ``lo`` (the same matrix, FP32 or FP64
+        values).  Returns (x, corrections applied, final ||r|| / ||b||)."""
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        flags = self._flags(permuted, plain)
+        w, nb = lo._work(CALL_SOLVE, degree, flags, b.device)
+        it = ctypes.c_int32()
+        rel = ctypes.c_double()
+        _check(_lib.mpk_refine_solve(self._h, lo._h, int(degree), float(lmin), float(lmax), _dptr(b), _dptr(x),
+                                     float(tol), int(max_iter), flags, _dptr(w), nb, ctypes.byref(it),
+                                     ctypes.byref(rel), _stream(stream)))
+        return x, it.value, rel.value
 
     def permute(self, x, direction=0, out=None, stream=None):
         import torch
