@@ -84,7 +84,7 @@ def main():
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 matrix-value measurement")
     ap.add_argument("--no-solve", action="store_true", help="skip the refinement-solve latency measurement")
     ap.add_argument("--solve-reps", type=int, default=10)
-    ap.add_argument("--solve-degree", type=int, default=128)
+    ap.add_argument("--solve-degree", type=int, default=256)
     ap.add_argument("--only", choices=["both", "blocked", "plain"], default="both",
                     help="restrict the launches (for profiler runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -214,8 +214,10 @@ def main():
         out["roofline_equivalent_frac"] = round(value / (flops / (b_blk / (HBM_PEAK_GBS * 1e9)) / 1e9), 4)
     if not args.no_f32 and args.only == "both":
         # FP32 storage of the matrix values (vectors, products and sums stay FP64)
+        # four chunks per wave: FP32 values leave registers for them (measured faster
+        # than two for the power kernel)
         plan32 = Plan.from_csr(A, p_block=args.p_block or min(p, 15),
-                               chunks_per_worker=args.chunks_per_worker, values="f32").upload(dev)
+                               chunks_per_worker=args.chunks_per_worker or 4, values="f32").upload(dev)
         xd32 = plan32.permute(torch.tensor(x, device=dev), 0)
         Y32 = torch.empty_like(Y)
         wb32, _ = timed(False, plan32, xd32, Y32)
@@ -230,6 +232,7 @@ def main():
             "ms_per_step": round(wb32 / args.steps * 1e3, 5),
             "speedup_vs_plain_f32": round(wp32 / wb32, 3),
             "speedup_vs_f64_blocked": round(wall / wb32, 3) if key == "blocked" else None,
+            "chunks_per_worker": args.chunks_per_worker or 4,
             "bytes_per_launch": int(bytes_per_launch - 4 * nnz / launches_per_step),
             "max_rel_err_vs_f64_per_power": float(err.max()),
             "note": "matrix values rounded once to FP32 at upload; vectors, products and sums "
@@ -260,7 +263,10 @@ def main():
                     "p99_ms": round(float(np.percentile(lat, 99)), 3),
                     "corrections": res[1], "final_rel_residual": res[2],
                     "powers_per_solve": res[1] * (d - 1)}
-        mixed = solves(plan32, False)
+        # corrections with FP32 values and two chunks per wave (the polynomial kernel
+        # needs the registers that four chunks would take)
+        plan_lo = Plan.from_csr(A, p_block=args.p_block or min(p, 15), values="f32").upload(dev)
+        mixed = solves(plan_lo, False)
         fp64_plain = solves(plan, True)
         out["solve"] = {
             "workload": f"A x = b, 3D 7-point Laplacian {g}^3, b uniform[-1,1] seed 1 (level order), x0 = 0, "

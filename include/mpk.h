@@ -89,10 +89,10 @@ typedef struct {
                                 negative value makes every wait give up at
                                 once (forces the failure path in tests)      */
     int32_t chunks_per_worker; /* chunks a wave of the blocked kernel carries
-                                together through a block (1, 2 or 4); 0 lets
-                                the planner choose: 4 for FP32 values of rows
-                                with at most 8 slots, else 2; always 1 when
-                                rows need more than 16 register slots        */
+                                together through a block (1, 2 or 4; 0 = 2;
+                                always 1 when rows need more than 16 register
+                                slots).  With FP32 values, 4 suits mpk_apply
+                                on rows of at most 8 slots                    */
     int32_t value_type;      /* storage of the matrix values on the device:
                                 MPK_VALUES_F64 (0) or MPK_VALUES_F32 (1).  FP32
                                 rounds each value once to nearest at upload;
@@ -224,7 +224,9 @@ mpk_status mpk_apply(mpk_plan_t plan, const double* x, double* Y, int64_t ldy, i
  * c (host, d+1 entries) and params (host) are copied before return.
  * x and out are device vectors of n entries (perm space with
  * MPK_IO_PERMUTED); out must not alias x.  Intermediate vectors live in
- * `work` (two vectors, plus two more without MPK_IO_PERMUTED).
+ * `work`: a ring of p_block + 2 vectors (so that a launch never rewrites a
+ * vector it reads and may gather with plain loads), plus two more without
+ * MPK_IO_PERMUTED.
  * Errors: MPK_ERR_ARG (d < 0, unknown kind, delta == 0, null pointers, work
  * too small), MPK_ERR_STATE, MPK_ERR_HIP.
  */

@@ -605,6 +605,11 @@ SpmvFn pick_spmv(const mpk::HostPlan& H, int kind, bool poly) {
 
 int grid_1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256)); }
 
+// Vectors in the ring of a polynomial: q + 2 (one launch's q outputs, its
+// input and, for Chebyshev, the power before it stay distinct, so the
+// launch may gather with plain loads).
+int poly_ring(mpk_plan_t p) { return p->H.p_block + 2; }
+
 mpk_status check_uploaded(mpk_plan_t p) {
     if (!p) return fail(MPK_ERR_ARG, "null plan");
     if (!p->dev) return fail(MPK_ERR_STATE, "plan has no device buffer: call mpk_upload first");
@@ -704,12 +709,15 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
         a.out_ld = j.ld;
         a.out_mod = j.mod;
         // Plain loads may read the powers written in this launch when no
-        // 128-byte line is read before its producer publishes it: every power
-        // of the job has a slot of its own (no ring reuse, so neither the input
-        // slot nor any output slot is rewritten) and chunks start on line
-        // boundaries.  A launch begins with clean caches and producers store
-        // through to memory before publishing.  Otherwise device-coherent loads.
-        a.plain_gather = j.mod >= j.p && ((uintptr_t)j.out0 & 127) == 0 && ((j.ld * 8) & 127) == 0;
+        // 128-byte line is read before its producer publishes it: the launch
+        // writes q slots distinct from each other and from the slots it reads
+        // (y_base, and y_{base-1} for Chebyshev), which holds when every power
+        // of the job has its own slot or the ring has at least q + 2 slots, and
+        // chunks start on line boundaries.  A launch begins with clean caches
+        // and producers store through to memory before publishing.  Otherwise
+        // device-coherent loads.
+        a.plain_gather = (j.mod >= j.p || j.mod >= q + 2) && ((uintptr_t)j.out0 & 127) == 0 &&
+                         ((j.ld * 8) & 127) == 0;
         a.base_slot = base % j.mod;
         a.copy0 = base == 0 ? j.copy0 : nullptr;
         a.acc_in = (j.poly && base > 0) ? j.acc : nullptr;
@@ -942,9 +950,9 @@ MPK_API mpk_status mpk_work_bytes(mpk_plan_t p, int32_t call, int32_t pw, uint32
     const bool perm = flags & MPK_IO_PERMUTED;
     switch (call) {
         case MPK_CALL_APPLY: *bytes = perm ? 0 : v * (1 + (size_t)pw); break;
-        case MPK_CALL_POLY: *bytes = v * (perm ? 2 : 4); break;
+        case MPK_CALL_POLY: *bytes = v * (poly_ring(p) + (perm ? 0 : 2)); break;
         case MPK_CALL_SSTEP: *bytes = perm ? 0 : v * (1 + (size_t)pw); break;
-        case MPK_CALL_SOLVE: *bytes = v * (perm ? 4 : 6) + 8 * (size_t)(kRedParts + 8); break;
+        case MPK_CALL_SOLVE: *bytes = v * (2 + poly_ring(p) + (perm ? 0 : 2)) + 8 * (size_t)(kRedParts + 8); break;
         default: return fail(MPK_ERR_ARG, "unknown call kind %d", call);
     }
     return MPK_OK;
@@ -1010,11 +1018,12 @@ MPK_API mpk_status poly_apply(mpk_plan_t p, int32_t kind, int32_t d, const doubl
     double* w = (double*)work;
     const double* xin = x;
     double* acc = out;
-    if (!permuted) {
-        s = permute_vecs(p, st, x, 0, w + 2 * (size_t)n, 0, 1, 0);
+    if (!permuted) {  // level-order copies after the ring
+        const size_t ring = (size_t)poly_ring(p) * n;
+        s = permute_vecs(p, st, x, 0, w + ring, 0, 1, 0);
         if (s != MPK_OK) return s;
-        xin = w + 2 * (size_t)n;
-        acc = w + 3 * (size_t)n;
+        xin = w + ring;
+        acc = w + ring + n;
     }
     if (d == 0) {
         scale_kernel<<<grid_1d(n), 256, 0, st>>>(xin, acc, c[0], n);
@@ -1025,9 +1034,9 @@ MPK_API mpk_status poly_apply(mpk_plan_t p, int32_t kind, int32_t d, const doubl
         j.poly = true;
         j.p = d;
         j.x = xin;
-        j.out0 = w;  // ring of two vectors: t_k in slot (k-1) % 2
+        j.out0 = w;  // ring of poly_ring(p) vectors: t_k in slot (k-1) % mod
         j.ld = n;
-        j.mod = 2;
+        j.mod = poly_ring(p);
         j.acc = acc;
         j.c.assign(c, c + d + 1);
         if (j.kind == KIND_NEWTON) j.lam.assign(params, params + d);
@@ -1072,8 +1081,8 @@ MPK_API mpk_status mpk_refine_solve(mpk_plan_t hi, mpk_plan_t lo, int32_t degree
     double* w = (double*)work;
     double* r = w;                // residual
     double* z = w + nn;           // correction
-    double* ring = w + 2 * nn;    // two Chebyshev vectors
-    double* part = w + 4 * nn;    // partial sums, then two scalars
+    double* ring = w + 2 * nn;    // Chebyshev vectors
+    double* part = w + (2 + poly_ring(lo)) * nn;  // partial sums, then two scalars
     double* sc = part + kRedParts;
     double* bp = (double*)b;
     double* xp = x;
@@ -1132,7 +1141,7 @@ MPK_API mpk_status mpk_refine_solve(mpk_plan_t hi, mpk_plan_t lo, int32_t degree
             j.x = r;
             j.out0 = ring;
             j.ld = n;
-            j.mod = 2;
+            j.mod = poly_ring(lo);
             j.acc = z;
             j.c = coef;
             j.theta = theta;

@@ -222,10 +222,10 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
     // register slots: the smallest supported width covering every chunk, capped
     P.reg_slots = P.max_width <= 4 ? 4 : P.max_width <= 7 ? 7 : P.max_width <= 8 ? 8
                 : P.max_width <= 16 ? 16 : P.max_width <= 32 ? 32 : 48;
-    // chunks per worker when the caller leaves it open: FP32 values halve the
-    // register cost of a slot, which leaves room for four chunks of narrow rows
-    // (measured faster than two); wide rows leave room for one chunk only
-    if (P.group == 0) P.group = (P.value_type == 1 && P.reg_slots <= 8) ? 4 : 2;
+    // chunks per worker when the caller leaves it open: two (four chunks of
+    // FP32 values fit the plain power kernel better, but not the polynomial
+    // kernels, and a plan serves both); wide rows leave room for one chunk only
+    if (P.group == 0) P.group = 2;
     if (P.reg_slots >= 32) P.group = 1;
 
     // ---- chunk ownership by position inside the level (R6) ------------------

@@ -118,7 +118,9 @@ def test_work_bytes():
     plan = M.Plan.from_csr(S.laplacian_2d(10))
     assert plan.work_bytes(M.CALL_APPLY, 4, M.MPK_IO_PERMUTED) == 0
     assert plan.work_bytes(M.CALL_APPLY, 4, 0) == 100 * 8 * 5
-    assert plan.work_bytes(M.CALL_POLY, 8, M.MPK_IO_PERMUTED) == 100 * 8 * 2
+    assert plan.work_bytes(M.CALL_POLY, 8, M.MPK_IO_PERMUTED) == 100 * 8 * (4 + 2)  # ring of p_block + 2
+    assert plan.work_bytes(M.CALL_POLY, 8, 0) == 100 * 8 * (4 + 2 + 2)
+    assert plan.work_bytes(M.CALL_SOLVE, 8, M.MPK_IO_PERMUTED) == 100 * 8 * (2 + 6) + 8 * (2048 + 8)
     assert plan.work_bytes(M.CALL_SSTEP, 3, 0) == 100 * 8 * 4
 
 

@@ -86,9 +86,11 @@ def test_f32_values_integer_matrix_equals_fp64_bitwise():
     assert np.array_equal(apply_orig(plan, perm, x, 8), apply_orig(p64, perm, x, 8))
 
 
-@pytest.mark.parametrize("G", [1, 4])
-def test_f32_values_chunks_per_worker(G):
-    A = S.knn_graph_laplacian(9000, k=26, seed=6)
+@pytest.mark.parametrize("G", [1, 2, 4])
+@pytest.mark.parametrize("mk", [lambda: S.knn_graph_laplacian(9000, k=26, seed=6),  # wide rows: G = 1
+                                lambda: S.laplacian_3d(23, 19, 21)])                # narrow rows
+def test_f32_values_chunks_per_worker(G, mk):
+    A = mk()
     plan, perm = f32_plan(A, p_block=5, chunks_per_worker=G)
     x = S.uniform_vector(A.n, 6)
     got = apply_orig(plan, perm, x, 12)
