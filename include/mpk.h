@@ -100,7 +100,13 @@ typedef struct {
                                 call returns the FP64 MPK of the rounded matrix
                                 (the paper works in FP64 only; this halves the
                                 value bytes)                                  */
-    int32_t reserved[9];     /* must be zero                                  */
+    int32_t max_reg_slots;   /* largest number of SELL slots per row the
+                                blocked kernel keeps in registers (4, 7, 8,
+                                16 or 32; 0 = automatic: the smallest of these
+                                covering the widest chunk, 32 at most).  Slots
+                                beyond it are re-read from memory at every
+                                power.                                        */
+    int32_t reserved[8];     /* must be zero                                  */
 } mpk_options;
 
 /* Fills *opt with the defaults (all zero). */
@@ -205,8 +211,11 @@ mpk_status mpk_work_bytes(mpk_plan_t plan, int32_t call, int32_t p, uint32_t fla
  * space (x_perm[i] = x[perm[i]]), which is the fast path; otherwise the library
  * permutes through `work` (mpk_work_bytes).  Powers run in blocks of
  * q = p_block (the last block holds the remaining p mod q, Sec. 3 remainder
- * loop).  MPK_PLAIN runs p full SpMV launches instead (the comparator).
- * Results of the blocked and plain paths are bitwise identical.
+ * loop); q is lowered until the deadlock bound of the plan (mpk_min_workers)
+ * fits the resident waves, and when only q = 1 fits (BFS levels too wide for
+ * the waves) the call runs one SpMV launch per power, as blocking could not
+ * reuse the matrix.  MPK_PLAIN always runs p full SpMV launches (the
+ * comparator).  Results of the blocked and plain paths are bitwise identical.
  * Errors: MPK_ERR_ARG (p < 1, ldy < n, null pointers, work too small),
  * MPK_ERR_STATE (not uploaded), MPK_ERR_HIP.
  */

@@ -563,10 +563,9 @@ BlockFn block_fn(int reg) {
         case 16: return mpk_block_kernel<16, G, KIND, POLY, VT>;
         default: break;
     }
-    // 32 and 48 register slots exist with one chunk per worker only (the
-    // planner sets G = 1 for such rows), so only G = 1 instantiates them
-    if constexpr (G == 1) return reg == 32 ? mpk_block_kernel<32, 1, KIND, POLY, VT>
-                                           : mpk_block_kernel<48, 1, KIND, POLY, VT>;
+    // 32 register slots exist with one chunk per worker only (the planner
+    // sets G = 1 for such rows), so only G = 1 instantiates them
+    if constexpr (G == 1) return reg == 32 ? mpk_block_kernel<32, 1, KIND, POLY, VT> : nullptr;
     return nullptr;
 }
 
@@ -676,7 +675,10 @@ const double* job_vec(const PowerJob& j, int k) { return k == 0 ? j.x : job_dest
 mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plain) {
     if (j.p == 0) return MPK_OK;
     if (p->H.n == 0) return MPK_OK;
-    if (plain) {
+    // When the deadlock bound admits only one power per launch (levels too wide
+    // for the resident waves), blocking cannot reuse the matrix and the plain
+    // kernel is faster; both give bitwise-equal results.
+    if (plain || p->q_eff[j.kind][j.poly] <= 1) {
         for (int k = 1; k <= j.p; ++k) {
             SpmvArgs a{};
             a.in = job_vec(j, k - 1);
@@ -759,8 +761,11 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
     if (n > 0 && rowptr[n] > 0 && (!col || !val)) return fail(MPK_ERR_ARG, "col or val is null");
     mpk_options o{};
     if (opt) o = *opt;
-    for (int i = 0; i < 9; ++i)
+    for (int i = 0; i < 8; ++i)
         if (o.reserved[i] != 0) return fail(MPK_ERR_ARG, "mpk_options.reserved must be zero");
+    if (o.max_reg_slots != 0 && o.max_reg_slots != 4 && o.max_reg_slots != 7 && o.max_reg_slots != 8 &&
+        o.max_reg_slots != 16 && o.max_reg_slots != 32)
+        return fail(MPK_ERR_ARG, "max_reg_slots must be 0, 4, 7, 8, 16 or 32");
     if (o.value_type != MPK_VALUES_F64 && o.value_type != MPK_VALUES_F32)
         return fail(MPK_ERR_ARG, "value_type must be MPK_VALUES_F64 (0) or MPK_VALUES_F32 (1)");
     if (o.root_mode != 0 && o.root_mode != 1) return fail(MPK_ERR_ARG, "root_mode must be 0 or 1");
@@ -783,6 +788,7 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
         p->H.watchdog = o.watchdog_polls;
         p->H.group = o.chunks_per_worker;  // 0: the planner chooses
         p->H.value_type = o.value_type;
+        p->H.max_reg = o.max_reg_slots;
         mpk::build_plan(p->H, n, rowptr, col, val);
         p->L = make_layout(p->H);
     } catch (const std::bad_alloc&) {

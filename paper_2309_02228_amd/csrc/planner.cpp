@@ -221,7 +221,8 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
     }
     // register slots: the smallest supported width covering every chunk, capped
     P.reg_slots = P.max_width <= 4 ? 4 : P.max_width <= 7 ? 7 : P.max_width <= 8 ? 8
-                : P.max_width <= 16 ? 16 : P.max_width <= 32 ? 32 : 48;
+                : P.max_width <= 16 ? 16 : 32;
+    if (P.max_reg > 0) P.reg_slots = std::min(P.reg_slots, P.max_reg);
     // chunks per worker when the caller leaves it open: two (four chunks of
     // FP32 values fit the plain power kernel better, but not the polynomial
     // kernels, and a plan serves both); wide rows leave room for one chunk only

@@ -20,6 +20,7 @@ struct HostPlan {
     int32_t root_mode = 0, root = 0, p_block = 4, workers_req = 0, watchdog = 0;
     int32_t group = 2;  // chunks a worker carries together (G); 0 = chosen by the planner
     int32_t value_type = 0;  // 0: FP64 values on the device, 1: FP32 (rounded at upload)
+    int32_t max_reg = 0;     // cap on register slots (0 = automatic)
 
     // Sec. 3 level structure
     int32_t nlevels = 0;

@@ -40,7 +40,8 @@ class Options(ctypes.Structure):
     _fields_ = [("root_mode", ctypes.c_int32), ("root", ctypes.c_int32),
                 ("p_block", ctypes.c_int32), ("workers_per_xcd", ctypes.c_int32),
                 ("watchdog_polls", ctypes.c_int32), ("chunks_per_worker", ctypes.c_int32),
-                ("value_type", ctypes.c_int32), ("reserved", ctypes.c_int32 * 9)]
+                ("value_type", ctypes.c_int32), ("max_reg_slots", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 8)]
 
 
 def _load():
@@ -124,7 +125,7 @@ class Plan:
     """
 
     def __init__(self, n, rowptr, col, val, root=None, p_block=0, workers_per_xcd=0,
-                 watchdog_polls=0, chunks_per_worker=0, values="f64"):
+                 watchdog_polls=0, chunks_per_worker=0, values="f64", max_reg_slots=0):
         self._h = None
         self.n = int(n)
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
@@ -141,6 +142,7 @@ class Plan:
         if values not in VALUE_TYPES:
             raise ValueError(f"values must be one of {sorted(VALUE_TYPES)}")
         opt.value_type = VALUE_TYPES[values]
+        opt.max_reg_slots = int(max_reg_slots)
         self.values = values
         h = ctypes.c_void_p()
         nbytes = ctypes.c_size_t()

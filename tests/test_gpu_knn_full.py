@@ -1,0 +1,71 @@
+"""Full-size parity for the unstructured workload: 8,000,000 uniform points in
+the unit cube, symmetrised 26-nearest-neighbour graph Laplacian plus 0.1 I (the
+stand-in for the paper's unstructured matrices, about 29.5 nonzeros per row).
+
+It takes about 70 s on the MI355X machine (the k-d tree build and the FP64
+oracle over ~236 M nonzeros dominate); run with -s to see its steps."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+if not torch.cuda.is_available():  # collected on CPU-only hosts, never run there
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_02228_amd import Plan  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-12
+
+
+def say(t0, msg):
+    print(f"[{time.perf_counter() - t0:7.1f} s] {msg}", flush=True)
+
+
+def rel_err(got, ref):
+    return np.linalg.norm(got - ref, axis=-1) / np.linalg.norm(ref, axis=-1)
+
+
+def test_knn_8m_mpk_and_chebyshev_degree8():
+    t0 = time.perf_counter()
+    A = S.knn_graph_laplacian(8_000_000, k=26, seed=0)
+    say(t0, f"matrix: n={A.n} nnz={A.col.size} ({A.col.size / A.n:.2f} per row)")
+    plan = Plan.from_csr(A, p_block=4)
+    lv = plan.levels()
+    say(t0, f"plan: {plan.info()}")
+    level, nl, _ = O.bfs_levels(A)
+    assert lv["nlevels"] == nl and np.array_equal(lv["level_of_row"], level)
+    say(t0, f"levels bit-exact ({nl} levels)")
+    plan.upload(DEV)
+    perm = lv["perm"].astype(np.int64)
+    x = S.uniform_vector(A.n, 0)
+    xd = torch.tensor(x[perm], device=DEV)
+    Yp = plan.apply(xd, 8).cpu().numpy()
+    Yplain = plan.apply(xd, 8, plain=True).cpu().numpy()
+    plan.check()
+    assert np.array_equal(Yp, Yplain)
+    Y = np.empty_like(Yp)
+    Y[:, perm] = Yp
+    del Yp, Yplain
+    say(t0, "GPU MPK p = 8 done (blocked = plain bitwise)")
+    ref = O.mpk(A, x, 8)
+    err = rel_err(Y, ref)
+    say(t0, f"oracle MPK done; rel err per power {err}")
+    assert np.all(err <= TOL)
+    del Y, ref
+    # degree-8 Chebyshev polynomial preconditioner on [0.1, Gershgorin bound] (R12)
+    lmax = 2.0 * np.max(np.diff(A.rowptr)) + 0.1
+    c, theta, delta = O.chebyshev_inverse_coeffs(8, 0.1, lmax)
+    out = plan.poly("chebyshev", c, xd, params=np.array([theta, delta])).cpu().numpy()
+    plan.check()
+    got = np.empty_like(out)
+    got[perm] = out
+    e = rel_err(got, O.poly_chebyshev(A, x, c, theta, delta))
+    say(t0, f"Chebyshev degree 8: rel err {e:.2e}")
+    assert e <= TOL
