@@ -30,6 +30,9 @@ sparse iterative solvers on multi-core CPUs"):
   ``simulate_blocked_mpk``          -- Sec. 3 (an execution order derived
   from the level structure; p_opt and the remainder loop), in the readings
   R5-R7 and R10
+* ``group_levels``, ``wavefront_schedule``, ``validate_schedule``,
+  ``run_schedule``                  -- Sec. 3 (level groups from the cache size
+  and the skewed wavefront over them), readings R14 and R15
 
 Parity status of each function is stated in its docstring.  The readings
 taken where the paper is silent are listed in ``mpk_oracle.READINGS``.

@@ -13,7 +13,8 @@ pinned   spmv, mpk, round_values, chebyshev_inverse_coeffs, refine_solve, newton
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
          hop_min, window_ok, min_workers,
-         simulate_blocked_mpk
+         simulate_blocked_mpk, group_levels, wavefront_schedule,
+         validate_schedule, run_schedule
          (pins: exact integer arithmetic, closed-form Laplacian eigenpairs,
          closed-form grid levels, scipy shortest paths, brute force on tiny
          inputs, special cases; see tests/test_oracle_pins.py)
@@ -75,6 +76,17 @@ READINGS = {
            "r_i = b - A x_i in FP64 with the unrounded matrix; stop when ||r_i|| <= tol "
            "||b||; else x_{i+1} = x_i + s(A~) r_i with s of R12 applied to the matrix "
            "whose values are stored in FP32 (R11).",
+    "R14": "Level groups for a cache of C bytes and q powers (Sec. 3: groups from the "
+           "level structure and the cache size): w(level) = sum over its rows of "
+           "nnz_row * (value bytes + 4) + 4 + 16; budget B = floor(C / q); levels are "
+           "taken in order and a new group starts before level l when the current "
+           "group is non-empty, w(group) + w(l) > B and the group has at least "
+           "min_group_rows rows.",
+    "R15": "Wavefront execution of a block of q powers over groups g = [s_g, e_g], "
+           "g = 0..G-1: task (k, g) computes power k on levels [lo, hi] with "
+           "lo = max(0, s_g - (k - 1)) (0 for g = 0) and hi = e_g - (k - 1) (L - 1 for "
+           "g = G - 1), empty when hi < lo, at stage g + k - 1; stages run in order, "
+           "G + q - 1 of them.",
     "R11": "Reduced-precision matrix storage (the paper works in FP64 only): each stored "
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
@@ -378,6 +390,91 @@ def level_permutation(level, nlevels):
     level_ptr = np.zeros(nlevels + 1, dtype=np.int64)
     np.cumsum(np.bincount(level, minlength=nlevels), out=level_ptr[1:])
     return perm, iperm, level_ptr
+
+
+def group_levels(A, level_ptr, perm, cache_bytes, q, value_bytes=8, min_group_rows=0):
+    """Reading R14.  ``level_ptr`` and ``perm`` from ``level_permutation``; row
+    weights use the original rows' entry counts.  Returns group_ptr (G + 1
+    level indices): group g holds levels group_ptr[g] .. group_ptr[g+1]-1."""
+    n, rowptr, _, _ = _arrays(A)
+    nnz_row = np.diff(rowptr)[np.asarray(perm, dtype=np.int64)]
+    budget = cache_bytes // q
+    L = len(level_ptr) - 1
+    group_ptr = [0]
+    w_group, rows_group = 0, 0
+    for lev in range(L):
+        a, b = int(level_ptr[lev]), int(level_ptr[lev + 1])
+        w = int(nnz_row[a:b].sum()) * (value_bytes + 4) + (b - a) * (4 + 16)
+        if rows_group > 0 and w_group + w > budget and rows_group >= min_group_rows:
+            group_ptr.append(lev)
+            w_group, rows_group = 0, 0
+        w_group += w
+        rows_group += b - a
+    group_ptr.append(L)
+    return np.array(group_ptr, dtype=np.int64)
+
+
+def wavefront_schedule(group_ptr, q):
+    """Reading R15.  Returns the tasks of one block of q powers as a list of
+    (stage, k, level_lo, level_hi), k = 1..q, in stage order (then k), empty
+    tasks left out."""
+    G = len(group_ptr) - 1
+    L = int(group_ptr[-1])
+    tasks = []
+    for stage in range(G + q - 1):
+        for k in range(1, q + 1):
+            g = stage - (k - 1)
+            if not (0 <= g < G):
+                continue
+            lo = 0 if g == 0 else max(0, int(group_ptr[g]) - (k - 1))
+            hi = L - 1 if g == G - 1 else int(group_ptr[g + 1]) - 1 - (k - 1)
+            if hi >= lo:
+                tasks.append((stage, k, lo, hi))
+    return tasks
+
+
+def validate_schedule(B, level_ptr, tasks, q):
+    """Checks a block schedule on the permuted matrix B: every (k, row) is covered
+    exactly once; every read of y_{k-1}[j] (j a column of a row of the task)
+    happens at a stage strictly later than the write of y_{k-1}[j] (k >= 2); a
+    stage has at most one task per k.  Raises AssertionError on a violation."""
+    n, rowptr, col, _ = _arrays(B)
+    written = np.full((q + 1, n), -1, dtype=np.int64)  # stage that wrote y_k[row]
+    written[0, :] = -(1 << 40)                        # y_0 = x exists before the block
+    seen = set()
+    for stage, k, lo, hi in tasks:
+        assert (stage, k) not in seen, f"two tasks for power {k} in stage {stage}"
+        seen.add((stage, k))
+        r0, r1 = int(level_ptr[lo]), int(level_ptr[hi + 1])
+        assert np.all(written[k, r0:r1] == -1), f"rows of power {k} covered twice"
+        cols = col[rowptr[r0]:rowptr[r1]]
+        assert np.all(written[k - 1, cols] < stage) and np.all(written[k - 1, cols] != -1), \
+            f"power {k} in stage {stage} reads y_{k - 1} before it is written"
+        written[k, r0:r1] = stage
+    assert np.all(written[1:] >= 0), "some (power, row) is never computed"
+
+
+def run_schedule(B, x, p, q, level_ptr, tasks_for, kind=None):
+    """Executes p powers on the permuted matrix B block by block (R10), each
+    block as the task list ``tasks_for(qb)`` in stage order, row by row with
+    the row sums of ``spmv_rows``.  ``kind`` as in ``simulate_blocked_mpk``."""
+    n = int(B[0])
+    Y = np.full((p + 1, n), np.nan)
+    Y[0] = np.asarray(x, dtype=np.float64)
+    base = 0
+    while base < p:
+        qb = min(q, p - base)
+        for _, k, lo, hi in tasks_for(qb):
+            gk = base + k
+            r0, r1 = int(level_ptr[lo]), int(level_ptr[hi + 1])
+            acc = spmv_rows(B, Y[gk - 1], r0, r1)
+            if kind is None:
+                Y[gk, r0:r1] = acc
+            else:
+                prev2 = Y[gk - 2, r0:r1] if gk >= 2 else None
+                Y[gk, r0:r1] = kind(gk, acc, Y[gk - 1, r0:r1], prev2)
+        base += qb
+    return Y[1:]
 
 
 def permute_symmetric(A, perm, iperm):

@@ -599,3 +599,83 @@ def test_blocked_schedule_operator_kinds():
                                         else 2.0 * (acc - th * prev) / de - prev2)
     Y = O.simulate_blocked_mpk(B, x, 6, 4, 8, owner, deps, 4, kind=cheb)
     assert np.array_equal(Y, O.chebyshev_basis(B, x, 6, th, de)[1:])
+
+
+# ------------------------------------------ level groups and wavefront (R14, R15)
+def test_group_levels_hand_worked_chain():
+    # 1D chain of 10 rows from root 0: level l = row l; end rows hold 2 entries,
+    # interior rows 3, so w = 2*12+20 = 44 or 3*12+20 = 56 bytes.  C = 1000, q = 4
+    # gives B = 250: 44+56+56+56 = 212, +56 = 268 > 250 -> cut before level 4;
+    # 4*56 = 224, +56 = 280 > 250 -> cut before level 8; 56+44 = 100.
+    A = S.laplacian_1d(10)
+    level, nl, _ = O.bfs_levels(A, 0)
+    perm, iperm, lp = O.level_permutation(level, nl)
+    assert list(O.group_levels(A, lp, perm, 1000, 4)) == [0, 4, 8, 10]
+    # a floor of 5 rows per group keeps level 4 in group 0 (268 bytes, 5 rows) and
+    # cuts before level 5; group 1 reaches 224 bytes at level 8 but holds only 4
+    # rows when level 9 would overflow it, so it runs to the end
+    assert list(O.group_levels(A, lp, perm, 1000, 4, min_group_rows=5)) == [0, 5, 10]
+    # one group when everything fits; one level per group when nothing does
+    assert list(O.group_levels(A, lp, perm, 10 ** 6, 4)) == [0, 10]
+    assert list(O.group_levels(A, lp, perm, 4, 4)) == list(range(11))
+
+
+def test_wavefront_schedule_hand_worked():
+    # groups [0,3], [4,7], [8,9] over L = 10 levels, q = 2 (R15)
+    tasks = O.wavefront_schedule(np.array([0, 4, 8, 10]), 2)
+    assert tasks == [(0, 1, 0, 3), (1, 1, 4, 7), (1, 2, 0, 2), (2, 1, 8, 9), (2, 2, 3, 6), (3, 2, 7, 9)]
+
+
+SCHED_CASES = {
+    "lap3d": lambda: S.laplacian_3d(14, 11, 9),
+    "lap2d": lambda: S.laplacian_2d(40, 31),
+    "rand_nonsym": lambda: S.random_pattern(1500, 4, 5),
+    "disconnected": lambda: S.block_diagonal(S.laplacian_2d(9, 8), S.identity(30), S.laplacian_1d(90)),
+    "knn": lambda: S.knn_graph_laplacian(1200, k=26, seed=3),
+}
+
+
+def _sched_setup(A):
+    level, nl, _ = O.bfs_levels(A)
+    perm, iperm, lp = O.level_permutation(level, nl)
+    return O.permute_symmetric(A, perm, iperm), perm, lp
+
+
+@pytest.mark.parametrize("name", sorted(SCHED_CASES))
+@pytest.mark.parametrize("cache,q", [(20_000, 2), (60_000, 4), (5_000, 5), (10 ** 9, 3)])
+def test_schedule_valid_and_equal_to_plain(name, cache, q):
+    # P5: coverage, read-after-write order, one task per k per stage, G + q - 1
+    # stages; executing it gives the plain MPK bitwise
+    A = SCHED_CASES[name]()
+    B, perm, lp = _sched_setup(A)
+    gp = O.group_levels(A, lp, perm, cache, q)
+    tasks = O.wavefront_schedule(gp, q)
+    O.validate_schedule(B, lp, tasks, q)
+    assert max(t[0] for t in tasks) <= len(gp) - 1 + q - 1
+    x = S.uniform_vector(A.n, 1)
+    p = 2 * q + 1  # two full blocks and a remainder
+    got = O.run_schedule(B, x, p, q, lp, lambda qb: O.wavefront_schedule(gp, qb))
+    assert np.array_equal(got, O.mpk(B, x, p))
+
+
+def test_schedule_validator_catches_planted_mistakes():
+    # mistakes planted in the oracle's own schedule must be rejected
+    A = S.laplacian_2d(30, 20)
+    B, perm, lp = _sched_setup(A)
+    gp = O.group_levels(A, lp, perm, 8_000, 3)
+    assert len(gp) > 4
+    tasks = O.wavefront_schedule(gp, 3)
+    # 1) run power 2 of group 1 one stage early (before its inputs exist)
+    bad = [(s - 1, k, lo, hi) if (k == 2 and s == 2) else (s, k, lo, hi) for s, k, lo, hi in tasks]
+    with pytest.raises(AssertionError):
+        O.validate_schedule(B, lp, bad, 3)
+    # 2) forget the shift by k - 1 levels (reads the next group's fresh rows)
+    L = int(gp[-1])
+    G = len(gp) - 1
+    noshift = [(g + k - 1, k, int(gp[g]), L - 1 if g == G - 1 else int(gp[g + 1]) - 1)
+               for g in range(G) for k in range(1, 4)]
+    with pytest.raises(AssertionError):
+        O.validate_schedule(B, lp, sorted(noshift), 3)
+    # 3) drop a task (rows never computed)
+    with pytest.raises(AssertionError):
+        O.validate_schedule(B, lp, tasks[:-1], 3)
