@@ -150,6 +150,17 @@ def main():
         per = np.array([evs[k].elapsed_time(evs[k + 1]) for k in range(args.steps)]) * 1e-3
         return wall, per
 
+    def timed_staged():
+        for _ in range(args.warmup):
+            plan.apply(xd, p, Y=Y, staged=True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        for _ in range(args.steps):
+            plan.apply(xd, p, Y=Y, staged=True)
+        torch.cuda.synchronize()
+        plan.check()
+        return time.perf_counter() - t_start, None
+
     res = {}
     if args.only in ("both", "blocked"):
         wall_b, per_b = timed(False)
@@ -206,12 +217,25 @@ def main():
         "plan_build_s": round(t_plan, 3),
         "plan_upload_s": round(t_upload, 3),
     }
+    if args.only == "both":
+        # the paper's level-group wavefront (one launch per stage) for comparison
+        wall_s, _ = timed_staged()
+        ng, tasks = plan.schedule(info["p_block"])
+        res_staged = {"gflops": round(flops * args.steps / wall_s / 1e9, 2),
+                      "ms_per_step": round(wall_s / args.steps * 1e3, 5),
+                      "groups": ng, "stages_per_block": int(tasks[:, 0].max()) + 1 if len(tasks) else 0,
+                      "cache_mib": 256,
+                      "note": "level groups under floor(C/q) bytes, task (k, g) at stage g + k - 1; "
+                              "one launch per stage"}
+        log(f"staged:  {wall_s / args.steps * 1e6:.1f} us/step ({ng} groups)")
     if "plain" in res and "blocked" in res:
         wp = res["plain"][0]
         out["plain_gflops"] = round(flops * args.steps / wp / 1e9, 2)
         out["speedup_vs_plain"] = round(wp / res["blocked"][0], 3)
         out["plan_build_spmv_equivalents"] = round(t_plan / (wp / args.steps / p), 1)
         out["roofline_equivalent_frac"] = round(value / (flops / (b_blk / (HBM_PEAK_GBS * 1e9)) / 1e9), 4)
+    if args.only == "both":
+        out["staged_wavefront"] = res_staged
     if not args.no_f32 and args.only == "both":
         # FP32 storage of the matrix values (vectors, products and sums stay FP64)
         # four chunks per wave: FP32 values leave registers for them (measured faster

@@ -57,6 +57,9 @@ typedef enum {
 #define MPK_IO_PERMUTED 1u /* x and outputs are in the plan's level order (perm space) */
 #define MPK_PLAIN 2u       /* comparator: one full SpMV launch per power (Alg. 1),
                               same layout and same per-row arithmetic            */
+#define MPK_STAGED 4u      /* the level-group wavefront of Sec. 3 (see
+                              mpk_get_schedule): one launch per stage, same
+                              per-row arithmetic; ignored with MPK_PLAIN       */
 
 /* polynomial kinds for poly_apply */
 #define MPK_POLY_MONOMIAL 0  /* phi_k = A^k                                     */
@@ -106,7 +109,13 @@ typedef struct {
                                 covering the widest chunk, 32 at most).  Slots
                                 beyond it are re-read from memory at every
                                 power.                                        */
-    int32_t reserved[8];     /* must be zero                                  */
+    int32_t cache_mib;       /* C of the level groups used by mpk_get_schedule
+                                and MPK_STAGED, in MiB (0 = 256, the MI355X
+                                Infinity Cache, the closest analogue of the
+                                last-level cache the paper blocks for)        */
+    int32_t min_group_rows;  /* row floor below which a level group is never
+                                closed (>= 0)                                 */
+    int32_t reserved[6];     /* must be zero                                  */
 } mpk_options;
 
 /* Fills *opt with the defaults (all zero). */
@@ -253,6 +262,24 @@ mpk_status poly_apply(mpk_plan_t plan, int32_t kind, int32_t d, const double* c,
  * `work`.  Errors: MPK_ERR_ARG (s < 1, ldv < n, zero sigma, null pointers,
  * work too small), MPK_ERR_STATE, MPK_ERR_HIP.
  */
+/*
+ * Level groups and wavefront schedule of one block of q powers (Sec. 3: an
+ * execution order from the level structure and the cache size):
+ *   levels are grouped greedily and contiguously: a group is closed before
+ *   level l when it is non-empty, has at least min_group_rows rows and
+ *   w(group) + w(l) > floor(C / q), with w(level) = sum over its rows of
+ *   nnz_row * (value bytes + 4) + 20;
+ *   task (k, g), k = 1..q, computes power k on the levels of group g shifted
+ *   down by k - 1 (from level 0 for g = 0, to the last level for the last
+ *   group) and runs at stage g + k - 1; a stage's tasks are independent.
+ * On return *ntasks holds the number of non-empty tasks and *ngroups the
+ * number of groups; if `tasks` is not NULL it receives 4 ints per task,
+ * {stage, k, row_begin, row_end} (permuted rows, end exclusive), in stage
+ * order, then k.  q must be in 1..15.  Host only; no upload needed.
+ * Errors: MPK_ERR_ARG (null plan or counts, q out of range).
+ */
+mpk_status mpk_get_schedule(mpk_plan_t plan, int32_t q, int32_t* ntasks, int32_t* ngroups, int32_t* tasks);
+
 /*
  * Solve A x = b by FP64 iterative refinement around the degree-d Chebyshev
  * polynomial preconditioner (the polynomial preconditioner of Sec. 5; the

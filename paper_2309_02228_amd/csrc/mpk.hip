@@ -393,6 +393,56 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
     }
 }
 
+// ---- staged kernel: one stage of the level-group wavefront ------------------
+// A stage holds at most q tasks (one per power of the block), each a range of
+// permuted rows.  Waves stride over the chunks that cover all the tasks' rows;
+// every lane computes its row sum, and only rows inside the task are stored.
+struct StageTaskDev {
+    const double* in;     // y_{gk-1}
+    const double* prev2;  // y_{gk-2} (Chebyshev), null for gk < 2
+    double* out;          // y_gk
+    int c0, nchunks;      // chunks covering rows [r0, r1)
+    int r0, r1;
+    int gk, kl;           // global power; its index in the coefficient arrays
+};
+
+struct StageArgs {
+    DevPlan P;
+    StageTaskDev t[kMaxQ];
+    int ntasks;
+    double* acc;  // polynomial accumulator, updated in place (null: none)
+    double c0;
+    Coefs C;
+};
+
+template <int KIND, bool POLY, typename VT>
+__global__ __launch_bounds__(kBlockThreads) void stage_kernel(StageArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int W = gridDim.x * kWaves;
+    int total = 0;
+    for (int t = 0; t < a.ntasks; ++t) total += a.t[t].nchunks;
+    for (int i = blockIdx.x * kWaves + (threadIdx.x >> 6); i < total; i += W) {
+        int t = 0, first = 0;
+        while (i >= first + a.t[t].nchunks) first += a.t[t++].nchunks;
+        const StageTaskDev& T = a.t[t];
+        const int c = T.c0 + (i - first);
+        const int row = c * kChunkRows + lane;
+        const int64_t off = a.P.off[c];
+        const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
+        const double s = row_sum_mem<VT>(a.P, T.in, off, width, lane);
+        if (row >= T.r0 && row < T.r1) {
+            const double prev = (KIND != KIND_MONO || POLY) ? T.in[row] : 0.0;
+            const double prev2 = (KIND == KIND_CHEB && T.prev2) ? T.prev2[row] : 0.0;
+            const double y = finish<KIND>(s, prev, prev2, T.gk, T.kl, a.C);
+            T.out[row] = y;
+            if (POLY) {
+                const double acc = T.gk == 1 ? a.c0 * prev : a.acc[row];
+                a.acc[row] = fma(a.C.c[T.kl], y, acc);
+            }
+        }
+    }
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -547,6 +597,8 @@ struct mpk_plan_s {
     int grid_block[3][2] = {};
     int q_eff[3][2] = {};    // powers per launch meeting the deadlock bound
     int grid_spmv = 0;       // workgroups of a plain launch
+    int cus = 0;             // compute units of the device the plan was uploaded on
+    std::vector<std::vector<mpk::StageTask>> sched;  // wavefront schedule per q (lazy)
 };
 
 namespace {
@@ -596,6 +648,19 @@ SpmvFn pick_spmv_vt(int kind, bool poly) {
     if (kind == KIND_MONO) return poly ? spmv_kernel<KIND_MONO, true, VT> : spmv_kernel<KIND_MONO, false, VT>;
     if (kind == KIND_NEWTON) return poly ? spmv_kernel<KIND_NEWTON, true, VT> : spmv_kernel<KIND_NEWTON, false, VT>;
     return poly ? spmv_kernel<KIND_CHEB, true, VT> : spmv_kernel<KIND_CHEB, false, VT>;
+}
+
+using StageFn = void (*)(StageArgs);
+template <typename VT>
+StageFn pick_stage_vt(int kind, bool poly) {
+    if (kind == KIND_MONO) return poly ? stage_kernel<KIND_MONO, true, VT> : stage_kernel<KIND_MONO, false, VT>;
+    if (kind == KIND_NEWTON)
+        return poly ? stage_kernel<KIND_NEWTON, true, VT> : stage_kernel<KIND_NEWTON, false, VT>;
+    return poly ? stage_kernel<KIND_CHEB, true, VT> : stage_kernel<KIND_CHEB, false, VT>;
+}
+
+StageFn pick_stage(const mpk::HostPlan& H, int kind, bool poly) {
+    return H.value_type == 1 ? pick_stage_vt<float>(kind, poly) : pick_stage_vt<double>(kind, poly);
 }
 
 SpmvFn pick_spmv(const mpk::HostPlan& H, int kind, bool poly) {
@@ -672,9 +737,60 @@ struct PowerJob {
 double* job_dest(const PowerJob& j, int k) { return j.out0 + (int64_t)((k - 1) % j.mod) * j.ld; }
 const double* job_vec(const PowerJob& j, int k) { return k == 0 ? j.x : job_dest(j, k); }
 
-mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plain) {
+const std::vector<mpk::StageTask>& schedule(mpk_plan_t p, int q) {
+    if (p->sched.size() <= (size_t)q) p->sched.resize(q + 1);
+    if (p->sched[q].empty()) p->sched[q] = mpk::wavefront_schedule(p->H, q);
+    return p->sched[q];
+}
+
+// The level-group wavefront (readings R14, R15): blocks of q powers, each as
+// G + q - 1 stage launches.
+mpk_status run_staged(mpk_plan_t p, hipStream_t st, const PowerJob& j) {
+    if (j.copy0) HIP_TRY(hipMemcpyAsync(j.copy0, j.x, sizeof(double) * p->H.n, hipMemcpyDeviceToDevice, st));
+    const StageFn fn = pick_stage(p->H, j.kind, j.poly);
+    for (int base = 0; base < j.p; base += p->H.p_block) {
+        const int qb = std::min(p->H.p_block, j.p - base);
+        const auto& tasks = schedule(p, qb);
+        for (size_t t0 = 0; t0 < tasks.size();) {
+            StageArgs a{};
+            a.P = p->D;
+            a.acc = j.poly ? j.acc : nullptr;
+            a.c0 = j.poly ? j.c[0] : 0.0;
+            a.C.theta = j.theta;
+            a.C.delta = j.delta;
+            int total = 0;
+            size_t t1 = t0;
+            for (; t1 < tasks.size() && tasks[t1].stage == tasks[t0].stage; ++t1) {
+                const auto& T = tasks[t1];
+                const int gk = base + T.k, kl = T.k - 1;
+                StageTaskDev& d = a.t[a.ntasks++];
+                d.in = job_vec(j, gk - 1);
+                d.prev2 = (j.kind == KIND_CHEB && gk >= 2) ? job_vec(j, gk - 2) : nullptr;
+                d.out = job_dest(j, gk);
+                d.r0 = T.row_begin;
+                d.r1 = T.row_end;
+                d.c0 = T.row_begin / kChunkRows;
+                d.nchunks = (T.row_end - 1) / kChunkRows - d.c0 + 1;
+                d.gk = gk;
+                d.kl = kl;
+                a.C.lam[kl] = j.lam.empty() ? 0.0 : j.lam[gk - 1];
+                a.C.sig[kl] = j.sig.empty() ? 1.0 : j.sig[gk - 1];
+                a.C.c[kl] = j.poly ? j.c[gk] : 0.0;
+                total += d.nchunks;
+            }
+            const int grid = std::max(1, std::min(p->cus * 32, (total + kWaves - 1) / kWaves));
+            hipLaunchKernelGGL(fn, dim3(grid), dim3(kBlockThreads), 0, st, a);
+            HIP_TRY(hipGetLastError());
+            t0 = t1;
+        }
+    }
+    return MPK_OK;
+}
+
+mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plain, bool staged = false) {
     if (j.p == 0) return MPK_OK;
     if (p->H.n == 0) return MPK_OK;
+    if (staged && !plain) return run_staged(p, st, j);
     // When the deadlock bound admits only one power per launch (levels too wide
     // for the resident waves), blocking cannot reuse the matrix and the plain
     // kernel is faster; both give bitwise-equal results.
@@ -761,8 +877,10 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
     if (n > 0 && rowptr[n] > 0 && (!col || !val)) return fail(MPK_ERR_ARG, "col or val is null");
     mpk_options o{};
     if (opt) o = *opt;
-    for (int i = 0; i < 8; ++i)
+    for (int i = 0; i < 6; ++i)
         if (o.reserved[i] != 0) return fail(MPK_ERR_ARG, "mpk_options.reserved must be zero");
+    if (o.cache_mib < 0) return fail(MPK_ERR_ARG, "cache_mib must be >= 0");
+    if (o.min_group_rows < 0) return fail(MPK_ERR_ARG, "min_group_rows must be >= 0");
     if (o.max_reg_slots != 0 && o.max_reg_slots != 4 && o.max_reg_slots != 7 && o.max_reg_slots != 8 &&
         o.max_reg_slots != 16 && o.max_reg_slots != 32)
         return fail(MPK_ERR_ARG, "max_reg_slots must be 0, 4, 7, 8, 16 or 32");
@@ -789,6 +907,8 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
         p->H.group = o.chunks_per_worker;  // 0: the planner chooses
         p->H.value_type = o.value_type;
         p->H.max_reg = o.max_reg_slots;
+        p->H.cache_bytes = (int64_t)(o.cache_mib ? o.cache_mib : 256) << 20;
+        p->H.min_group_rows = o.min_group_rows;
         mpk::build_plan(p->H, n, rowptr, col, val);
         p->L = make_layout(p->H);
     } catch (const std::bad_alloc&) {
@@ -946,6 +1066,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     // plain launches: up to 32 workgroups per CU (128 waves), a few chunks per
     // wave; this measured faster than 8 per CU at the 160^3 Laplacian
     p->grid_spmv = std::max(1, std::min(cus * 32, (H.nchunks + kWaves - 1) / kWaves));
+    p->cus = cus;
     return MPK_OK;
 }
 
@@ -970,7 +1091,7 @@ MPK_API mpk_status mpk_apply(mpk_plan_t p, const double* x, double* Y, int64_t l
     if (pw < 1) return fail(MPK_ERR_ARG, "p must be >= 1 (got %d)", pw);
     if (ldy < p->H.n) return fail(MPK_ERR_ARG, "ldy (%lld) < n (%d)", (long long)ldy, p->H.n);
     if (p->H.n > 0 && (!x || !Y)) return fail(MPK_ERR_ARG, "x or Y is null");
-    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return fail(MPK_ERR_ARG, "unknown flag bits");
     size_t need = 0;
     mpk_work_bytes(p, MPK_CALL_APPLY, pw, flags, &need);
     if (need > 0 && (!work || work_bytes < need))
@@ -993,7 +1114,7 @@ MPK_API mpk_status mpk_apply(mpk_plan_t p, const double* x, double* Y, int64_t l
         j.out0 = xw + p->H.n;
         j.ld = p->H.n;
     }
-    s = run_powers(p, st, j, flags & MPK_PLAIN);
+    s = run_powers(p, st, j, flags & MPK_PLAIN, flags & MPK_STAGED);
     if (s != MPK_OK) return s;
     if (!permuted) s = permute_vecs(p, st, j.out0, p->H.n, Y, ldy, pw, 1);
     return s;
@@ -1010,7 +1131,7 @@ MPK_API mpk_status poly_apply(mpk_plan_t p, int32_t kind, int32_t d, const doubl
     if (kind == MPK_POLY_CHEBYSHEV && d > 0 && params[1] == 0.0) return fail(MPK_ERR_ARG, "delta must be nonzero");
     if (p->H.n > 0 && (!x || !out)) return fail(MPK_ERR_ARG, "x or out is null");
     if (x == out && p->H.n > 0) return fail(MPK_ERR_ARG, "out must not alias x");
-    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return fail(MPK_ERR_ARG, "unknown flag bits");
     size_t need = 0;
     mpk_work_bytes(p, MPK_CALL_POLY, d, flags, &need);
     if (!work || work_bytes < need)
@@ -1050,11 +1171,27 @@ MPK_API mpk_status poly_apply(mpk_plan_t p, int32_t kind, int32_t d, const doubl
             j.theta = params[0];
             j.delta = params[1];
         }
-        s = run_powers(p, st, j, flags & MPK_PLAIN);
+        s = run_powers(p, st, j, flags & MPK_PLAIN, flags & MPK_STAGED);
         if (s != MPK_OK) return s;
     }
     if (!permuted) s = permute_vecs(p, st, acc, 0, out, 0, 1, 1);
     return s;
+}
+
+MPK_API mpk_status mpk_get_schedule(mpk_plan_t p, int32_t q, int32_t* ntasks, int32_t* ngroups, int32_t* tasks) {
+    if (!p || !ntasks || !ngroups) return fail(MPK_ERR_ARG, "null argument");
+    if (q < 1 || q > mpk::kMaxBlock) return fail(MPK_ERR_ARG, "q must be in 1..%d", mpk::kMaxBlock);
+    const auto& T = schedule(p, q);
+    *ntasks = (int32_t)T.size();
+    *ngroups = (int32_t)mpk::group_levels(p->H, q).size() - 1;
+    if (tasks)
+        for (size_t i = 0; i < T.size(); ++i) {
+            tasks[4 * i + 0] = T[i].stage;
+            tasks[4 * i + 1] = T[i].k;
+            tasks[4 * i + 2] = T[i].row_begin;
+            tasks[4 * i + 3] = T[i].row_end;
+        }
+    return MPK_OK;
 }
 
 MPK_API mpk_status mpk_refine_solve(mpk_plan_t hi, mpk_plan_t lo, int32_t degree, double lmin, double lmax,
@@ -1071,7 +1208,7 @@ MPK_API mpk_status mpk_refine_solve(mpk_plan_t hi, mpk_plan_t lo, int32_t degree
     if (!(lmin > 0.0) || !(lmax > lmin)) return fail(MPK_ERR_ARG, "need 0 < lmin < lmax");
     if (!(tol >= 0.0)) return fail(MPK_ERR_ARG, "tol must be >= 0");
     if (max_iter < 0) return fail(MPK_ERR_ARG, "max_iter must be >= 0");
-    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return fail(MPK_ERR_ARG, "unknown flag bits");
     const int32_t n = hi->H.n;
     if (n > 0 && (!b || !x)) return fail(MPK_ERR_ARG, "b or x is null");
     size_t need = 0;
@@ -1152,7 +1289,7 @@ MPK_API mpk_status mpk_refine_solve(mpk_plan_t hi, mpk_plan_t lo, int32_t degree
             j.c = coef;
             j.theta = theta;
             j.delta = delta;
-            s = run_powers(lo, st, j, flags & MPK_PLAIN);
+            s = run_powers(lo, st, j, flags & MPK_PLAIN, flags & MPK_STAGED);
             if (s != MPK_OK) return s;
         }
         axpy_kernel<<<grid_1d(n), 256, 0, st>>>(xp, z, n);
@@ -1178,7 +1315,7 @@ MPK_API mpk_status sstep_basis(mpk_plan_t p, int32_t sdeg, const double* lambda,
         for (int k = 0; k < sdeg; ++k)
             if (sigma[k] == 0.0) return fail(MPK_ERR_ARG, "sigma[%d] is zero", k);
     if (p->H.n > 0 && (!v || !V)) return fail(MPK_ERR_ARG, "v or V is null");
-    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return fail(MPK_ERR_ARG, "unknown flag bits");
     size_t need = 0;
     mpk_work_bytes(p, MPK_CALL_SSTEP, sdeg, flags, &need);
     if (need > 0 && (!work || work_bytes < need))
@@ -1208,7 +1345,7 @@ MPK_API mpk_status sstep_basis(mpk_plan_t p, int32_t sdeg, const double* lambda,
     }
     j.out0 = Vp + ld;
     j.ld = ld;
-    s = run_powers(p, st, j, flags & MPK_PLAIN);
+    s = run_powers(p, st, j, flags & MPK_PLAIN, flags & MPK_STAGED);
     if (s != MPK_OK) return s;
     if (!permuted) s = permute_vecs(p, st, Vp, ld, V, ldv, sdeg + 1, 1);
     return s;

@@ -173,6 +173,8 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
     P.level_ptr.assign(P.nlevels + 1, 0);
     for (int32_t i = 0; i < n; ++i) ++P.level_ptr[P.level_of_row[i] + 1];
     for (int32_t l = 0; l < P.nlevels; ++l) P.level_ptr[l + 1] += P.level_ptr[l];
+    P.level_nnz.assign(P.nlevels, 0);
+    for (int32_t i = 0; i < n; ++i) P.level_nnz[P.level_of_row[i]] += rowptr[i + 1] - rowptr[i];
     P.perm.assign(n, 0);
     P.iperm.assign(n, 0);
     {
@@ -356,6 +358,43 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
         }
         P.min_workers[q] = need;
     }
+}
+
+std::vector<int32_t> group_levels(const HostPlan& P, int32_t q) {
+    // greedy and contiguous under the budget floor(C / q) (R14)
+    const int64_t budget = P.cache_bytes / std::max(1, q);
+    const int64_t vbytes = P.value_type == 1 ? 4 : 8;
+    std::vector<int32_t> gp{0};
+    int64_t w_group = 0, rows_group = 0;
+    for (int32_t l = 0; l < P.nlevels; ++l) {
+        const int64_t rows = P.level_ptr[l + 1] - P.level_ptr[l];
+        const int64_t w = P.level_nnz[l] * (vbytes + 4) + rows * (4 + 16);
+        if (rows_group > 0 && w_group + w > budget && rows_group >= P.min_group_rows) {
+            gp.push_back(l);
+            w_group = rows_group = 0;
+        }
+        w_group += w;
+        rows_group += rows;
+    }
+    gp.push_back(P.nlevels);
+    return gp;
+}
+
+std::vector<StageTask> wavefront_schedule(const HostPlan& P, int32_t q) {
+    // task (k, g) on levels shifted down by k - 1, at stage g + k - 1 (R15)
+    const std::vector<int32_t> gp = group_levels(P, q);
+    const int32_t G = (int32_t)gp.size() - 1, L = P.nlevels;
+    std::vector<StageTask> tasks;
+    for (int32_t stage = 0; stage < G + q - 1; ++stage)
+        for (int32_t k = 1; k <= q; ++k) {
+            const int32_t g = stage - (k - 1);
+            if (g < 0 || g >= G) continue;
+            const int32_t lo = g == 0 ? 0 : std::max(0, gp[g] - (k - 1));
+            const int32_t hi = g == G - 1 ? L - 1 : gp[g + 1] - 1 - (k - 1);
+            if (hi < lo) continue;
+            tasks.push_back({stage, k, P.level_ptr[lo], P.level_ptr[hi + 1]});
+        }
+    return tasks;
 }
 
 }  // namespace mpk

@@ -21,6 +21,8 @@ struct HostPlan {
     int32_t group = 2;  // chunks a worker carries together (G); 0 = chosen by the planner
     int32_t value_type = 0;  // 0: FP64 values on the device, 1: FP32 (rounded at upload)
     int32_t max_reg = 0;     // cap on register slots (0 = automatic)
+    int64_t cache_bytes = 256ll << 20;  // C of the level groups (R14)
+    int32_t min_group_rows = 0;         // row floor of a level group (R14)
 
     // Sec. 3 level structure
     int32_t nlevels = 0;
@@ -28,6 +30,7 @@ struct HostPlan {
     std::vector<int32_t> level_of_row;  // n, by original row
     std::vector<int32_t> perm, iperm;   // perm[new] = old, iperm[old] = new
     std::vector<int32_t> roots;         // BFS root of each component
+    std::vector<int64_t> level_nnz;     // nlevels: stored entries of each level's rows
 
     // SELL-64 layout of P A P^T
     int32_t nchunks = 0;
@@ -52,6 +55,19 @@ struct HostPlan {
     std::vector<int32_t> min_workers;    // index q = 0..p_block (entry 0 unused), in units
                                          // of G chunks per worker
 };
+
+// One task of the wavefront schedule (R15): power k (1..q) of a block on the
+// permuted rows [row_begin, row_end), run at `stage`.
+struct StageTask {
+    int32_t stage, k, row_begin, row_end;
+};
+
+// Level groups under floor(C / q) bytes (R14): group g holds levels
+// group_ptr[g] .. group_ptr[g + 1] - 1.
+std::vector<int32_t> group_levels(const HostPlan& P, int32_t q);
+
+// The tasks of one block of q powers in stage order, then k (R15).
+std::vector<StageTask> wavefront_schedule(const HostPlan& P, int32_t q);
 
 // Validates the CSR input; returns an empty string or an error message.
 std::string validate_csr(int32_t n, const int32_t* rowptr, const int32_t* col);

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(_HERE, "libmpk.so")
 
 MPK_IO_PERMUTED = 1
 MPK_PLAIN = 2
+MPK_STAGED = 4
 VALUE_TYPES = {"f64": 0, "f32": 1}
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
 CALL_APPLY, CALL_POLY, CALL_SSTEP, CALL_SOLVE = 0, 1, 2, 3
@@ -27,6 +28,7 @@ STATUS = {0: "MPK_OK", -1: "MPK_ERR_ARG", -2: "MPK_ERR_CSR", -3: "MPK_ERR_NOMEM"
 EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_levels",
            "mpk_get_levels", "mpk_get_partition", "mpk_get_deps", "mpk_min_workers",
            "mpk_upload", "mpk_work_bytes", "mpk_apply", "poly_apply", "sstep_basis", "mpk_refine_solve",
+           "mpk_get_schedule",
            "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy"]
 
 
@@ -41,7 +43,8 @@ class Options(ctypes.Structure):
                 ("p_block", ctypes.c_int32), ("workers_per_xcd", ctypes.c_int32),
                 ("watchdog_polls", ctypes.c_int32), ("chunks_per_worker", ctypes.c_int32),
                 ("value_type", ctypes.c_int32), ("max_reg_slots", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 8)]
+                ("cache_mib", ctypes.c_int32), ("min_group_rows", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 6)]
 
 
 def _load():
@@ -73,6 +76,7 @@ def _load():
         "mpk_apply": (I32, [P, D, D, I64, I32, U32, P, SZ, P]),
         "poly_apply": (I32, [P, I32, I32, P, P, D, D, U32, P, SZ, P]),
         "sstep_basis": (I32, [P, I32, P, P, D, D, I64, U32, P, SZ, P]),
+        "mpk_get_schedule": (I32, [P, I32, pI32, pI32, P]),
         "mpk_refine_solve": (I32, [P, P, I32, ctypes.c_double, ctypes.c_double, D, D, ctypes.c_double, I32,
                                    U32, P, SZ, pI32, ctypes.POINTER(ctypes.c_double), P]),
         "mpk_permute": (I32, [P, D, D, I32, P]),
@@ -125,7 +129,8 @@ class Plan:
     """
 
     def __init__(self, n, rowptr, col, val, root=None, p_block=0, workers_per_xcd=0,
-                 watchdog_polls=0, chunks_per_worker=0, values="f64", max_reg_slots=0):
+                 watchdog_polls=0, chunks_per_worker=0, values="f64", max_reg_slots=0, cache_mib=0,
+                 min_group_rows=0):
         self._h = None
         self.n = int(n)
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
@@ -143,6 +148,8 @@ class Plan:
             raise ValueError(f"values must be one of {sorted(VALUE_TYPES)}")
         opt.value_type = VALUE_TYPES[values]
         opt.max_reg_slots = int(max_reg_slots)
+        opt.cache_mib = int(cache_mib)
+        opt.min_group_rows = int(min_group_rows)
         self.values = values
         h = ctypes.c_void_p()
         nbytes = ctypes.c_size_t()
@@ -186,6 +193,15 @@ class Plan:
         _check(_lib.mpk_get_deps(self._h, ctypes.byref(nd), _ptr(ptr), _ptr(idx)))
         return ptr, idx[:nd.value]
 
+    def schedule(self, q):
+        """Level-group wavefront of one block of q powers: (ngroups, tasks) with tasks an
+        (ntasks, 4) array of {stage, k, row_begin, row_end} in permuted rows."""
+        nt, ng = ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.mpk_get_schedule(self._h, int(q), ctypes.byref(nt), ctypes.byref(ng), None))
+        t = np.empty((max(1, nt.value), 4), np.int32)
+        _check(_lib.mpk_get_schedule(self._h, int(q), ctypes.byref(nt), ctypes.byref(ng), _ptr(t)))
+        return ng.value, t[:nt.value]
+
     def min_workers(self, q):
         w = ctypes.c_int32()
         _check(_lib.mpk_min_workers(self._h, int(q), ctypes.byref(w)))
@@ -222,36 +238,36 @@ class Plan:
         return w, nb
 
     @staticmethod
-    def _flags(permuted, plain):
-        return (MPK_IO_PERMUTED if permuted else 0) | (MPK_PLAIN if plain else 0)
+    def _flags(permuted, plain, staged=False):
+        return (MPK_IO_PERMUTED if permuted else 0) | (MPK_PLAIN if plain else 0) | (MPK_STAGED if staged else 0)
 
-    def apply(self, x, p, Y=None, permuted=True, plain=False, stream=None):
+    def apply(self, x, p, Y=None, permuted=True, plain=False, stream=None, staged=False):
         """Y[k-1] = A^k x for k = 1..p (a (p, n) float64 tensor)."""
         import torch
         if Y is None:
             Y = torch.empty((p, self.n), dtype=torch.float64, device=x.device)
-        flags = self._flags(permuted, plain)
+        flags = self._flags(permuted, plain, staged)
         w, nb = self._work(CALL_APPLY, p, flags, x.device)
         ldy = Y.stride(0) if Y.dim() == 2 else self.n
         _check(_lib.mpk_apply(self._h, _dptr(x), _dptr(Y), ldy, int(p), flags, _dptr(w), nb,
                               _stream(stream)))
         return Y
 
-    def poly(self, kind, c, x, params=None, out=None, permuted=True, plain=False, stream=None):
+    def poly(self, kind, c, x, params=None, out=None, permuted=True, plain=False, stream=None, staged=False):
         """out = sum_k c[k] phi_k(A) x (kind: monomial, newton, chebyshev)."""
         import torch
         c = np.ascontiguousarray(c, dtype=np.float64)
         pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
         if out is None:
             out = torch.empty(self.n, dtype=torch.float64, device=x.device)
-        flags = self._flags(permuted, plain)
+        flags = self._flags(permuted, plain, staged)
         d = c.size - 1
         w, nb = self._work(CALL_POLY, d, flags, x.device)
         _check(_lib.poly_apply(self._h, POLY_KINDS[kind], d, _ptr(c), _ptr(pr), _dptr(x), _dptr(out),
                                flags, _dptr(w), nb, _stream(stream)))
         return out
 
-    def sstep(self, v, lambdas, sigmas=None, V=None, permuted=True, plain=False, stream=None):
+    def sstep(self, v, lambdas, sigmas=None, V=None, permuted=True, plain=False, stream=None, staged=False):
         """(s+1, n) Newton basis: V[0] = v, V[k] = (A - lambda_k I) V[k-1] / sigma_k."""
         import torch
         lam = np.ascontiguousarray(lambdas, dtype=np.float64)
@@ -259,21 +275,21 @@ class Plan:
         s = lam.size
         if V is None:
             V = torch.empty((s + 1, self.n), dtype=torch.float64, device=v.device)
-        flags = self._flags(permuted, plain)
+        flags = self._flags(permuted, plain, staged)
         w, nb = self._work(CALL_SSTEP, s, flags, v.device)
         _check(_lib.sstep_basis(self._h, s, _ptr(lam), _ptr(sig), _dptr(v), _dptr(V), V.stride(0),
                                 flags, _dptr(w), nb, _stream(stream)))
         return V
 
     def refine_solve(self, lo, b, degree, lmin, lmax, tol=1e-10, max_iter=1000, x=None, permuted=True,
-                     plain=False, stream=None):
+                     plain=False, stream=None, staged=False):
         """Solve A x = b: FP64 residuals with this plan (FP64 values), corrections with
         the degree-``degree`` Chebyshev polynomial of ``lo`` (the same matrix, FP32 or FP64
         values).  Returns (x, corrections applied, final ||r|| / ||b||)."""
         import torch
         if x is None:
             x = torch.zeros_like(b)
-        flags = self._flags(permuted, plain)
+        flags = self._flags(permuted, plain, staged)
         w, nb = lo._work(CALL_SOLVE, degree, flags, b.device)
         it = ctypes.c_int32()
         rel = ctypes.c_double()

@@ -210,3 +210,29 @@ def test_f32_values_shrink_the_device_buffer():
     assert p64.device_bytes - p32.device_bytes >= 4 * slots - 512  # 4 bytes per slot, alignment aside
     with pytest.raises(ValueError):
         M.Plan.from_csr(A, values="bf16")
+
+
+@pytest.mark.parametrize("name", ["lap3d", "rand_nonsym", "blocks", "knn", "lap1d", "single"])
+@pytest.mark.parametrize("cache_mib,q,floor,values", [(1, 4, 0, "f64"), (1, 2, 5000, "f64"), (2, 7, 0, "f32"),
+                                                      (256, 4, 0, "f64"), (1, 15, 0, "f64")])
+def test_planner_schedule_bit_exact_to_oracle(name, cache_mib, q, floor, values):
+    A = MATRICES[name]()
+    plan = M.Plan.from_csr(A, cache_mib=cache_mib, min_group_rows=floor, values=values)
+    ng, tasks = plan.schedule(q)
+    level, nl, _ = O.bfs_levels(A)
+    perm, iperm, lp = O.level_permutation(level, nl)
+    gp = O.group_levels(A, lp, perm, cache_mib << 20, q, value_bytes=4 if values == "f32" else 8,
+                        min_group_rows=floor)
+    assert ng == len(gp) - 1
+    want = [(s, k, lp[lo], lp[hi + 1]) for s, k, lo, hi in O.wavefront_schedule(gp, q)]
+    assert [tuple(int(v) for v in t) for t in tasks] == [tuple(int(v) for v in t) for t in want]
+
+
+def test_schedule_argument_errors():
+    plan = M.Plan.from_csr(S.laplacian_2d(8))
+    lib = M.lib()
+    nt, ng = ctypes.c_int32(), ctypes.c_int32()
+    assert lib.mpk_get_schedule(plan._h, 0, ctypes.byref(nt), ctypes.byref(ng), None) == -1
+    assert lib.mpk_get_schedule(plan._h, 16, ctypes.byref(nt), ctypes.byref(ng), None) == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, cache_mib=-1)[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, min_group_rows=-2)[0] == -1
