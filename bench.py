@@ -83,6 +83,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 matrix-value measurement")
     ap.add_argument("--no-solve", action="store_true", help="skip the refinement-solve latency measurement")
+    ap.add_argument("--no-sweep", action="store_true", help="skip the p = 1..8 sweep")
     ap.add_argument("--solve-reps", type=int, default=10)
     ap.add_argument("--solve-degree", type=int, default=256)
     ap.add_argument("--only", choices=["both", "blocked", "plain"], default="both",
@@ -236,6 +237,31 @@ def main():
         out["roofline_equivalent_frac"] = round(value / (flops / (b_blk / (HBM_PEAK_GBS * 1e9)) / 1e9), 4)
     if args.only == "both":
         out["staged_wavefront"] = res_staged
+    if args.only == "both" and not args.no_sweep:
+        # p = 1..8 with one plan of blocks up to 8 powers (shorter jobs are one block)
+        plan8 = Plan.from_csr(A, p_block=8).upload(dev)
+        x8 = plan8.permute(torch.tensor(x, device=dev), 0)
+        Y8 = torch.empty((8, n), dtype=torch.float64, device=dev)
+        sweep = {}
+        for pp in range(1, 9):
+            tb, tpl = [], []
+            for plain_ in (False, True):
+                for _ in range(3):
+                    plan8.apply(x8, pp, Y=Y8[:pp], plain=plain_)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(10):
+                    plan8.apply(x8, pp, Y=Y8[:pp], plain=plain_)
+                e1.record(stream)
+                e1.synchronize()
+                (tpl if plain_ else tb).append(e0.elapsed_time(e1) / 10 * 1e-3)
+            plan8.check()
+            f = 2.0 * nnz * pp
+            sweep[str(pp)] = {"blocked_gflops": round(f / tb[0] / 1e9, 1), "plain_gflops": round(f / tpl[0] / 1e9, 1),
+                              "speedup": round(tpl[0] / tb[0], 3)}
+        out["p_sweep"] = sweep
+        log("p sweep: " + ", ".join(f"p={k}: {v['speedup']}x" for k, v in sweep.items()))
+        del plan8, Y8
     if not args.no_f32 and args.only == "both":
         # FP32 storage of the matrix values (vectors, products and sums stay FP64)
         # four chunks per wave: FP32 values leave registers for them (measured faster

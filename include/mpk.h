@@ -223,7 +223,8 @@ mpk_status mpk_work_bytes(mpk_plan_t plan, int32_t call, int32_t p, uint32_t fla
  * loop); q is lowered until the deadlock bound of the plan (mpk_min_workers)
  * fits the resident waves, and when only q = 1 fits (BFS levels too wide for
  * the waves) the call runs one SpMV launch per power, as blocking could not
- * reuse the matrix.  MPK_PLAIN always runs p full SpMV launches (the
+ * reuse the matrix; so does any block of a single power (p = 1, or a
+ * one-power remainder).  MPK_PLAIN always runs p full SpMV launches (the
  * comparator).  Results of the blocked and plain paths are bitwise identical.
  * Errors: MPK_ERR_ARG (p < 1, ldy < n, null pointers, work too small),
  * MPK_ERR_STATE (not uploaded), MPK_ERR_HIP.

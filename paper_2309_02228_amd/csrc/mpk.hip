@@ -787,32 +787,38 @@ mpk_status run_staged(mpk_plan_t p, hipStream_t st, const PowerJob& j) {
     return MPK_OK;
 }
 
+// Power k of the job as one full SpMV launch (Alg. 1).
+mpk_status plain_power(mpk_plan_t p, hipStream_t st, const PowerJob& j, int k) {
+    SpmvArgs a{};
+    a.in = job_vec(j, k - 1);
+    a.prev2 = (j.kind == KIND_CHEB && k >= 2) ? job_vec(j, k - 2) : nullptr;
+    a.out = job_dest(j, k);
+    a.acc_in = (j.poly && k >= 2) ? j.acc : nullptr;
+    a.acc_out = j.poly ? j.acc : nullptr;
+    a.c0 = j.poly ? j.c[0] : 0.0;
+    a.gk = k;
+    a.C.lam[0] = j.lam.empty() ? 0.0 : j.lam[k - 1];
+    a.C.sig[0] = j.sig.empty() ? 1.0 : j.sig[k - 1];
+    a.C.c[0] = j.poly ? j.c[k] : 0.0;
+    a.C.theta = j.theta;
+    a.C.delta = j.delta;
+    if (k == 1 && j.copy0) {
+        HIP_TRY(hipMemcpyAsync(j.copy0, j.x, sizeof(double) * p->H.n, hipMemcpyDeviceToDevice, st));
+    }
+    return launch_spmv(p, st, j.kind, j.poly, a);
+}
+
 mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plain, bool staged = false) {
     if (j.p == 0) return MPK_OK;
     if (p->H.n == 0) return MPK_OK;
     if (staged && !plain) return run_staged(p, st, j);
-    // When the deadlock bound admits only one power per launch (levels too wide
-    // for the resident waves), blocking cannot reuse the matrix and the plain
-    // kernel is faster; both give bitwise-equal results.
+    // A block of one power cannot reuse the matrix, and when the deadlock bound
+    // admits only one power per launch (levels too wide for the resident waves)
+    // every block is such a block: the plain kernel is faster there, and both
+    // give bitwise-equal results.
     if (plain || p->q_eff[j.kind][j.poly] <= 1) {
         for (int k = 1; k <= j.p; ++k) {
-            SpmvArgs a{};
-            a.in = job_vec(j, k - 1);
-            a.prev2 = (j.kind == KIND_CHEB && k >= 2) ? job_vec(j, k - 2) : nullptr;
-            a.out = job_dest(j, k);
-            a.acc_in = (j.poly && k >= 2) ? j.acc : nullptr;
-            a.acc_out = j.poly ? j.acc : nullptr;
-            a.c0 = j.poly ? j.c[0] : 0.0;
-            a.gk = k;
-            a.C.lam[0] = j.lam.empty() ? 0.0 : j.lam[k - 1];
-            a.C.sig[0] = j.sig.empty() ? 1.0 : j.sig[k - 1];
-            a.C.c[0] = j.poly ? j.c[k] : 0.0;
-            a.C.theta = j.theta;
-            a.C.delta = j.delta;
-            if (k == 1 && j.copy0) {
-                HIP_TRY(hipMemcpyAsync(j.copy0, j.x, sizeof(double) * p->H.n, hipMemcpyDeviceToDevice, st));
-            }
-            mpk_status s = launch_spmv(p, st, j.kind, j.poly, a);
+            mpk_status s = plain_power(p, st, j, k);
             if (s != MPK_OK) return s;
         }
         return MPK_OK;
@@ -820,6 +826,11 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
     const int qe = p->q_eff[j.kind][j.poly];
     for (int base = 0; base < j.p; base += qe) {
         const int q = std::min(qe, j.p - base);
+        if (q == 1) {  // a one-power block (p = 1, or the remainder)
+            mpk_status s = plain_power(p, st, j, base + 1);
+            if (s != MPK_OK) return s;
+            continue;
+        }
         BlockArgs a{};
         a.in = job_vec(j, base);
         a.prev2 = (j.kind == KIND_CHEB && base >= 1) ? job_vec(j, base - 1) : nullptr;
