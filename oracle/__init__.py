@@ -13,6 +13,8 @@ sparse iterative solvers on multi-core CPUs"):
 * ``spmv``, ``mpk``                 -- Sec. 3, Alg. 1 and Alg. 2
 * ``round_values``                  -- reduced-precision storage of the matrix
   values (reading R11; the paper itself works in FP64)
+* ``round_values_bf16_rowscale``    -- BF16 values with a per-row FP32 scale
+  (reading R16)
 * ``chebyshev_inverse_coeffs``      -- the degree-d Chebyshev polynomial
   preconditioner (Sec. 5; reading R12)
 * ``refine_solve``                  -- FP64 iterative refinement around it, with

@@ -9,7 +9,7 @@ and unique within a row), vectors are float64 NumPy arrays.
 
 Parity status
 -------------
-pinned   spmv, mpk, round_values, chebyshev_inverse_coeffs, refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
+pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_coeffs, refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
          hop_min, window_ok, min_workers,
@@ -87,6 +87,10 @@ READINGS = {
            "lo = max(0, s_g - (k - 1)) (0 for g = 0) and hi = e_g - (k - 1) (L - 1 for "
            "g = G - 1), empty when hi < lo, at stage g + k - 1; stages run in order, "
            "G + q - 1 of them.",
+    "R16": "BF16 storage with a per-row scale (beyond the paper): a_ij ~ s_i q_ij with "
+           "s_i = fl32(max_j |a_ij|) (1 for an all-zero row) and q_ij the BF16 value "
+           "nearest (ties to even) to fl32(a_ij / s_i); the product is formed exactly in "
+           "FP64 and the MPK is the FP64 MPK of the matrix of those products.",
     "R11": "Reduced-precision matrix storage (the paper works in FP64 only): each stored "
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
@@ -137,6 +141,30 @@ def spmv_rows(A, x, r0, r1):
     prod = val[a:b] * np.asarray(x, dtype=np.float64)[col[a:b]]
     rows = np.repeat(np.arange(r1 - r0, dtype=np.int64), np.diff(rowptr[r0:r1 + 1]))
     return np.bincount(rows, weights=prod, minlength=r1 - r0)
+
+
+def _bf16_rne(v32):
+    """Rounds FP32 values to the nearest BF16 value (ties to even) on their bit
+    patterns: keep the upper 16 bits after adding 0x7FFF plus the lowest kept bit."""
+    b = np.asarray(v32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+def round_values_bf16_rowscale(A):
+    """Reading R16: a_ij ~ s_i q_ij with s_i = fl32(max_j |a_ij|) (1 for an all-zero
+    row) and q_ij = bf16(fl32(a_ij / s_i)) (round to nearest even); the product
+    s_i q_ij (8 + 24 significant bits) is exact in FP64.  Returns the matrix of
+    those products."""
+    n, rowptr, col, val = A
+    rp = np.asarray(rowptr, dtype=np.int64)
+    v = np.asarray(val, dtype=np.float64)
+    rows = np.repeat(np.arange(int(n)), np.diff(rp))
+    amax = np.zeros(int(n))
+    np.maximum.at(amax, rows, np.abs(v))
+    scale = np.where(amax > 0, amax, 1.0).astype(np.float32)
+    q = _bf16_rne((v / scale[rows].astype(np.float64)).astype(np.float32))
+    return type(A)(n, rowptr, col, scale[rows].astype(np.float64) * q.astype(np.float64))
 
 
 def round_values(A, dtype=np.float32):

@@ -149,6 +149,45 @@ def test_refine_solve_reaches_direct_solution():
     assert all(h1 < h0 for h0, h1 in zip(hist, hist[1:]))  # each step contracts
 
 
+def test_bf16_rounding_hand_constants():
+    # BF16 keeps 8 significant bits: near 1 the spacing is 2^-7.  catches: truncation
+    # instead of rounding, ties rounded away from even, a wrong bit count
+    from oracle import mpk_oracle as M
+    v = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -9, 1 + 3 * 2 ** -8, -(1 + 2 ** -8), 2.0 ** -20 * 1.75],
+                 dtype=np.float32)
+    want = [1.0, 1.0, 1 + 2 ** -7, 1 + 2 ** -6, -1.0, 2.0 ** -20 * 1.75]
+    assert [float(t) for t in M._bf16_rne(v)] == want
+
+
+def test_bf16_rowscale_hand_worked():
+    # row [6, -1, 0.1]: s = 6, q = bf16(1), bf16(-1/6), bf16(0.1/6).  -1/6 lies in
+    # [2^-3, 2^-2) where BF16 spacing is 2^-10: 1024/6 = 170.67 -> 171, so the entry
+    # becomes -6 * 171/1024; 0.1/6 = 0.016667 in [2^-6, 2^-5), spacing 2^-13:
+    # 8192 * 0.016667 = 136.53 -> 137 (via its FP32 value), entry 6 * 137/8192.
+    # catches: scaling by something other than the row maximum, a lost sign
+    from fractions import Fraction
+    A = S.from_dense([[6.0, -1.0, 0.1], [0.0, 0.0, 0.0], [1.0 / 3.0, 0.0, 2.0]])
+    got = [Fraction(float(v)) for v in O.round_values_bf16_rowscale(A).val]
+    assert got[:3] == [Fraction(6), Fraction(-6 * 171, 1024), Fraction(6 * 137, 8192)]
+    # row 2: s = 2, 1/6 -> 171/1024 again
+    assert got[3:] == [Fraction(2 * 171, 1024), Fraction(2)]
+
+
+@pytest.mark.parametrize("p", [1, 4, 8])
+def test_bf16_rowscale_mpk_within_perturbation_bound(p):
+    # |a~ - a| <= (2^-8 + 2^-22) |a| (BF16 rounding plus the FP32 quotient and scale
+    # roundings), so |A~^k x - A^k x| <= ((1 + u)^k - 1) |A|^k |x|.  catches: a scale
+    # applied twice, a missing scale, precision lost beyond one BF16 rounding
+    A = S.laplacian_3d(9, 8, 7)
+    x = S.uniform_vector(A.n, 2)
+    u = 2.0 ** -8 + 2.0 ** -22
+    bound = O.mpk(A._replace(val=np.abs(A.val)), np.abs(x), p)
+    err = np.abs(O.mpk(O.round_values_bf16_rowscale(A), x, p) - O.mpk(A, x, p))
+    for k in range(p):
+        assert np.all(err[k] <= ((1 + u) ** (k + 1) - 1) * bound[k] * (1 + 1e-12)), k
+    assert err.max() > 0  # -1/6 is not a BF16 value: the stencil is perturbed
+
+
 def test_mpk_hand_worked_grid3x3(golden_dir):
     rows = {}
     with open(os.path.join(golden_dir, "grid3x3_power2.txt")) as f:
