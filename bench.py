@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--chunks-per-worker", type=int, default=0)
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-f32", action="store_true", help="skip the FP32 matrix-value measurement")
+    ap.add_argument("--no-f32", action="store_true", help="skip the FP32 and BF16 matrix-value measurements")
     ap.add_argument("--no-solve", action="store_true", help="skip the refinement-solve latency measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the p = 1..8 sweep")
     ap.add_argument("--solve-reps", type=int, default=10)
@@ -262,36 +262,42 @@ def main():
         out["p_sweep"] = sweep
         log("p sweep: " + ", ".join(f"p={k}: {v['speedup']}x" for k, v in sweep.items()))
         del plan8, Y8
-    if not args.no_f32 and args.only == "both":
-        # FP32 storage of the matrix values (vectors, products and sums stay FP64)
-        # four chunks per wave: FP32 values leave registers for them (measured faster
-        # than two for the power kernel)
-        plan32 = Plan.from_csr(A, p_block=args.p_block or min(p, 15),
-                               chunks_per_worker=args.chunks_per_worker or 4, values="f32").upload(dev)
-        xd32 = plan32.permute(torch.tensor(x, device=dev), 0)
-        Y32 = torch.empty_like(Y)
-        wb32, _ = timed(False, plan32, xd32, Y32)
-        wp32, _ = timed(True, plan32, xd32, Y32)
+    for vals in ([] if args.no_f32 or args.only != "both" else ["f32", "bf16"]):
+        # reduced-precision storage of the matrix values (vectors, products and sums stay FP64)
+        # with four chunks per wave: the narrow values leave registers for them (measured
+        # faster than two for the power kernel)
+        plan_r = Plan.from_csr(A, p_block=args.p_block or min(p, 15),
+                               chunks_per_worker=args.chunks_per_worker or 4, values=vals).upload(dev)
+        xd_r = plan_r.permute(torch.tensor(x, device=dev), 0)
+        Y_r = torch.empty_like(Y)
+        wb_r, _ = timed(False, plan_r, xd_r, Y_r)
+        wp_r, _ = timed(True, plan_r, xd_r, Y_r)
         plan.apply(xd, p, Y=Y)
-        plan32.apply(xd32, p, Y=Y32)
+        plan_r.apply(xd_r, p, Y=Y_r)
         torch.cuda.synchronize()
-        err = ((Y32 - Y).norm(dim=1) / Y.norm(dim=1)).cpu().numpy()
-        out["f32_values"] = {
-            "blocked_gflops": round(flops * args.steps / wb32 / 1e9, 2),
-            "plain_gflops": round(flops * args.steps / wp32 / 1e9, 2),
-            "ms_per_step": round(wb32 / args.steps * 1e3, 5),
-            "speedup_vs_plain_f32": round(wp32 / wb32, 3),
-            "speedup_vs_f64_blocked": round(wall / wb32, 3) if key == "blocked" else None,
+        err = ((Y_r - Y).norm(dim=1) / Y.norm(dim=1)).cpu().numpy()
+        vbytes = {"f32": 4, "bf16": 2}[vals]
+        out[f"{vals}_values"] = {
+            "blocked_gflops": round(flops * args.steps / wb_r / 1e9, 2),
+            "plain_gflops": round(flops * args.steps / wp_r / 1e9, 2),
+            "ms_per_step": round(wb_r / args.steps * 1e3, 5),
+            "speedup_vs_plain": round(wp_r / wb_r, 3),
+            "speedup_vs_f64_blocked": round(wall / wb_r, 3) if key == "blocked" else None,
             "chunks_per_worker": args.chunks_per_worker or 4,
-            "bytes_per_launch": int(bytes_per_launch - 4 * nnz / launches_per_step),
+            "bytes_per_launch": int(bytes_per_launch - (8 - vbytes) * nnz / launches_per_step
+                                    + (4 * n if vals == "bf16" else 0) / launches_per_step),
             "max_rel_err_vs_f64_per_power": float(err.max()),
-            "note": "matrix values rounded once to FP32 at upload; vectors, products and sums "
-                    "in FP64; the 7-point stencil's values are integers, so FP32 storage is exact",
+            "note": {"f32": "matrix values rounded once to FP32 at upload; vectors, products and sums "
+                            "in FP64; the 7-point stencil's values are integers, so FP32 storage is exact",
+                     "bf16": "a_ij ~ s_i q_ij with s_i = fl32(max_j |a_ij|) per row and q_ij in BF16 "
+                             "(nearest, ties to even); s_i q_ij is exact in FP64; the stencil's -1/6 "
+                             "is not a BF16 value, so the powers carry the stated error"}[vals],
         }
-        log(f"f32 values: blocked {wb32 / args.steps * 1e6:.1f} us/step, plain {wp32 / args.steps * 1e6:.1f} "
+        log(f"{vals} values: blocked {wb_r / args.steps * 1e6:.1f} us/step, plain {wp_r / args.steps * 1e6:.1f} "
             f"us/step, max rel err vs FP64 {err.max():.2e}")
+        del plan_r, Y_r
     out["solve_latency_ms"] = {"p50": None, "p99": None, "note": "not measured"}
-    if not args.no_f32 and not args.no_solve and args.only == "both":
+    if not args.no_solve and args.only == "both":
         # A x = b to 1e-10 by FP64 iterative refinement around a Chebyshev polynomial
         # preconditioner on the exact spectrum bounds of the Dirichlet stencil
         cg = np.cos(np.pi / (g + 1))
@@ -313,10 +319,13 @@ def main():
                     "p99_ms": round(float(np.percentile(lat, 99)), 3),
                     "corrections": res[1], "final_rel_residual": res[2],
                     "powers_per_solve": res[1] * (d - 1)}
-        # corrections with FP32 values and two chunks per wave (the polynomial kernel
-        # needs the registers that four chunks would take)
+        # corrections with FP32 (or BF16) values and two chunks per wave (the polynomial
+        # kernel needs the registers that four chunks would take)
+        # (BF16 corrections are not used here: their perturbation of the spectrum, about
+        # 2^-8 of |A|, dwarfs lambda_min = 0.0011, and refinement barely contracts)
         plan_lo = Plan.from_csr(A, p_block=args.p_block or min(p, 15), values="f32").upload(dev)
         mixed = solves(plan_lo, False)
+        del plan_lo
         fp64_plain = solves(plan, True)
         out["solve"] = {
             "workload": f"A x = b, 3D 7-point Laplacian {g}^3, b uniform[-1,1] seed 1 (level order), x0 = 0, "

@@ -69,6 +69,10 @@ typedef enum {
 /* value storage for mpk_options.value_type */
 #define MPK_VALUES_F64 0
 #define MPK_VALUES_F32 1
+#define MPK_VALUES_BF16_ROWSCALE 2 /* a_ij ~ s_i q_ij: s_i = fl32(max_j |a_ij|) per row,
+                                     q_ij = BF16 nearest (ties to even) to
+                                     fl32(a_ij / s_i); s_i q_ij is formed exactly
+                                     in FP64 at every use                      */
 
 /* call kinds for mpk_work_bytes */
 #define MPK_CALL_APPLY 0
@@ -97,12 +101,14 @@ typedef struct {
                                 slots).  With FP32 values, 4 suits mpk_apply
                                 on rows of at most 8 slots                    */
     int32_t value_type;      /* storage of the matrix values on the device:
-                                MPK_VALUES_F64 (0) or MPK_VALUES_F32 (1).  FP32
-                                rounds each value once to nearest at upload;
-                                vectors, products and sums stay FP64, so every
-                                call returns the FP64 MPK of the rounded matrix
-                                (the paper works in FP64 only; this halves the
-                                value bytes)                                  */
+                                MPK_VALUES_F64 (0), MPK_VALUES_F32 (1) or
+                                MPK_VALUES_BF16_ROWSCALE (2).  The reduced
+                                forms round each value once at upload; vectors,
+                                products and sums stay FP64, so every call
+                                returns the FP64 MPK of the rounded matrix (the
+                                paper works in FP64 only; FP32 halves the value
+                                bytes, BF16 quarters them and adds 4 bytes of
+                                scale per row)                                */
     int32_t max_reg_slots;   /* largest number of SELL slots per row the
                                 blocked kernel keeps in registers (4, 7, 8,
                                 16 or 32; 0 = automatic: the smallest of these

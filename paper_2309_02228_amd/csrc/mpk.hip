@@ -52,7 +52,8 @@ enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2 };
 
 // ------------------------------------------------------------------ device
 struct DevPlan {
-    const void* val;           // SELL values: double, or float for FP32 storage
+    const void* val;           // SELL values: double, float (FP32) or BF16 bits
+    const float* rowscale;     // per permuted row (BF16 storage only)
     const int32_t* col;
     const int64_t* off;
     const int32_t* seq;
@@ -112,10 +113,30 @@ struct SpmvArgs {
 // Row sum over the chunk's slots j = 0..width-1, in this order, as one FMA
 // chain.  Slots are fetched in batches of 8 (columns and values first, then
 // the gathers) so that a batch costs two memory round trips.
+// A stored value as FP64.  BF16 storage (VT = uint16_t) holds q with the
+// row's FP32 scale s; s * q has at most 8 + 24 significant bits, so the FP64
+// product is exact.
+template <typename VT>
+__device__ __forceinline__ double decode(VT v, float scale) {
+    if constexpr (sizeof(VT) == 2)
+        return (double)scale * (double)__uint_as_float((uint32_t)v << 16);
+    else
+        return (double)v;
+}
+
+template <typename VT>
+__device__ __forceinline__ float row_scale(const DevPlan& P, int row) {
+    if constexpr (sizeof(VT) == 2)
+        return P.rowscale[row];
+    else
+        return 1.0f;
+}
+
 template <typename VT>
 __device__ __forceinline__ double row_sum_mem(const DevPlan& P, const double* in, int64_t off,
-                                              int width, int lane) {
+                                              int width, int lane, int row) {
     const VT* val = (const VT*)P.val;
+    const float sc = row_scale<VT>(P, row);
     double s = 0.0;
     for (int j0 = 0; j0 < width; j0 += 8) {
         int cj[8];
@@ -127,7 +148,7 @@ __device__ __forceinline__ double row_sum_mem(const DevPlan& P, const double* in
             if (j0 + t < width) {
                 const int64_t slot = off + (int64_t)(j0 + t) * kChunkRows + lane;
                 cj[t] = __builtin_nontemporal_load(P.col + slot);
-                vj[t] = (double)__builtin_nontemporal_load(val + slot);
+                vj[t] = decode<VT>(__builtin_nontemporal_load(val + slot), sc);
             }
         }
 #pragma unroll
@@ -150,7 +171,7 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
         const int row = c * kChunkRows + lane;
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
-        const double s = row_sum_mem<VT>(a.P, a.in, off, width, lane);
+        const double s = row_sum_mem<VT>(a.P, a.in, off, width, lane, row);
         if (row < a.P.n) {
             const double prev = (KIND != KIND_MONO || POLY) ? a.in[row] : 0.0;
             const double prev2 = (KIND == KIND_CHEB && a.prev2) ? a.prev2[row] : 0.0;
@@ -300,6 +321,9 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                     rv[g][j] = __builtin_nontemporal_load(val + slot);
                 }
             }
+        float rsc[G];  // row scales (BF16 storage)
+#pragma unroll
+        for (int g = 0; g < G; ++g) rsc[g] = row_scale<VT>(a.P, c[g] >= 0 ? row[g] : 0);
         // the row's own previous value is needed by the shifted kinds, the
         // polynomial accumulator and the basis copy only
         const bool need_prev = KIND != KIND_MONO || POLY || a.copy0 != nullptr;
@@ -347,10 +371,10 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                 for (int j = 0; j < REG; ++j)
                     if (rc[g][j] >= 0) {
                         VT r = rv[g][j];
-                        // keep FP32 values narrow in registers: convert at each use
+                        // keep narrow values narrow in registers: convert at each use
                         // instead of letting the compiler hoist a widened copy
-                        if constexpr (sizeof(VT) == 4) asm volatile("" : "+v"(r));
-                        s[g] = fma((double)r, xv[j], s[g]);
+                        if constexpr (sizeof(VT) < 8) asm volatile("" : "+v"(r));
+                        s[g] = fma(decode<VT>(r, rsc[g]), xv[j], s[g]);
                     }
             }
 #pragma unroll
@@ -359,8 +383,8 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                     const int64_t slot = off[g] + (int64_t)j * kChunkRows + lane;
                     const int cj = a.P.col[slot];
                     if (cj >= 0)
-                        s[g] = fma((double)val[slot], kl == 0 || a.plain_gather ? src[cj] : load_coherent(src + cj),
-                                   s[g]);
+                        s[g] = fma(decode<VT>(val[slot], rsc[g]),
+                                   kl == 0 || a.plain_gather ? src[cj] : load_coherent(src + cj), s[g]);
                 }
             double* dst = dest(a, kl);
             const bool last = kl + 1 == a.q;
@@ -429,7 +453,7 @@ __global__ __launch_bounds__(kBlockThreads) void stage_kernel(StageArgs a) {
         const int row = c * kChunkRows + lane;
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
-        const double s = row_sum_mem<VT>(a.P, T.in, off, width, lane);
+        const double s = row_sum_mem<VT>(a.P, T.in, off, width, lane, row);
         if (row >= T.r0 && row < T.r1) {
             const double prev = (KIND != KIND_MONO || POLY) ? T.in[row] : 0.0;
             const double prev2 = (KIND == KIND_CHEB && T.prev2) ? T.prev2[row] : 0.0;
@@ -497,7 +521,7 @@ __global__ __launch_bounds__(kBlockThreads) void residual_kernel(DevPlan P, cons
         const int row = c * kChunkRows + lane;
         const int64_t off = P.off[c];
         const int width = (int)((P.off[c + 1] - off) / kChunkRows);
-        const double s = row_sum_mem<VT>(P, x, off, width, lane);
+        const double s = row_sum_mem<VT>(P, x, off, width, lane, row);
         if (row < P.n) {
             const double ri = b[row] - s;
             r[row] = ri;
@@ -552,8 +576,8 @@ mpk_status fail(mpk_status s, const char* fmt, ...) {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t val, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, dep_ptr, dep_idx, done, tickets, status,
-        total;
+    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, dep_ptr, dep_idx, done, tickets,
+        status, total;
 };
 
 Layout make_layout(const mpk::HostPlan& H) {
@@ -565,7 +589,8 @@ Layout make_layout(const mpk::HostPlan& H) {
         return at;
     };
     const size_t slots = H.sell_val.size();
-    L.val = take(slots * (H.value_type == 1 ? 4 : 8));
+    L.val = take(slots * (H.value_type == MPK_VALUES_BF16_ROWSCALE ? 2 : H.value_type == MPK_VALUES_F32 ? 4 : 8));
+    L.rowscale = take(H.value_type == MPK_VALUES_BF16_ROWSCALE ? (size_t)H.nchunks * kChunkRows * 4 : 0);
     L.col = take(slots * 4);
     L.off = take((H.nchunks + 1) * 8);
     L.perm = take((size_t)H.n * 4);
@@ -639,8 +664,9 @@ BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
 
 // The planner keeps one chunk per worker when rows need 32 or more slots.
 BlockFn pick_block(const mpk::HostPlan& H, int kind, bool poly) {
-    return H.value_type == 1 ? pick_block_vt<float>(H.reg_slots, H.group, kind, poly)
-                             : pick_block_vt<double>(H.reg_slots, H.group, kind, poly);
+    if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_vt<uint16_t>(H.reg_slots, H.group, kind, poly);
+    return H.value_type == MPK_VALUES_F32 ? pick_block_vt<float>(H.reg_slots, H.group, kind, poly)
+                                          : pick_block_vt<double>(H.reg_slots, H.group, kind, poly);
 }
 
 template <typename VT>
@@ -660,11 +686,13 @@ StageFn pick_stage_vt(int kind, bool poly) {
 }
 
 StageFn pick_stage(const mpk::HostPlan& H, int kind, bool poly) {
-    return H.value_type == 1 ? pick_stage_vt<float>(kind, poly) : pick_stage_vt<double>(kind, poly);
+    if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_stage_vt<uint16_t>(kind, poly);
+    return H.value_type == MPK_VALUES_F32 ? pick_stage_vt<float>(kind, poly) : pick_stage_vt<double>(kind, poly);
 }
 
 SpmvFn pick_spmv(const mpk::HostPlan& H, int kind, bool poly) {
-    return H.value_type == 1 ? pick_spmv_vt<float>(kind, poly) : pick_spmv_vt<double>(kind, poly);
+    if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_spmv_vt<uint16_t>(kind, poly);
+    return H.value_type == MPK_VALUES_F32 ? pick_spmv_vt<float>(kind, poly) : pick_spmv_vt<double>(kind, poly);
 }
 
 int grid_1d(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(4096, (n + 255) / 256)); }
@@ -895,8 +923,9 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
     if (o.max_reg_slots != 0 && o.max_reg_slots != 4 && o.max_reg_slots != 7 && o.max_reg_slots != 8 &&
         o.max_reg_slots != 16 && o.max_reg_slots != 32)
         return fail(MPK_ERR_ARG, "max_reg_slots must be 0, 4, 7, 8, 16 or 32");
-    if (o.value_type != MPK_VALUES_F64 && o.value_type != MPK_VALUES_F32)
-        return fail(MPK_ERR_ARG, "value_type must be MPK_VALUES_F64 (0) or MPK_VALUES_F32 (1)");
+    if (o.value_type < MPK_VALUES_F64 || o.value_type > MPK_VALUES_BF16_ROWSCALE)
+        return fail(MPK_ERR_ARG, "value_type must be MPK_VALUES_F64 (0), MPK_VALUES_F32 (1) or "
+                                 "MPK_VALUES_BF16_ROWSCALE (2)");
     if (o.root_mode != 0 && o.root_mode != 1) return fail(MPK_ERR_ARG, "root_mode must be 0 or 1");
     if (o.root_mode == 1 && (o.root < 0 || o.root >= n)) return fail(MPK_ERR_ARG, "root out of range");
     if (o.p_block < 0 || o.p_block > mpk::kMaxBlock)
@@ -999,7 +1028,32 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
         return hipMemcpyAsync(d + at, src, nb, hipMemcpyHostToDevice, st);
     };
     std::vector<float> val32;  // FP32 storage: each value rounded once to nearest
-    if (H.value_type == 1) {
+    std::vector<uint16_t> val16;
+    std::vector<float> scale;
+    if (H.value_type == MPK_VALUES_BF16_ROWSCALE) {
+        // per permuted row: s = fl32(max |a|) (1 for an empty or zero row), and
+        // each value as the BF16 nearest (ties to even) to fl32(a / s)
+        const size_t rows = (size_t)H.nchunks * kChunkRows;
+        std::vector<double> amax(rows, 0.0);
+        for (int32_t c = 0; c < H.nchunks; ++c)
+            for (int64_t sl = H.chunk_off[c]; sl < H.chunk_off[c + 1]; ++sl) {
+                const size_t r = (size_t)c * kChunkRows + (size_t)((sl - H.chunk_off[c]) % kChunkRows);
+                amax[r] = std::max(amax[r], std::fabs(H.sell_val[sl]));
+            }
+        scale.resize(rows);
+        for (size_t r = 0; r < rows; ++r) scale[r] = amax[r] > 0.0 ? (float)amax[r] : 1.0f;
+        val16.resize(H.sell_val.size());
+        for (int32_t c = 0; c < H.nchunks; ++c)
+            for (int64_t sl = H.chunk_off[c]; sl < H.chunk_off[c + 1]; ++sl) {
+                const size_t r = (size_t)c * kChunkRows + (size_t)((sl - H.chunk_off[c]) % kChunkRows);
+                const float q = (float)(H.sell_val[sl] / (double)scale[r]);
+                uint32_t b;
+                std::memcpy(&b, &q, 4);
+                val16[sl] = (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+            }
+        HIP_TRY(put(L.val, val16.data(), val16.size() * 2));
+        HIP_TRY(put(L.rowscale, scale.data(), scale.size() * 4));
+    } else if (H.value_type == MPK_VALUES_F32) {
         val32.resize(H.sell_val.size());
         for (size_t i = 0; i < val32.size(); ++i) val32[i] = (float)H.sell_val[i];
         HIP_TRY(put(L.val, val32.data(), val32.size() * 4));
@@ -1028,6 +1082,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
 
     DevPlan D{};
     D.val = (const void*)(d + L.val);
+    D.rowscale = (const float*)(d + L.rowscale);
     D.col = (const int32_t*)(d + L.col);
     D.off = (const int64_t*)(d + L.off);
     D.seq = (const int32_t*)(d + L.seq);

@@ -363,7 +363,7 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
 std::vector<int32_t> group_levels(const HostPlan& P, int32_t q) {
     // greedy and contiguous under the budget floor(C / q) (R14)
     const int64_t budget = P.cache_bytes / std::max(1, q);
-    const int64_t vbytes = P.value_type == 1 ? 4 : 8;
+    const int64_t vbytes = P.value_type == 1 ? 4 : P.value_type == 2 ? 2 : 8;
     std::vector<int32_t> gp{0};
     int64_t w_group = 0, rows_group = 0;
     for (int32_t l = 0; l < P.nlevels; ++l) {

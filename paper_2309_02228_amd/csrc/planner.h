@@ -19,7 +19,7 @@ struct HostPlan {
     // options
     int32_t root_mode = 0, root = 0, p_block = 4, workers_req = 0, watchdog = 0;
     int32_t group = 2;  // chunks a worker carries together (G); 0 = chosen by the planner
-    int32_t value_type = 0;  // 0: FP64 values on the device, 1: FP32 (rounded at upload)
+    int32_t value_type = 0;  // 0: FP64 values on the device, 1: FP32, 2: BF16 with a row scale
     int32_t max_reg = 0;     // cap on register slots (0 = automatic)
     int64_t cache_bytes = 256ll << 20;  // C of the level groups (R14)
     int32_t min_group_rows = 0;         // row floor of a level group (R14)

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmpk.so")
 MPK_IO_PERMUTED = 1
 MPK_PLAIN = 2
 MPK_STAGED = 4
-VALUE_TYPES = {"f64": 0, "f32": 1}
+VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}  # bf16: BF16 values with a per-row FP32 scale
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
 CALL_APPLY, CALL_POLY, CALL_SSTEP, CALL_SOLVE = 0, 1, 2, 3
 

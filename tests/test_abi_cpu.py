@@ -157,7 +157,8 @@ def test_malformed_csr_rejected():
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, root_mode=1, root=3)[0] == -1
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, root_mode=2)[0] == -1
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, chunks_per_worker=3)[0] == -1
-    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, value_type=2)[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, value_type=3)[0] == -1
+    assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, value_type=2)[0] == 0
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, value_type=1)[0] == 0
     assert _build(0, [0], [], [])[0] == 0                                  # empty matrix
 
@@ -209,11 +210,14 @@ def test_f32_values_shrink_the_device_buffer():
     assert p32.info()["values"] == "f32" and p64.info()["values"] == "f64"
     assert p64.device_bytes - p32.device_bytes >= 4 * slots - 512  # 4 bytes per slot, alignment aside
     with pytest.raises(ValueError):
-        M.Plan.from_csr(A, values="bf16")
+        M.Plan.from_csr(A, values="f16")
+    p16 = M.Plan.from_csr(A, values="bf16")  # 2 bytes per slot plus a 4-byte scale per row
+    assert p32.device_bytes - p16.device_bytes >= 2 * slots - 4 * 64 * p16.info()["nchunks"] - 1024
 
 
 @pytest.mark.parametrize("name", ["lap3d", "rand_nonsym", "blocks", "knn", "lap1d", "single"])
 @pytest.mark.parametrize("cache_mib,q,floor,values", [(1, 4, 0, "f64"), (1, 2, 5000, "f64"), (2, 7, 0, "f32"),
+                                                      (1, 3, 0, "bf16"),
                                                       (256, 4, 0, "f64"), (1, 15, 0, "f64")])
 def test_planner_schedule_bit_exact_to_oracle(name, cache_mib, q, floor, values):
     A = MATRICES[name]()
@@ -221,7 +225,7 @@ def test_planner_schedule_bit_exact_to_oracle(name, cache_mib, q, floor, values)
     ng, tasks = plan.schedule(q)
     level, nl, _ = O.bfs_levels(A)
     perm, iperm, lp = O.level_permutation(level, nl)
-    gp = O.group_levels(A, lp, perm, cache_mib << 20, q, value_bytes=4 if values == "f32" else 8,
+    gp = O.group_levels(A, lp, perm, cache_mib << 20, q, value_bytes={"f64": 8, "f32": 4, "bf16": 2}[values],
                         min_group_rows=floor)
     assert ng == len(gp) - 1
     want = [(s, k, lp[lo], lp[hi + 1]) for s, k, lo, hi in O.wavefront_schedule(gp, q)]

@@ -1,12 +1,13 @@
-"""GPU parity of FP32 matrix-value storage (reading R11) through the C ABI.
+"""GPU parity of reduced-precision matrix-value storage through the C ABI:
+FP32 values (reading R11) and BF16 values with a per-row FP32 scale (R16).
 
-The device keeps each matrix value rounded once to FP32 while vectors, products
-and sums stay FP64, so the result must match the oracle's FP64 MPK of the
-rounded matrix within the FP64 tolerance, and blocked and plain kernels must
-agree bitwise.  Each test also states the error against the FP64 oracle of the
+The device keeps each matrix value rounded once while vectors, products and
+sums stay FP64, so the result must match the oracle's FP64 MPK of the rounded
+matrix within the FP64 tolerance, and blocked and plain kernels must agree
+bitwise.  Each test also states the error against the FP64 oracle of the
 unrounded matrix and checks it against the perturbation bound
-((1 + 2^-24)^k - 1) |A|^k |x| (relative L2), since every reduced-precision
-result must state that error."""
+((1 + u)^k - 1) |A|^k |x| (relative L2), u = 2^-24 for FP32 and 2^-8 + 2^-22
+for BF16, since every reduced-precision result must state that error."""
 import numpy as np
 import pytest
 
@@ -23,7 +24,9 @@ from paper_2309_02228_amd import Plan  # noqa: E402
 
 DEV = "cuda:0"
 TOL = 1e-12
-U32 = 2.0 ** -24
+U = {"f32": 2.0 ** -24, "bf16": 2.0 ** -8 + 2.0 ** -22}
+ROUND = {"f32": O.round_values, "bf16": O.round_values_bf16_rowscale}
+VALUES = ["f32", "bf16"]
 
 
 def rel_err(got, ref):
@@ -40,18 +43,18 @@ def apply_orig(plan, perm, x, p, plain=False):
     return Y
 
 
-def f32_plan(A, **kw):
-    plan = Plan.from_csr(A, values="f32", **kw).upload(DEV)
+def f32_plan(A, values="f32", **kw):
+    plan = Plan.from_csr(A, values=values, **kw).upload(DEV)
     return plan, plan.levels()["perm"].astype(np.int64)
 
 
-def fp64_error_bound(A, x, p):
+def fp64_error_bound(A, x, p, values="f32"):
     """Relative L2 bound per power from |A~ - A| <= u |A|, plus the FP64 tolerance."""
     absA = A._replace(val=np.abs(A.val))
     ab = O.mpk(absA, np.abs(x), p)
     ref = O.mpk(A, x, p)
     k = np.arange(1, p + 1)
-    return ((1 + U32) ** k - 1) * np.linalg.norm(ab, axis=-1) / np.linalg.norm(ref, axis=-1) + TOL
+    return ((1 + U[values]) ** k - 1) * np.linalg.norm(ab, axis=-1) / np.linalg.norm(ref, axis=-1) + TOL
 
 
 CASES = {
@@ -62,17 +65,18 @@ CASES = {
 }
 
 
+@pytest.mark.parametrize("values", VALUES)
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("p", [1, 4, 9])
-def test_f32_values_match_rounded_oracle(name, p):
+def test_f32_values_match_rounded_oracle(name, p, values):
     A = CASES[name]()
-    plan, perm = f32_plan(A, p_block=4)
+    plan, perm = f32_plan(A, values, p_block=4)
     x = S.uniform_vector(A.n, 2)
     got = apply_orig(plan, perm, x, p)
-    assert np.all(rel_err(got, O.mpk(O.round_values(A), x, p)) <= TOL)
+    assert np.all(rel_err(got, O.mpk(ROUND[values](A), x, p)) <= TOL)
     assert np.array_equal(apply_orig(plan, perm, x, p, plain=True), got)
     err64 = rel_err(got, O.mpk(A, x, p))  # the stated error against the FP64 oracle
-    assert np.all(err64 <= fp64_error_bound(A, x, p)), err64
+    assert np.all(err64 <= fp64_error_bound(A, x, p, values)), err64
 
 
 def test_f32_values_integer_matrix_equals_fp64_bitwise():
@@ -86,22 +90,25 @@ def test_f32_values_integer_matrix_equals_fp64_bitwise():
     assert np.array_equal(apply_orig(plan, perm, x, 8), apply_orig(p64, perm, x, 8))
 
 
+@pytest.mark.parametrize("values", VALUES)
 @pytest.mark.parametrize("G", [1, 2, 4])
 @pytest.mark.parametrize("mk", [lambda: S.knn_graph_laplacian(9000, k=26, seed=6),  # wide rows: G = 1
                                 lambda: S.laplacian_3d(23, 19, 21)])                # narrow rows
-def test_f32_values_chunks_per_worker(G, mk):
+def test_f32_values_chunks_per_worker(G, mk, values):
     A = mk()
-    plan, perm = f32_plan(A, p_block=5, chunks_per_worker=G)
+    plan, perm = f32_plan(A, values, p_block=5, chunks_per_worker=G)
     x = S.uniform_vector(A.n, 6)
     got = apply_orig(plan, perm, x, 12)
-    assert np.all(rel_err(got, O.mpk(O.round_values(A), x, 12)) <= TOL)
+    assert np.all(rel_err(got, O.mpk(ROUND[values](A), x, 12)) <= TOL)
+    assert np.array_equal(apply_orig(plan, perm, x, 12, plain=True), got)
 
 
+@pytest.mark.parametrize("values", VALUES)
 @pytest.mark.parametrize("kind", ["newton", "chebyshev"])
-def test_f32_values_poly_and_sstep(kind):
+def test_f32_values_poly_and_sstep(kind, values):
     A = S.knn_graph_laplacian(12000, k=26, seed=3)
-    Ar = O.round_values(A)
-    plan, perm = f32_plan(A, p_block=4)
+    Ar = ROUND[values](A)
+    plan, perm = f32_plan(A, values, p_block=4)
     x = S.uniform_vector(A.n, 5)
     rng = np.random.default_rng(7)
     c = rng.uniform(-1, 1, 9) / 60.0 ** np.arange(9)
@@ -134,3 +141,16 @@ def test_f32_values_full_size_160_cubed():
     got = apply_orig(plan, perm, x, 4)
     assert np.all(rel_err(got, O.mpk(A, x, 4)) <= TOL)
     assert np.array_equal(apply_orig(plan, perm, x, 4, plain=True), got)
+
+
+@pytest.mark.slow
+def test_bf16_values_full_size_160_cubed():
+    # the stencil's -1/6 is not a BF16 value: the result differs from FP64, within the bound
+    A = S.laplacian_3d(160)
+    plan, perm = f32_plan(A, "bf16", p_block=4)
+    x = S.uniform_vector(A.n, 0)
+    got = apply_orig(plan, perm, x, 4)
+    assert np.all(rel_err(got, O.mpk(O.round_values_bf16_rowscale(A), x, 4)) <= TOL)
+    assert np.array_equal(apply_orig(plan, perm, x, 4, plain=True), got)
+    err64 = rel_err(got, O.mpk(A, x, 4))
+    assert np.all(err64 <= fp64_error_bound(A, x, 4, "bf16")) and err64.max() > 0, err64

@@ -99,3 +99,14 @@ def test_initial_guess_and_argument_errors():
         hi.refine_solve(other, torch.tensor(b[perm], device=DEV), 8, lmin, lmax)  # different matrix
     with pytest.raises(MPKError):
         hi.refine_solve(lo, torch.tensor(b[perm], device=DEV), 8, lmax, lmin)  # lmin >= lmax
+
+
+def test_bf16_corrections_still_reach_1e10():
+    # corrections from BF16 values (u ~ 2^-8) still contract: the FP64 residual decides
+    A, lmin, lmax, b = knn_problem(20000, 8)
+    hi = Plan.from_csr(A).upload(DEV)
+    lo = Plan.from_csr(A, values="bf16").upload(DEV)
+    perm = hi.levels()["perm"].astype(np.int64)
+    x, k, rel = solve_orig(hi, lo, perm, b, 16, lmin, lmax, 1e-10, 800)
+    assert rel <= 1e-10 and 0 < k < 800
+    assert np.linalg.norm(b - O.spmv(A, x)) <= 1.0000001e-10 * np.linalg.norm(b)
