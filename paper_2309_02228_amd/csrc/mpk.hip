@@ -1200,7 +1200,7 @@ MPK_API mpk_status poly_apply(mpk_plan_t p, int32_t kind, int32_t d, const doubl
     if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return fail(MPK_ERR_ARG, "unknown flag bits");
     size_t need = 0;
     mpk_work_bytes(p, MPK_CALL_POLY, d, flags, &need);
-    if (!work || work_bytes < need)
+    if (need > 0 && (!work || work_bytes < need))
         return fail(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
     mpk_status s = check_uploaded(p);
     if (s != MPK_OK) return s;
