@@ -70,6 +70,174 @@ def cpu_baseline(A, x, p, budget_s):
                       f"({el:.1f} s, single-threaded NumPy)"}
 
 
+def serving_bench(args, A160, plan160, dev):
+    """Open-loop serving of a mixed request stream through the library's request
+    server: Poisson arrivals of matrix powers y_p = A^p x (p uniform in 2..10,
+    FP64 or FP32 matrix values) and refinement solves to 1e-8 (FP64 residuals,
+    FP32 Chebyshev corrections) on a catalogue of 2D/3D Laplacians and 26-NN
+    graph Laplacians with N from 1e4 to 4.1e6.  Requests carry host vectors
+    (pinned), so latencies include the PCIe copies.  Every request is first run
+    alone (one worker, one request at a time); its alone latency sets the
+    arrival rate and the per-request slowdown, and a sample of results is
+    compared bit for bit between the two runs."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2309_02228_amd import Plan
+    from paper_2309_02228_amd.mpk import Server
+
+    rng = np.random.default_rng(args.serve_seed)
+
+    def lap_bounds(dims):
+        return (sum(2 - 2 * np.cos(np.pi / (m + 1)) for m in dims),
+                sum(2 + 2 * np.cos(np.pi / (m + 1)) for m in dims))
+
+    cat = []
+    t0 = time.perf_counter()
+    for name, make, dims in [("lap2d_100^2", lambda: synth.laplacian_2d(100), (100, 100)),
+                             ("lap3d_50^3", lambda: synth.laplacian_3d(50), (50, 50, 50)),
+                             ("knn26_3e4", lambda: synth.knn_graph_laplacian(30000, seed=3), None),
+                             ("knn26_3e5", lambda: synth.knn_graph_laplacian(300000, seed=4), None),
+                             ("lap2d_700^2", lambda: synth.laplacian_2d(700), (700, 700)),
+                             ("lap3d_100^3", lambda: synth.laplacian_3d(100), (100, 100, 100)),
+                             ("lap3d_160^3", None, (160, 160, 160))]:
+        A = A160 if make is None else make()
+        if dims is not None:
+            lmin, lmax = lap_bounds(dims)
+        else:
+            lmin, lmax = 0.1, 2.0 * float(np.max(np.diff(A.rowptr))) + 0.1
+        hi = plan160 if make is None else Plan.from_csr(A, p_block=4).upload(dev)
+        lo = Plan.from_csr(A, p_block=4, values="f32").upload(dev)
+        deg = int(min(256, max(16, np.ceil(1.2 * np.sqrt(lmax / lmin)))))
+        cat.append({"name": name, "n": A.n, "hi": hi, "lo": lo, "lmin": lmin, "lmax": lmax, "degree": deg,
+                    "x": synth.uniform_vector(A.n, 10), "b": synth.uniform_vector(A.n, 11)})
+    torch.cuda.synchronize()
+    log(f"serving: catalogue of {len(cat)} matrices planned in {time.perf_counter() - t0:.1f} s")
+
+    nreq = args.serve_requests
+    reqs = []
+    for i in range(nreq):
+        m = int(rng.integers(len(cat)))
+        if rng.random() < 0.75:
+            reqs.append(("apply", m, int(rng.integers(2, 11)), "f64" if rng.random() < 0.5 else "f32"))
+        else:
+            reqs.append(("solve", m))
+    total = sum(cat[r[1]]["n"] for r in reqs)
+    pinned = torch.empty(total + sum(c["n"] for c in cat) * 2, dtype=torch.float64, pin_memory=True).numpy()
+    at = 0
+    for c in cat:  # inputs in pinned host memory, shared read-only by the requests
+        for key in ("x", "b"):
+            pinned[at:at + c["n"]] = c[key]
+            c[key] = pinned[at:at + c["n"]]
+            at += c["n"]
+    outs = []
+    for r in reqs:
+        outs.append(pinned[at:at + cat[r[1]]["n"]])
+        at += cat[r[1]]["n"]
+
+    def submit(srv, i):
+        r, c = reqs[i], cat[reqs[i][1]]
+        if r[0] == "apply":
+            plan = c["hi"] if r[3] == "f64" else c["lo"]
+            return srv.submit_apply(plan, c["x"], r[2], permuted=False, last_only=True, Y=outs[i])
+        outs[i][:] = 0.0
+        return srv.submit_solve(c["hi"], c["lo"], c["b"], c["degree"], c["lmin"], c["lmax"], tol=1e-8,
+                                max_iter=400, x0=outs[i], permuted=False)
+
+    pool = args.serve_pool_gib << 30
+    # alone: one worker, one request at a time
+    check_idx = list(range(min(64, nreq)))
+    alone, ref = np.zeros(nreq), {}
+    srv = Server(workers=1, device_bytes=pool)
+    for i in range(nreq):
+        res = srv.wait(submit(srv, i))
+        alone[i] = res["latency_s"]
+        if i in check_idx:
+            ref[i] = outs[i].copy()
+        if reqs[i][0] == "solve" and res["relres"] > 1e-8:
+            raise RuntimeError(f"served solve {i} ended at relres {res['relres']:.3g}")
+    srv.close()
+    log(f"serving: {nreq} requests alone, {alone.sum():.2f} s of service, mean {alone.mean() * 1e3:.2f} ms")
+
+    rate = args.serve_load / alone.mean()
+    gaps = rng.exponential(1.0 / rate, size=nreq)
+    arrive = np.cumsum(gaps) - gaps[0]
+    srv = Server(workers=args.serve_workers, device_bytes=pool)
+    lat, queue = np.zeros(nreq), np.zeros(nreq)
+    tickets = [None] * nreq
+    import threading
+    submitted = threading.Semaphore(0)
+
+    failed = []
+
+    def waiter():
+        for i in range(nreq):
+            submitted.acquire()
+            if tickets[i] is None:  # the submitting loop stopped early
+                return
+            try:
+                res = srv.wait(tickets[i])
+            except Exception as e:  # re-raised on the main thread
+                failed.append(e)
+                continue
+            lat[i], queue[i] = res["latency_s"], res["queue_s"]
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t_start = time.perf_counter()
+    try:
+        for i in range(nreq):
+            delay = t_start + arrive[i] - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = submit(srv, i)
+            submitted.release()
+            if (i + 1) % 128 == 0:
+                log(f"serving: {i + 1} of {nreq} requests submitted")
+    finally:
+        submitted.release()  # lets the waiter see a missing ticket if the loop stopped early
+        th.join()
+        makespan = time.perf_counter() - t_start
+        srv.close()
+    if failed:
+        raise failed[0]
+    same = all(np.array_equal(ref[i], outs[i]) for i in check_idx)
+    if not same:
+        raise RuntimeError("served results differ from the same requests run alone")
+
+    def pct(v, q):
+        return round(float(np.percentile(v, q)) * 1e3, 3) if len(v) else None
+
+    kinds = np.array([r[0] for r in reqs])
+    by = {}
+    for k in ("apply", "solve"):
+        m = kinds == k
+        by[k] = {"count": int(m.sum()), "p50_ms": pct(lat[m], 50), "p99_ms": pct(lat[m], 99),
+                 "alone_p50_ms": pct(alone[m], 50), "alone_p99_ms": pct(alone[m], 99)}
+    slow = lat / alone
+    out = {
+        "workload": f"{nreq} requests, Poisson arrivals at {rate:.1f}/s ({args.serve_load:.2f} x the alone "
+                    f"service rate); matrices: " + ", ".join(f"{c['name']} (N={c['n']})" for c in cat) +
+                    "; 75% y_p = A^p x (p uniform 2..10, FP64 or FP32 values, y_p returned), 25% refinement "
+                    "solves to 1e-8 (FP32 Chebyshev corrections of degree min(256, 1.2 sqrt(kappa)))",
+        "workers": args.serve_workers, "pool_gib": args.serve_pool_gib,
+        "throughput_req_s": round(nreq / makespan, 2), "makespan_s": round(makespan, 3),
+        "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "queue_p50_ms": pct(queue, 50),
+        "by_kind": by,
+        "slowdown_vs_alone": {"p50": round(float(np.percentile(slow, 50)), 3),
+                              "p99": round(float(np.percentile(slow, 99)), 3)},
+        "alone_service_s": round(float(alone.sum()), 3),
+        "bitwise_same_as_alone": f"{len(check_idx)} sampled requests",
+        "note": "host buffers in pinned memory; latency = submit to result in host memory, PCIe copies "
+                "included; plans built once before the run (the plan cache)",
+    }
+    log(f"serving: {nreq / makespan:.1f} req/s, p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms "
+        f"(solves p50 {by['solve']['p50_ms']} / p99 {by['solve']['p99_ms']} ms)")
+    for c in cat:
+        del c["lo"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -85,6 +253,13 @@ def main():
     ap.add_argument("--no-solve", action="store_true", help="skip the refinement-solve latency measurement")
     ap.add_argument("--no-sweep", action="store_true", help="skip the p = 1..8 sweep")
     ap.add_argument("--solve-reps", type=int, default=10)
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-serving measurement")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-load", type=float, default=0.8,
+                    help="arrival rate as a fraction of the one-at-a-time service rate")
+    ap.add_argument("--serve-pool-gib", type=int, default=8)
+    ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--solve-degree", type=int, default=256)
     ap.add_argument("--only", choices=["both", "blocked", "plain"], default="both",
                     help="restrict the launches (for profiler runs)")
@@ -341,6 +516,12 @@ def main():
                                            "(continuously batched) solve is not built"}
         log(f"solve: mixed {mixed['p50_ms']:.1f} ms p50 ({mixed['corrections']} corrections), fp64 plain "
             f"{fp64_plain['p50_ms']:.1f} ms p50")
+    if not args.no_serve and args.only == "both":
+        out["serving"] = serving_bench(args, A, plan, dev)
+        sv = out["serving"]["by_kind"]["solve"]
+        out["solve_latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"],
+                                   "note": "served refinement solves to 1e-8 in the mixed request stream "
+                                           "(serving.workload), PCIe copies included"}
     if not args.no_cpu_baseline and args.only == "both":
         log("cpu baseline: FP64 oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(A, x, p, args.cpu_budget)

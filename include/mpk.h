@@ -25,9 +25,11 @@
  *     current device and hold FP64 values; they must not alias each other
  *     unless stated.  The caller owns every buffer it passes; the library
  *     owns only the plan object (host memory), released by mpk_destroy().
- *   - A plan may be used from one stream at a time (its launches share
- *     per-plan synchronisation counters).  Calls that overlap on two streams
- *     are not supported.
+ *   - Calls on one plan may overlap on several streams and host threads:
+ *     blocked (persistent) launches on one device are chained one after the
+ *     other by the library, whatever stream or plan issues them, and all
+ *     other launches use only caller buffers.  A device error raised by one
+ *     call may be reported by mpk_check_device on another call of the plan.
  *   - Indices are 0-based int32; n and nnz must be below 2^31.
  */
 #ifndef MPK_H
@@ -40,7 +42,8 @@
 extern "C" {
 #endif
 
-typedef struct mpk_plan_s* mpk_plan_t; /* opaque; owned by the library */
+typedef struct mpk_plan_s* mpk_plan_t;     /* opaque; owned by the library */
+typedef struct mpk_server_s* mpk_server_t; /* opaque; owned by the library */
 
 typedef enum {
     MPK_OK = 0,
@@ -60,6 +63,8 @@ typedef enum {
 #define MPK_STAGED 4u      /* the level-group wavefront of Sec. 3 (see
                               mpk_get_schedule): one launch per stage, same
                               per-row arithmetic; ignored with MPK_PLAIN       */
+#define MPK_LAST_POWER 8u  /* mpk_server_submit_apply only: Y receives y_p alone
+                              (n doubles) instead of all p powers                */
 
 /* polynomial kinds for poly_apply */
 #define MPK_POLY_MONOMIAL 0  /* phi_k = A^k                                     */
@@ -351,6 +356,60 @@ mpk_status mpk_plan_info(mpk_plan_t plan, int64_t* n, int64_t* nnz, int32_t* nle
 
 /* Releases the plan (not the caller's device buffers).  NULL is ignored. */
 void mpk_destroy(mpk_plan_t plan);
+
+/*
+ * ---- Request server ----------------------------------------------------
+ * Serves matrix power requests (mpk_apply) and refinement solves
+ * (mpk_refine_solve) submitted from host memory by any number of host
+ * threads, on the device that is current at mpk_server_create.  Each of
+ * `workers` threads owns a HIP stream and runs one request at a time: copy
+ * in, compute, copy out, mpk_check_device.  Requests are admitted in arrival
+ * order; the oldest waiting request starts as soon as a worker is free and
+ * its device memory fits in the server's pool of `device_bytes` (one
+ * allocation made here, sub-allocated first-fit with 256-byte alignment).
+ * Plans must stay alive and uploaded until their requests have been waited
+ * for.  Host buffers passed to a submit call belong to the caller but must
+ * stay valid, and unwritten by the caller, until mpk_server_wait returns for
+ * that ticket.  Results equal those of the same call made alone.
+ * Errors: MPK_ERR_ARG (null, bad scalar or flag), MPK_ERR_NOMEM (a request
+ * larger than the whole pool is refused at submit), MPK_ERR_HIP.
+ */
+mpk_status mpk_server_create(int32_t workers, size_t device_bytes, mpk_server_t* out);
+
+/*
+ * Queues Y(:, k-1) = y_k, k = 1..p, for x (host, n doubles) into Y (host,
+ * n x p column-major), as mpk_apply with `flags`; with MPK_LAST_POWER in
+ * flags, Y (n doubles) receives y_p only.  Device memory taken: n + n*p
+ * doubles plus mpk_work_bytes(plan, MPK_CALL_APPLY, p, flags).
+ * *ticket identifies the request for mpk_server_wait.
+ */
+mpk_status mpk_server_submit_apply(mpk_server_t server, mpk_plan_t plan, const double* x, int32_t p,
+                                   double* Y, uint32_t flags, int64_t* ticket);
+
+/*
+ * Queues mpk_refine_solve(hi, lo, degree, lmin, lmax, b, x, tol, max_iter,
+ * flags): b (host, n doubles) is the right-hand side, x (host, n doubles)
+ * holds the initial guess on entry and the solution when the request is
+ * done.  Device memory taken: 2n doubles plus
+ * mpk_work_bytes(lo, MPK_CALL_SOLVE, degree, flags).
+ */
+mpk_status mpk_server_submit_solve(mpk_server_t server, mpk_plan_t hi, mpk_plan_t lo, const double* b,
+                                   double* x, int32_t degree, double lmin, double lmax, double tol,
+                                   int32_t max_iter, uint32_t flags, int64_t* ticket);
+
+/*
+ * Blocks until request `ticket` is done and releases it (a ticket may be
+ * waited for once).  *status receives the request's own status (its message
+ * is then available from mpk_last_error on this thread); latency_s is the
+ * time from submit to completion, queue_s the time spent waiting for
+ * admission; iters and relres are the solve's (0 for applies).  Any output
+ * pointer may be NULL.  Returns MPK_ERR_ARG for an unknown ticket.
+ */
+mpk_status mpk_server_wait(mpk_server_t server, int64_t ticket, mpk_status* status, double* latency_s,
+                           double* queue_s, int32_t* iters, double* relres);
+
+/* Finishes every queued request, joins the workers and frees the pool. */
+void mpk_server_destroy(mpk_server_t server);
 
 #ifdef __cplusplus
 }

@@ -25,13 +25,14 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
 #include "../../include/mpk.h"
+#include "internal.h"
 #include "planner.h"
 
-#define MPK_API extern "C" __attribute__((visibility("default")))
 
 namespace {
 
@@ -567,6 +568,8 @@ mpk_status fail(mpk_status s, const char* fmt, ...) {
     return s;
 }
 
+void set_error_text(const char* msg) { g_err = msg; }
+
 #define HIP_TRY(expr)                                                                   \
     do {                                                                                \
         hipError_t e_ = (expr);                                                         \
@@ -623,7 +626,8 @@ struct mpk_plan_s {
     int q_eff[3][2] = {};    // powers per launch meeting the deadlock bound
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
-    std::vector<std::vector<mpk::StageTask>> sched;  // wavefront schedule per q (lazy)
+    std::vector<std::vector<mpk::StageTask>> sched;  // wavefront schedule per q (lazy, under mu)
+    std::mutex mu;
 };
 
 namespace {
@@ -708,8 +712,26 @@ mpk_status check_uploaded(mpk_plan_t p) {
     return MPK_OK;
 }
 
+// Blocked launches run one at a time per device, whatever stream or plan they
+// come from: a persistent kernel needs enough of its waves resident together,
+// and two at once could each hold part of the GPU while waiting for the rest.
+// Each launch waits for an event recorded after the previous one; all other
+// work keeps overlapping.
+struct BlockedChain {
+    std::mutex mu;
+    hipEvent_t last = nullptr;
+    bool recorded = false;
+};
+BlockedChain g_chain[16];
+
 // Launches the blocked kernel for powers base+1 .. base+q.
 mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, BlockArgs a) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    BlockedChain& ch = g_chain[dev & 15];
+    std::lock_guard<std::mutex> lk(ch.mu);
+    if (!ch.last) HIP_TRY(hipEventCreateWithFlags(&ch.last, hipEventDisableTiming));
+    if (ch.recorded) HIP_TRY(hipStreamWaitEvent(st, ch.last, 0));
     if (p->epoch + 1 >= kEpochLimit) {  // restart the done words from zero
         const int64_t nc = (int64_t)std::max<int32_t>(1, p->H.nchunks) * kFlagStride;
         fill_u32_kernel<<<grid_1d(nc), 256, 0, st>>>(p->D.done, nc, 0u);
@@ -727,6 +749,8 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
     hipLaunchKernelGGL(fn, dim3(p->grid_block[kind][poly]),
                        dim3(kBlockThreads), 0, st, a);
     HIP_TRY(hipGetLastError());
+    HIP_TRY(hipEventRecord(ch.last, st));
+    ch.recorded = true;
     return MPK_OK;
 }
 
@@ -766,7 +790,7 @@ double* job_dest(const PowerJob& j, int k) { return j.out0 + (int64_t)((k - 1) %
 const double* job_vec(const PowerJob& j, int k) { return k == 0 ? j.x : job_dest(j, k); }
 
 const std::vector<mpk::StageTask>& schedule(mpk_plan_t p, int q) {
-    if (p->sched.size() <= (size_t)q) p->sched.resize(q + 1);
+    std::lock_guard<std::mutex> lk(p->mu);  // sched is sized at plan creation: no reallocation
     if (p->sched[q].empty()) p->sched[q] = mpk::wavefront_schedule(p->H, q);
     return p->sched[q];
 }
@@ -898,6 +922,16 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
 }  // namespace
 
 // =================================================================== C ABI
+mpk_status mpk::set_error(mpk_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    set_error_text(buf);
+    return s;
+}
+
 MPK_API void mpk_options_default(mpk_options* opt) {
     if (opt) memset(opt, 0, sizeof *opt);
 }
@@ -939,6 +973,7 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
     mpk_plan_s* p = new (std::nothrow) mpk_plan_s;
     if (!p) return fail(MPK_ERR_NOMEM, "out of host memory");
     try {
+        p->sched.resize(mpk::kMaxBlock + 1);
         p->H.root_mode = o.root_mode;
         p->H.root = o.root;
         p->H.p_block = o.p_block ? o.p_block : 4;

@@ -16,6 +16,7 @@ LIB_PATH = os.path.join(_HERE, "libmpk.so")
 MPK_IO_PERMUTED = 1
 MPK_PLAIN = 2
 MPK_STAGED = 4
+MPK_LAST_POWER = 8  # server applies: return y_p only
 VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}  # bf16: BF16 values with a per-row FP32 scale
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
 CALL_APPLY, CALL_POLY, CALL_SSTEP, CALL_SOLVE = 0, 1, 2, 3
@@ -29,7 +30,9 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_get_levels", "mpk_get_partition", "mpk_get_deps", "mpk_min_workers",
            "mpk_upload", "mpk_work_bytes", "mpk_apply", "poly_apply", "sstep_basis", "mpk_refine_solve",
            "mpk_get_schedule",
-           "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy"]
+           "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy",
+           "mpk_server_create", "mpk_server_submit_apply", "mpk_server_submit_solve",
+           "mpk_server_wait", "mpk_server_destroy"]
 
 
 class MPKError(RuntimeError):
@@ -83,6 +86,13 @@ def _load():
         "mpk_check_device": (I32, [P, P]),
         "mpk_plan_info": (I32, [P, pI64, pI64, pI32, pI32, pI64, pI32, pI32, pI32]),
         "mpk_destroy": (None, [P]),
+        "mpk_server_create": (I32, [I32, SZ, ctypes.POINTER(P)]),
+        "mpk_server_submit_apply": (I32, [P, P, P, I32, P, U32, pI64]),
+        "mpk_server_submit_solve": (I32, [P, P, P, P, P, I32, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                          I32, U32, pI64]),
+        "mpk_server_wait": (I32, [P, I64, pI32, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double), pI32, ctypes.POINTER(ctypes.c_double)]),
+        "mpk_server_destroy": (None, [P]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -308,3 +318,77 @@ class Plan:
     def check(self, stream=None):
         """Synchronises and raises MPKError if a blocked launch reported a failure."""
         _check(_lib.mpk_check_device(self._h, _stream(stream)))
+
+
+class Server:
+    """Request server on the current device: host-memory MPK applications and
+    refinement solves, run by ``workers`` threads with a stream each and
+    admitted in arrival order against a device pool of ``device_bytes``."""
+
+    def __init__(self, workers=4, device_bytes=1 << 30):
+        h = ctypes.c_void_p()
+        _check(_lib.mpk_server_create(int(workers), int(device_bytes), ctypes.byref(h)))
+        self._h = h
+        self._keep = {}  # ticket -> host arrays and plans the request uses
+
+    def __del__(self):
+        self.close()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.mpk_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    @staticmethod
+    def _host(a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        return a
+
+    def submit_apply(self, plan, x, p, permuted=True, plain=False, staged=False, last_only=False, Y=None):
+        """Queues y_1..y_p of host vector x (y_p alone with ``last_only``) into
+        ``Y`` (a new (p, n) or (n,) float64 array if None); returns the ticket."""
+        x = self._host(x)
+        shape = (x.shape[0],) if last_only else (p, x.shape[0])  # row k-1 holds y_k
+        if Y is None:
+            Y = np.empty(shape, dtype=np.float64)
+        if Y.shape != shape or Y.dtype != np.float64 or not Y.flags.c_contiguous:
+            raise ValueError(f"Y must be a C-contiguous float64 array of shape {shape}")
+        flags = Plan._flags(permuted, plain, staged) | (MPK_LAST_POWER if last_only else 0)
+        t = ctypes.c_int64()
+        _check(_lib.mpk_server_submit_apply(self._h, plan._h, _ptr(x), int(p), _ptr(Y), flags, ctypes.byref(t)))
+        self._keep[t.value] = (plan, x, Y)
+        return t.value
+
+    def submit_solve(self, hi, lo, b, degree, lmin, lmax, tol=1e-10, max_iter=1000, x0=None, permuted=True,
+                     plain=False, staged=False):
+        """Queues a refinement solve of A x = b (host vectors); ``x0`` (zeros if
+        None) is the initial guess and receives the solution.  Returns the ticket."""
+        b = self._host(b)
+        x = np.zeros_like(b) if x0 is None else x0
+        if x.shape != b.shape or x.dtype != np.float64 or not x.flags.c_contiguous:
+            raise ValueError("x0 must be a C-contiguous float64 array shaped like b (overwritten by the solution)")
+        t = ctypes.c_int64()
+        _check(_lib.mpk_server_submit_solve(self._h, hi._h, lo._h, _ptr(b), _ptr(x), int(degree), float(lmin),
+                                            float(lmax), float(tol), int(max_iter),
+                                            Plan._flags(permuted, plain, staged), ctypes.byref(t)))
+        self._keep[t.value] = (hi, lo, b, x)
+        return t.value
+
+    def wait(self, ticket):
+        """Waits for a request.  Returns a dict with the result ("Y": p x n for an
+        apply, "x" for a solve), "latency_s", "queue_s", "iters", "relres";
+        raises MPKError if the request failed."""
+        st = ctypes.c_int32()
+        lat, qs, rel = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        it = ctypes.c_int32()
+        _check(_lib.mpk_server_wait(self._h, int(ticket), ctypes.byref(st), ctypes.byref(lat), ctypes.byref(qs),
+                                    ctypes.byref(it), ctypes.byref(rel)))
+        keep = self._keep.pop(int(ticket))
+        _check(st.value)
+        out = {"latency_s": lat.value, "queue_s": qs.value, "iters": it.value, "relres": rel.value}
+        if len(keep) == 3:
+            out["Y"] = keep[2]
+        else:
+            out["x"] = keep[3]
+        return out

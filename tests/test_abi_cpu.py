@@ -240,3 +240,20 @@ def test_schedule_argument_errors():
     assert lib.mpk_get_schedule(plan._h, 16, ctypes.byref(nt), ctypes.byref(ng), None) == -1
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, cache_mib=-1)[0] == -1
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, min_group_rows=-2)[0] == -1
+
+
+def test_server_argument_errors_without_gpu():
+    lib = M.lib()
+    h = ctypes.c_void_p()
+    assert lib.mpk_server_create(0, 1 << 20, ctypes.byref(h)) == -1       # no workers
+    assert lib.mpk_server_create(65, 1 << 20, ctypes.byref(h)) == -1      # too many workers
+    assert lib.mpk_server_create(2, 16, ctypes.byref(h)) == -1            # pool below one alignment unit
+    assert lib.mpk_server_create(2, 1 << 20, None) == -1
+    plan = M.Plan.from_csr(S.laplacian_2d(8))
+    x = np.ones(64)
+    t = ctypes.c_int64()
+    assert lib.mpk_server_submit_apply(None, plan._h, M._ptr(x), 2, M._ptr(x), 1, ctypes.byref(t)) == -1
+    assert lib.mpk_server_submit_solve(None, plan._h, plan._h, M._ptr(x), M._ptr(x), 4, 0.1, 8.0, 1e-10, 10,
+                                       1, ctypes.byref(t)) == -1
+    assert lib.mpk_server_wait(None, 1, None, None, None, None, None) == -1
+    lib.mpk_server_destroy(None)  # no-op
