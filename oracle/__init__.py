@@ -35,6 +35,10 @@ sparse iterative solvers on multi-core CPUs"):
 * ``group_levels``, ``wavefront_schedule``, ``validate_schedule``,
   ``run_schedule``                  -- Sec. 3 (level groups from the cache size
   and the skewed wavefront over them), readings R14 and R15
+* ``leja_order``, ``newton_shifts``, ``cholqr_truncated``, ``sstep_cycle``,
+  ``sstep_gmres``                   -- Sec. 4 (s-step GMRES, Alg. 3a/3c: Newton
+  basis, BOrtho, TSQR) with the right polynomial preconditioner of Sec. 5,
+  readings R17-R19
 
 Parity status of each function is stated in its docstring.  The readings
 taken where the paper is silent are listed in ``mpk_oracle.READINGS``.

@@ -10,6 +10,7 @@ and unique within a row), vectors are float64 NumPy arrays.
 Parity status
 -------------
 pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_coeffs, refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
+         leja_order, chebyshev_scale, newton_shifts, cholqr_truncated, sstep_cycle, sstep_gmres,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
          hop_min, window_ok, min_workers,
@@ -24,6 +25,7 @@ unpinned the choice of chunk-to-XCD ownership and the execution order are this
          write order, deadlock freedom, bitwise equality with the plain
          MPK) is pinned, not their identity with the paper's library.
 """
+import math
 from collections import deque
 
 import numpy as np
@@ -91,6 +93,31 @@ READINGS = {
            "s_i = fl32(max_j |a_ij|) (1 for an all-zero row) and q_ij the BF16 value "
            "nearest (ties to even) to fl32(a_ij / s_i); the product is formed exactly in "
            "FP64 and the MPK is the FP64 MPK of the matrix of those products.",
+    "R17": "s-step GMRES (Sec. 4, Alg. 3a/3c) with right polynomial preconditioning "
+           "(Sec. 5): operator M = A s(A), s of R12, x = x_0 + s(A) Q y. A restart cycle "
+           "starts from r = b - A x, q_0 = r / ||r||, and builds blocks of "
+           "sb = min(s, m - c) vectors: Newton basis W_0 = q_c, W_k = (M - lambda_k I) "
+           "W_{k-1} / sigma_k; BOrtho is one classical Gram-Schmidt sweep "
+           "(R_prev = Q^T W, W' = W - Q R_prev); TSQR is Cholesky QR of W' (G = W'^T W' "
+           "= R^T R, Q_new = W' R^{-1}); column j is dependent when its squared pivot is "
+           "not above 2^-48 (||R_prev[:, j]||^2 + G_jj), and the block then keeps its "
+           "first j columns and ends the cycle with a square Hessenberg matrix (the "
+           "Krylov space is invariant to working accuracy). The Hessenberg columns come "
+           "from M W_{0..sb-1} = W_{0..sb} B (B bidiagonal: lambda on the diagonal, "
+           "sigma below) and the triangular change of basis W = Q R. After each block the "
+           "least-squares residual of min ||beta e_0 - H y|| is compared with tol ||b|| "
+           "(the convergence check of Alg. 3c); the cycle ends there, at a dependent "
+           "column, or after m columns.",
+    "R18": "Newton shifts: for A with spectrum in [lmin, lmax], M's spectrum lies in "
+           "[1 - eps, 1 + eps], eps = 1 / T_d(theta / delta) (from R12). The paper takes "
+           "the shifts from Ritz values of a few standard GMRES steps; here they are the "
+           "s Chebyshev points 1 + eps cos(pi (2i + 1) / (2s)) of that interval in Leja "
+           "order (first the largest modulus, then the largest product of distances to "
+           "the points taken; ties to the lowest index), every column scaled by "
+           "sigma = eps / 2, so no Arnoldi run is needed.",
+    "R19": "The solve stops when the FP64 residual at the start of a cycle satisfies "
+           "||b - A x|| <= tol ||b|| or after max_cycles cycles; with reduced-precision "
+           "values (R11) only the basis and the preconditioner use the rounded matrix.",
     "R11": "Reduced-precision matrix storage (the paper works in FP64 only): each stored "
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
@@ -281,6 +308,165 @@ def refine_solve(A, b, x0, d, lmin, lmax, tol, max_iter, values=np.float32):
             break
         x = x + poly_chebyshev(Alo, r, c, theta, delta)
     return x, hist
+
+
+# --------------------------------------------------------------------------- #
+# Sec. 4 (s-step GMRES, Alg. 3a and 3c) with the right polynomial
+# preconditioner of Sec. 5 (readings R17-R19)
+# --------------------------------------------------------------------------- #
+def leja_order(points):
+    """Reading R18: Leja order.  The first point has the largest modulus; each next
+    one maximises the product of its distances to the points already taken.  Ties go
+    to the lowest index.  Returns the reordered array."""
+    pts = [float(v) for v in points]
+    left = list(range(len(pts)))
+    out = []
+    while left:
+        best, best_val = None, -1.0
+        for i in left:
+            if out:
+                val = 1.0
+                for z in out:
+                    val *= abs(pts[i] - z)
+            else:
+                val = abs(pts[i])
+            if val > best_val:
+                best, best_val = i, val
+        out.append(pts[best])
+        left.remove(best)
+    return np.array(out)
+
+
+def chebyshev_scale(d, lmin, lmax):
+    """T_d(theta/delta) for theta, delta of [lmin, lmax] (theta/delta > 1):
+    cosh(d arccosh(theta/delta))."""
+    theta, delta = 0.5 * (lmax + lmin), 0.5 * (lmax - lmin)
+    return math.cosh(d * math.acosh(theta / delta))
+
+
+def newton_shifts(s, d, lmin, lmax):
+    """Reading R18: the spectrum of M = A s(A) (s of R12, A SPD with spectrum in
+    [lmin, lmax]) lies in [1 - eps, 1 + eps], eps = 1 / T_d(theta/delta).  The shifts
+    are the s Chebyshev points 1 + eps cos(pi (2i + 1) / (2s)) of that interval in Leja
+    order, and every column is scaled by sigma = eps / 2.  Returns (lambdas, sigmas)."""
+    eps = 1.0 / chebyshev_scale(d, lmin, lmax)
+    i = np.arange(s)
+    pts = 1.0 + eps * np.cos(np.pi * (2 * i + 1) / (2 * s))
+    return leja_order(pts), np.full(s, 0.5 * eps)
+
+
+def cholqr_truncated(G, wnorm2, eta=2.0 ** -24):
+    """Reading R17, TSQR as Cholesky QR: the upper triangular R with G = R^T R, column
+    by column.  Column j is dependent when its squared pivot G_jj - sum_{l<j} R_lj^2 is
+    not above eta^2 * wnorm2[j] (or not finite); then R's column j holds its rows
+    0..j-1 only and the factorisation stops.  Returns (R, kept columns)."""
+    s = G.shape[0]
+    R = np.zeros((s, s))
+    for j in range(s):
+        for i in range(j):
+            R[i, j] = (G[i, j] - sum(R[l, i] * R[l, j] for l in range(i))) / R[i, i]
+        piv2 = G[j, j] - sum(R[l, j] ** 2 for l in range(j))
+        if not (math.isfinite(piv2) and piv2 > eta * eta * wnorm2[j]):
+            return R, j
+        R[j, j] = math.sqrt(piv2)
+    return R, s
+
+
+def sstep_cycle(apply_M, q0, m, s, lambdas, sigmas, beta, target):
+    """One restart cycle of s-step GMRES (Alg. 3c, reading R17) on the operator
+    ``apply_M``, from the unit vector q0 = r / beta.  Blocks of sb = min(s, m - c)
+    vectors: W_0 = q_c, W_k = (M - lambda_k I) W_{k-1} / sigma_k (the Newton basis of
+    Sec. 4); BOrtho, one classical Gram-Schmidt sweep R_prev = Q^T W, W' = W - Q R_prev;
+    TSQR, Cholesky QR of W' with truncation at a dependent column; the new Hessenberg
+    columns from the change of basis; the least-squares residual is checked after every
+    block (Alg. 3c's convergence check) against ``target``.
+    Returns (Q, H, y, rho): Q (k+1 or k vectors), H, the least-squares solution y of
+    min ||beta e_0 - H y|| and its residual rho."""
+    n = q0.size
+    Q = [np.asarray(q0, dtype=np.float64)]
+    H = np.zeros((1, 0))
+    c = 0
+    while True:
+        sb = min(s, m - c)
+        W = [Q[c]]
+        for k in range(1, sb + 1):
+            W.append((apply_M(W[k - 1]) - lambdas[k - 1] * W[k - 1]) / sigmas[k - 1])
+        Qm = np.array(Q)                      # (c+1, n)
+        Wm = np.array(W[1:])                  # (sb, n)
+        R_prev = Qm @ Wm.T                    # BOrtho: (c+1, sb)
+        Wp = Wm - R_prev.T @ Qm
+        G = Wp @ Wp.T                         # TSQR by Cholesky QR
+        wnorm2 = (R_prev ** 2).sum(axis=0) + np.diag(G)
+        R_new, kk = cholqr_truncated(G, wnorm2)
+        dep = kk < sb
+        for j in range(kk):                   # Q_new = W'[:, :kk] R_new[:kk, :kk]^{-1}
+            v = Wp[j] - sum(R_new[i, j] * Q[c + 1 + i] for i in range(j))
+            Q.append(v / R_new[j, j])
+        nh = kk + (1 if dep else 0)           # new Hessenberg columns
+        rows = c + kk + 1                     # Q vectors now held
+        # W_0..W_nh in the basis Q_0..Q_{rows-1}
+        Rfull = np.zeros((rows, nh + 1))
+        Rfull[c, 0] = 1.0
+        for i in range(1, nh + 1):
+            Rfull[: c + 1, i] = R_prev[:, i - 1]
+            top = min(i, kk)
+            Rfull[c + 1: c + 1 + top, i] = R_new[:top, i - 1]
+        B = np.zeros((nh + 1, nh))            # M W_{0..nh-1} = W_{0..nh} B
+        for i in range(nh):
+            B[i, i] = lambdas[i]
+            B[i + 1, i] = sigmas[i]
+        Rk_top = Rfull[:c, :nh]
+        Rk_bot = Rfull[c: c + nh, :nh]
+        rhs = Rfull @ B
+        if c > 0:
+            rhs[: c + 1] -= H[: c + 1, :c] @ Rk_top
+        Hnew = np.zeros((rows, c + nh))
+        Hnew[: H.shape[0], :c] = H[:, :c]
+        Hnew[:, c:] = np.linalg.solve(Rk_bot.T, rhs.T).T
+        H = Hnew
+        c += nh
+        e0 = np.zeros(H.shape[0])
+        e0[0] = beta
+        y = np.linalg.lstsq(H, e0, rcond=None)[0] if c > 0 else np.zeros(0)
+        rho = float(np.linalg.norm(e0 - H @ y)) if c > 0 else beta
+        if dep or c >= m or rho <= target:
+            return Q[:max(c, 1)], H, y, rho
+
+
+def sstep_gmres(A, b, x0, s, m, d, lmin, lmax, tol, max_cycles, values=None):
+    """s-step GMRES (Alg. 3a with Alg. 3c, Sec. 4) on A s(A) u = b, x = s(A) u (right
+    preconditioning, Sec. 5), s the degree d - 1 Chebyshev polynomial of R12, so one
+    application of the operator costs d powers.  Restart length m (blocks of s);
+    shifts of R18; each cycle starts from the FP64 residual r = b - A x with the
+    unrounded matrix and stops the solve when ||r|| <= tol ||b|| or after max_cycles
+    cycles (reading R19).  With ``values`` (e.g. np.float32) the basis and the
+    preconditioner use the matrix rounded to that type (R11).
+    Returns (x, true relative residual at the start of every cycle and at the end,
+    number of Hessenberg columns built)."""
+    Alo = A if values is None else round_values(A, values)
+    c, theta, delta = chebyshev_inverse_coeffs(d, lmin, lmax)
+    lambdas, sigmas = newton_shifts(s, d, lmin, lmax)
+
+    def apply_M(v):                          # A P^{-1} v
+        return spmv(Alo, poly_chebyshev(Alo, v, c, theta, delta))
+
+    b = np.asarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64)
+    nb = float(np.linalg.norm(b))
+    hist, iters = [], 0
+    for cyc in range(max_cycles + 1):
+        r = b - spmv(A, x)
+        beta = float(np.linalg.norm(r))
+        hist.append(beta / nb if nb > 0 else beta)
+        if hist[-1] <= tol or cyc == max_cycles or beta == 0.0:
+            break
+        Q, H, y, rho = sstep_cycle(apply_M, r / beta, m, s, lambdas, sigmas, beta, tol * nb)
+        iters += H.shape[1]
+        z = np.zeros_like(x)
+        for j in range(y.size):
+            z = z + y[j] * Q[j]
+        x = x + poly_chebyshev(Alo, z, c, theta, delta)
+    return x, hist, iters
 
 
 def chebyshev_basis(A, x, d, theta, delta):
