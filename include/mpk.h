@@ -323,6 +323,56 @@ mpk_status mpk_refine_solve(mpk_plan_t hi, mpk_plan_t lo, int32_t degree, double
                             void* work, size_t work_bytes, int32_t* iters_out, double* relres_out,
                             void* stream);
 
+/*
+ * Solve A x = b by restarted s-step GMRES (Sec. 4: Alg. 3a around the subspace
+ * routine of Alg. 3c) with the degree-d Chebyshev polynomial preconditioner
+ * applied from the right (Sec. 5: A P^{-1} u = b, x = P^{-1} u):
+ *   P^{-1} = s(A), s of degree d - 1 as in mpk_refine_solve, so the operator
+ *   M = A s(A) = I - T_d((theta I - A)/delta) / T_d(theta/delta) costs d
+ *   matrix powers per vector (one poly_apply launch on `lo`);
+ *   each restart cycle starts from r = b - A x computed with `hi` (FP64
+ *   values) and stops the solve when ||r||_2 <= tol ||b||_2 or after
+ *   max_cycles cycles;
+ *   a cycle builds at most m basis vectors in blocks of s: the Newton basis
+ *   W_k = (M - lambda_k I) W_{k-1} / sigma_k from the block's first vector,
+ *   with lambda_k the s Chebyshev points of [1 - eps, 1 + eps] (M's spectrum
+ *   when A's lies in [lmin, lmax]; eps = 1 / T_d(theta/delta)) in Leja order
+ *   and sigma_k = eps / 2; BOrtho, one block classical Gram-Schmidt sweep
+ *   against the previous vectors; TSQR, a Cholesky QR of the block in FP64,
+ *   which ends the cycle at a column whose Cholesky pivot is at most 2^-24
+ *   of its length before BOrtho (the Krylov space is then invariant); the
+ *   Hessenberg matrix follows from the change of basis and the small least-
+ *   squares problem is solved on the host after every block, ending the
+ *   cycle when its residual is at most tol ||b||;
+ *   x += s(A) Q y at the end of a cycle.
+ * The shifts need no Arnoldi run (the paper takes them from Ritz values);
+ * they assume a symmetric positive definite A with spectrum in [lmin, lmax].
+ * hi and lo: uploaded plans of the same matrix and level order (lo may be hi,
+ * or a plan with FP32 values for a mixed-precision solve: then the basis and
+ * the preconditioner use the rounded matrix and the residuals stay FP64).
+ * s in 1..16, m in s..256, d in 1..4096.  b and x are device vectors of n
+ * entries (perm space with MPK_IO_PERMUTED); x holds the initial guess on
+ * entry and the result on return.  work: device, 256-byte aligned,
+ * mpk_sstep_gmres_work_bytes(lo, s, m, d, flags) bytes.  iters_out (basis
+ * vectors built over all cycles), cycles_out and relres_out (the last
+ * ||r||/||b||, or ||r|| when b = 0) are host pointers and may be NULL.
+ * MPK_PLAIN / MPK_STAGED select the executor of the polynomial launches.
+ * The call synchronises `stream` twice per block and once per cycle; sums are
+ * reduced in a fixed order, so repeated calls give identical results.
+ * Errors: MPK_ERR_ARG (hi not FP64, plans of different matrices, s, m or d
+ * out of range, not 0 < lmin < lmax, tol < 0, max_cycles < 0, null pointers,
+ * work too small or misaligned), MPK_ERR_STATE, MPK_ERR_HIP, MPK_ERR_NOMEM.
+ */
+mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, double lmin,
+                           double lmax, const double* b, double* x, double tol, int32_t max_cycles,
+                           uint32_t flags, void* work, size_t work_bytes, int32_t* iters_out,
+                           int32_t* cycles_out, double* relres_out, void* stream);
+
+/* Device work bytes that mpk_sstep_gmres needs for these arguments (n, s, m, d
+ * and MPK_IO_PERMUTED in flags).  Errors: MPK_ERR_ARG. */
+mpk_status mpk_sstep_gmres_work_bytes(mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, uint32_t flags,
+                                      size_t* bytes);
+
 mpk_status sstep_basis(mpk_plan_t plan, int32_t s, const double* lambda, const double* sigma,
                        const double* v, double* V, int64_t ldv, uint32_t flags, void* work,
                        size_t work_bytes, void* stream);

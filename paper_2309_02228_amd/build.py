@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpk.so")
 SOURCES = [os.path.join(HERE, "csrc", "planner.cpp"), os.path.join(HERE, "csrc", "mpk.hip"),
-           os.path.join(HERE, "csrc", "server.cpp")]
+           os.path.join(HERE, "csrc", "server.cpp"), os.path.join(HERE, "csrc", "gmres.hip")]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "-fvisibility=hidden",
     "--offload-arch=gfx950",

@@ -1,0 +1,592 @@
+// s-step GMRES (Sec. 4, Alg. 3a with the subspace routine of Alg. 3c) with a right
+// Chebyshev polynomial preconditioner (Sec. 5), on one MI355X.
+//
+// The operator is M = A s(A), s the degree d - 1 Chebyshev interpolant of 1/lambda
+// on [lmin, lmax]; its residual polynomial gives M = I - T_d((theta I - A)/delta) /
+// T_d(theta/delta), so one Newton basis step (M - lambda_k I) v / sigma_k is a single
+// Chebyshev polynomial of degree d in A with two nonzero coefficients, run as one
+// blocked matrix power launch of d powers (poly_apply).  The orthogonalisation is
+// one block classical Gram-Schmidt sweep (BOrtho) and a Cholesky QR (TSQR), both in
+// FP64; the Hessenberg matrix is rebuilt from the change of basis on the host.
+//
+// Device work per block of s vectors: s polynomial launches, two tall-skinny Gram
+// products (Q^T W, then W'^T W') and two linear combinations (W - Q R_prev, then
+// W' R^{-1}).  The Gram products stream their operands once, coalesced (a row per
+// lane), and their partial sums are added in a fixed order, so a solve is
+// deterministic.  Small matrices travel between host and device with one
+// synchronisation per Gram product.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "internal.h"
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxParts = 1024;     // row blocks of a Gram product
+constexpr int kMaxS = 16;           // vectors per block
+constexpr int kMaxM = 256;          // restart length
+constexpr int kMaxC = (kMaxM + 1) * kMaxS;  // coefficients of a linear combination
+constexpr double kEta = 1.0 / 16777216.0;   // 2^-24: the dependent-column threshold
+
+// ------------------------------------------------------------------ kernels
+// Sum over the 64 lanes of a wave of 64 values per lane by recursive halving: at
+// distance w each lane keeps the half of its values selected by its lane bit w and
+// receives the partner's copy of that half.  Lane L ends with the total of value L.
+template <int W>
+__device__ __forceinline__ void halve(double* v, int lane) {
+    const bool hi = lane & W;
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+        const double send = hi ? v[i] : v[i + W];
+        const double keep = hi ? v[i + W] : v[i];
+        v[i] = keep + __shfl_xor(send, W);
+    }
+}
+
+// part[rb][j][k] = sum over rows r of block rb of X[j][r] * Y[k][r], j < a, k < b.
+// A workgroup covers one row block and one JB x KB tile; workgroups of the same row
+// block sit on the same XCD (workgroup i runs on XCD i mod 8), so the tiles re-read
+// each other's rows from that XCD's L2.
+template <int JB, int KB>
+__global__ __launch_bounds__(kThreads) void gram_partial_kernel(const double* __restrict__ X, int64_t ldx, int a,
+                                                                const double* __restrict__ Y, int64_t ldy, int b,
+                                                                int n, int rows_per_blk, int nrb, int ntj, int ntk,
+                                                                double* __restrict__ part) {
+    const int tiles = ntj * ntk;
+    const int id = blockIdx.x, xcd = id & 7, loc = id >> 3;
+    const int rb = (loc / tiles) * 8 + xcd;
+    const int tile = loc % tiles;
+    if (rb >= nrb) return;
+    const int j0 = (tile % ntj) * JB, k0 = (tile / ntj) * KB;
+    double acc[JB * KB];
+#pragma unroll
+    for (int e = 0; e < JB * KB; ++e) acc[e] = 0.0;
+    const int r0 = rb * rows_per_blk;
+    const int r1 = min(n, r0 + rows_per_blk);
+    for (int r = r0 + (int)threadIdx.x; r < r1; r += kThreads) {
+        double xv[JB], yv[KB];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) xv[j] = (j0 + j < a) ? __builtin_nontemporal_load(X + (j0 + j) * ldx + r) : 0.0;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) yv[k] = (k0 + k < b) ? Y[(k0 + k) * ldy + r] : 0.0;
+#pragma unroll
+        for (int j = 0; j < JB; ++j)
+#pragma unroll
+            for (int k = 0; k < KB; ++k) acc[j * KB + k] = fma(xv[j], yv[k], acc[j * KB + k]);
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ double red[kThreads / 64][64];
+    if constexpr (JB * KB == 64) {
+        halve<32>(acc, lane);
+        halve<16>(acc, lane);
+        halve<8>(acc, lane);
+        halve<4>(acc, lane);
+        halve<2>(acc, lane);
+        halve<1>(acc, lane);
+        red[wave][lane] = acc[0];
+    } else {
+#pragma unroll
+        for (int e = 0; e < JB * KB; ++e)
+            for (int off = 32; off > 0; off >>= 1) acc[e] += __shfl_xor(acc[e], off);
+        if (lane < JB * KB) {
+#pragma unroll
+            for (int e = 0; e < JB * KB; ++e)
+                if (e == lane) red[wave][lane] = acc[e];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < JB * KB) {
+        const int e = threadIdx.x, j = e / KB, k = e % KB;
+        double sum = 0.0;
+#pragma unroll
+        for (int w = 0; w < kThreads / 64; ++w) sum += red[w][e];
+        if (j0 + j < a && k0 + k < b) part[((int64_t)rb * a + j0 + j) * b + k0 + k] = sum;
+    }
+}
+
+// out[e] = sum over row blocks, in order, of part[rb][e], e < count.
+__global__ void reduce_parts_kernel(const double* __restrict__ part, int nrb, int count, double* __restrict__ out) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= count) return;
+    double s = 0.0;
+    for (int rb = 0; rb < nrb; ++rb) s += part[(int64_t)rb * count + e];
+    out[e] = s;
+}
+
+// Y[k][r] = alpha X0[k][r] + sum_{j < a} Q[j][r] C[j b + k], k < b <= KB.
+// Y may be X0 (elementwise update in place) or, with a == 1 and b == 1, Q itself.
+template <int KB>
+__global__ __launch_bounds__(kThreads) void lincomb_kernel(const double* X0, int64_t ldx0, double alpha,
+                                                           const double* Q, int64_t ldq, int a,
+                                                           const double* __restrict__ C, int b, double* Y,
+                                                           int64_t ldy, int n) {
+    __shared__ double cs[kMaxC];
+    for (int e = threadIdx.x; e < a * b; e += kThreads) cs[e] = C[e];
+    __syncthreads();
+    for (int r = blockIdx.x * kThreads + threadIdx.x; r < n; r += gridDim.x * kThreads) {
+        double acc[KB];
+#pragma unroll
+        for (int k = 0; k < KB; ++k) acc[k] = (k < b && X0) ? alpha * X0[k * ldx0 + r] : 0.0;
+        for (int j = 0; j < a; ++j) {
+            const double q = Q[j * ldq + r];
+#pragma unroll
+            for (int k = 0; k < KB; ++k)
+                if (k < b) acc[k] = fma(q, cs[j * b + k], acc[k]);
+        }
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+            if (k < b) Y[k * ldy + r] = acc[k];
+    }
+}
+
+// r = b - t
+__global__ void sub_kernel(const double* __restrict__ b, const double* __restrict__ t, double* __restrict__ r, int n) {
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) r[i] = b[i] - t[i];
+}
+
+int grid_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(8192, (n + kThreads - 1) / kThreads)); }
+
+// ------------------------------------------------------------ host helpers
+struct Layout {
+    int64_t ld = 0;          // doubles between vectors (256-byte multiple)
+    int rows_per_blk = 0, nrb = 0;
+    size_t q = 0, w = 0, t = 0, z = 0, part = 0, small = 0, cbuf = 0, io = 0, poly = 0, total = 0;
+    size_t poly_bytes = 0;
+};
+
+Layout layout(int64_t n, int s, int m, size_t poly_bytes, bool permuted) {
+    Layout L;
+    L.ld = std::max<int64_t>(32, (n + 31) / 32 * 32);
+    const int64_t rpt = std::max<int64_t>(4, (n + (int64_t)kThreads * kMaxParts - 1) / ((int64_t)kThreads * kMaxParts));
+    L.rows_per_blk = (int)(rpt * kThreads);
+    L.nrb = (int)std::max<int64_t>(1, (n + L.rows_per_blk - 1) / L.rows_per_blk);
+    size_t at = 0;
+    auto take = [&](size_t doubles) {
+        const size_t here = at;
+        at += (doubles + 31) / 32 * 32;
+        return here;
+    };
+    L.q = take((size_t)(m + 1) * L.ld);
+    L.w = take((size_t)s * L.ld);
+    L.t = take(L.ld);
+    L.z = take(L.ld);
+    L.part = take((size_t)L.nrb * (m + 1) * s);
+    L.small = take((size_t)(m + 1) * s);
+    L.cbuf = take((size_t)4 * kMaxC);
+    L.io = take(permuted ? 0 : 2 * (size_t)L.ld);
+    L.poly = take((poly_bytes + 7) / 8);
+    L.poly_bytes = poly_bytes;
+    L.total = at * 8;
+    return L;
+}
+
+// Dense least squares min ||e - H y|| for H (rows x cols, column-major, rows >= cols)
+// by Householder QR; returns y.
+std::vector<double> least_squares(const std::vector<double>& H, int rows, int cols, std::vector<double> e) {
+    std::vector<double> R(H);
+    for (int k = 0; k < cols; ++k) {
+        double nrm = 0.0;
+        for (int i = k; i < rows; ++i) nrm += R[k * rows + i] * R[k * rows + i];
+        nrm = std::sqrt(nrm);
+        if (nrm == 0.0) continue;
+        const double alpha = R[k * rows + k] > 0 ? -nrm : nrm;
+        std::vector<double> v(rows - k);
+        for (int i = k; i < rows; ++i) v[i - k] = R[k * rows + i];
+        v[0] -= alpha;
+        double vv = 0.0;
+        for (double t : v) vv += t * t;
+        if (vv == 0.0) continue;
+        for (int j = k; j < cols; ++j) {
+            double d = 0.0;
+            for (int i = k; i < rows; ++i) d += v[i - k] * R[j * rows + i];
+            d = 2.0 * d / vv;
+            for (int i = k; i < rows; ++i) R[j * rows + i] -= d * v[i - k];
+        }
+        double d = 0.0;
+        for (int i = k; i < rows; ++i) d += v[i - k] * e[i];
+        d = 2.0 * d / vv;
+        for (int i = k; i < rows; ++i) e[i] -= d * v[i - k];
+    }
+    std::vector<double> y(cols, 0.0);
+    for (int k = cols - 1; k >= 0; --k) {
+        double s = e[k];
+        for (int j = k + 1; j < cols; ++j) s -= R[j * rows + k] * y[j];
+        y[k] = R[k * rows + k] != 0.0 ? s / R[k * rows + k] : 0.0;
+    }
+    return y;
+}
+
+struct Solver {
+    mpk_plan_t hi, lo;
+    int32_t n;
+    int s, m, degree;
+    double theta, delta, tcheb;
+    uint32_t poly_flags;
+    Layout L;
+    double* base;
+    hipStream_t st;
+    std::vector<double> coef;            // s(A) in T_k((A - theta I)/delta), k < degree
+    std::vector<double> lam, sig;        // Newton shifts, Leja order, and scalings
+    std::vector<double> host_small;      // results of Gram products
+    std::vector<double> host_c[4];       // coefficient staging (rewritten only after a sync)
+
+    double* vec(size_t off) const { return base + off; }
+    double* Q(int j) const { return base + L.q + (size_t)j * L.ld; }
+    double* W(int k) const { return base + L.w + (size_t)k * L.ld; }  // W_{k+1}
+
+    mpk_status hip(hipError_t e, const char* what) {
+        if (e == hipSuccess) return MPK_OK;
+        return mpk::set_error(MPK_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+    }
+
+    // out (a x b, row-major a-major: out[j*b + k]) = X^T Y over the first n rows
+    mpk_status gram(const double* X, int a, const double* Y, int b, std::vector<double>& out) {
+        const bool one = a == 1 && b == 1;
+        const int JB = one ? 1 : 8, KB = one ? 1 : 8;
+        const int ntj = (a + JB - 1) / JB, ntk = (b + KB - 1) / KB;
+        const int grid = ((L.nrb + 7) / 8) * 8 * ntj * ntk;
+        double* part = vec(L.part);
+        if (one)
+            hipLaunchKernelGGL((gram_partial_kernel<1, 1>), dim3(grid), dim3(kThreads), 0, st, X, L.ld, a, Y, L.ld, b,
+                               n, L.rows_per_blk, L.nrb, ntj, ntk, part);
+        else
+            hipLaunchKernelGGL((gram_partial_kernel<8, 8>), dim3(grid), dim3(kThreads), 0, st, X, L.ld, a, Y, L.ld, b,
+                               n, L.rows_per_blk, L.nrb, ntj, ntk, part);
+        mpk_status s_ = hip(hipGetLastError(), "gram launch");
+        if (s_ != MPK_OK) return s_;
+        const int count = a * b;
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3((count + 255) / 256), dim3(256), 0, st, part, L.nrb, count,
+                           vec(L.small));
+        s_ = hip(hipGetLastError(), "reduce launch");
+        if (s_ != MPK_OK) return s_;
+        out.assign(count, 0.0);
+        s_ = hip(hipMemcpyAsync(out.data(), vec(L.small), count * sizeof(double), hipMemcpyDeviceToHost, st),
+                 "copy Gram");
+        if (s_ == MPK_OK) s_ = hip(hipStreamSynchronize(st), "synchronize");
+        return s_;
+    }
+
+    // Y[k] = alpha X0[k] + sum_j Q_[j] C[j b + k] with C from host; `slot` picks the
+    // staging buffer (each is rewritten only after a later synchronisation)
+    mpk_status lincomb(const double* X0, double alpha, const double* Qv, int a, const std::vector<double>& C, int b,
+                       double* Y, int slot) {
+        host_c[slot] = C;
+        double* dc = vec(L.cbuf) + (size_t)slot * kMaxC;
+        mpk_status s_ = hip(hipMemcpyAsync(dc, host_c[slot].data(), (size_t)a * b * sizeof(double),
+                                           hipMemcpyHostToDevice, st),
+                            "copy coefficients");
+        if (s_ != MPK_OK) return s_;
+        if (b <= 1)
+            hipLaunchKernelGGL(lincomb_kernel<1>, dim3(grid_rows(n)), dim3(kThreads), 0, st, X0, L.ld, alpha, Qv, L.ld,
+                               a, dc, b, Y, L.ld, n);
+        else if (b <= 8)
+            hipLaunchKernelGGL(lincomb_kernel<8>, dim3(grid_rows(n)), dim3(kThreads), 0, st, X0, L.ld, alpha, Qv, L.ld,
+                               a, dc, b, Y, L.ld, n);
+        else
+            hipLaunchKernelGGL(lincomb_kernel<16>, dim3(grid_rows(n)), dim3(kThreads), 0, st, X0, L.ld, alpha, Qv,
+                               L.ld, a, dc, b, Y, L.ld, n);
+        return hip(hipGetLastError(), "lincomb launch");
+    }
+
+    // out = (M - lambda I) in / sigma, M = I - T_d((theta I - A)/delta) / T_d(theta/delta)
+    mpk_status newton_step(const double* in, double* out, double lambda, double sigma) {
+        std::vector<double> c(degree + 1, 0.0);
+        c[0] = (1.0 - lambda) / sigma;
+        c[degree] += -((degree % 2) ? -1.0 : 1.0) / (tcheb * sigma);
+        const double params[2] = {theta, delta};
+        return poly_apply(lo, MPK_POLY_CHEBYSHEV, degree, c.data(), params, in, out, poly_flags, vec(L.poly),
+                          L.poly_bytes, st);
+    }
+
+    // out = s(A) in
+    mpk_status precondition(const double* in, double* out) {
+        const double params[2] = {theta, delta};
+        return poly_apply(lo, MPK_POLY_CHEBYSHEV, degree - 1, coef.data(), params, in, out, poly_flags, vec(L.poly),
+                          L.poly_bytes, st);
+    }
+
+    // r = b - A x into Q_0 with FP64 values; returns ||r||^2
+    mpk_status residual(const double* b, const double* x, double* rr) {
+        mpk_status s_ = mpk_apply(hi, x, vec(L.t), n, 1, MPK_IO_PERMUTED, nullptr, 0, st);
+        if (s_ != MPK_OK) return s_;
+        hipLaunchKernelGGL(sub_kernel, dim3(grid_rows(n)), dim3(kThreads), 0, st, b, (const double*)vec(L.t), Q(0), n);
+        s_ = hip(hipGetLastError(), "residual launch");
+        if (s_ != MPK_OK) return s_;
+        std::vector<double> g;
+        s_ = gram(Q(0), 1, Q(0), 1, g);
+        if (s_ == MPK_OK) *rr = g[0];
+        return s_;
+    }
+
+    // One restart cycle from Q_0 = r / beta; adds s(A) Q y to x.  Returns the number of
+    // Hessenberg columns built.
+    mpk_status cycle(double beta, double target, double* x, int* cols_out) {
+        std::vector<double> H;  // column-major, leading dimension m + 1
+        const int ldh = m + 1;
+        H.assign((size_t)ldh * m, 0.0);
+        int c = 0;
+        std::vector<double> rprev, G;
+        for (;;) {
+            const int sb = std::min(s, m - c);
+            // Newton basis of the block (Sec. 4): W_k = (M - lambda_k I) W_{k-1} / sigma_k
+            for (int k = 1; k <= sb; ++k) {
+                mpk_status s_ = newton_step(k == 1 ? Q(c) : W(k - 2), W(k - 1), lam[k - 1], sig[k - 1]);
+                if (s_ != MPK_OK) return s_;
+            }
+            // BOrtho: R_prev = Q_{0..c}^T W, W' = W - Q R_prev
+            mpk_status s_ = gram(Q(0), c + 1, W(0), sb, rprev);
+            if (s_ != MPK_OK) return s_;
+            std::vector<double> neg(rprev.size());
+            for (size_t e = 0; e < rprev.size(); ++e) neg[e] = -rprev[e];
+            s_ = lincomb(W(0), 1.0, Q(0), c + 1, neg, sb, W(0), 0);
+            if (s_ != MPK_OK) return s_;
+            // TSQR by Cholesky QR: G = W'^T W' = R^T R, truncated at a dependent column
+            s_ = gram(W(0), sb, W(0), sb, G);
+            if (s_ != MPK_OK) return s_;
+            std::vector<double> R((size_t)sb * sb, 0.0);  // R[i*sb + j], upper
+            int kk = sb;
+            for (int j = 0; j < sb; ++j) {
+                for (int i = 0; i < j; ++i) {
+                    double t = G[i * sb + j];
+                    for (int l = 0; l < i; ++l) t -= R[l * sb + i] * R[l * sb + j];
+                    R[i * sb + j] = t / R[i * sb + i];
+                }
+                double piv2 = G[j * sb + j];
+                for (int l = 0; l < j; ++l) piv2 -= R[l * sb + j] * R[l * sb + j];
+                double wn2 = G[j * sb + j];
+                for (int i = 0; i <= c; ++i) wn2 += rprev[i * sb + j] * rprev[i * sb + j];
+                if (!(std::isfinite(piv2) && piv2 > kEta * kEta * wn2)) {
+                    kk = j;
+                    break;
+                }
+                R[j * sb + j] = std::sqrt(piv2);
+            }
+            const bool dep = kk < sb;
+            if (kk > 0) {  // Q_{c+1..c+kk} = W'[:, :kk] R[:kk, :kk]^{-1}
+                std::vector<double> Rinv((size_t)kk * kk, 0.0);
+                for (int j = 0; j < kk; ++j) {
+                    Rinv[j * kk + j] = 1.0 / R[j * sb + j];
+                    for (int i = j - 1; i >= 0; --i) {
+                        double t = 0.0;
+                        for (int l = i + 1; l <= j; ++l) t += R[i * sb + l] * Rinv[l * kk + j];
+                        Rinv[i * kk + j] = -t / R[i * sb + i];
+                    }
+                }
+                s_ = lincomb(nullptr, 0.0, W(0), kk, Rinv, kk, Q(c + 1), 1);
+                if (s_ != MPK_OK) return s_;
+            }
+            // Hessenberg columns c .. c + nh - 1 from M W_{0..nh-1} = W_{0..nh} B and
+            // W_{0..nh} = Q_{0..rows-1} Rfull
+            const int nh = kk + (dep ? 1 : 0), rows = c + kk + 1;
+            std::vector<double> Rfull((size_t)rows * (nh + 1), 0.0);  // column-major, ld rows
+            Rfull[c] = 1.0;
+            for (int i = 1; i <= nh; ++i) {
+                for (int r = 0; r <= c; ++r) Rfull[(size_t)i * rows + r] = rprev[r * sb + (i - 1)];
+                const int top = std::min(i, kk);
+                for (int r = 0; r < top; ++r) Rfull[(size_t)i * rows + c + 1 + r] = R[r * sb + (i - 1)];
+            }
+            std::vector<double> rhs((size_t)rows * nh, 0.0);  // Rfull B - [H_old Rk_top; 0]
+            for (int col = 0; col < nh; ++col)
+                for (int r = 0; r < rows; ++r)
+                    rhs[(size_t)col * rows + r] =
+                        Rfull[(size_t)col * rows + r] * lam[col] + Rfull[(size_t)(col + 1) * rows + r] * sig[col];
+            if (c > 0)
+                for (int col = 0; col < nh; ++col)
+                    for (int r = 0; r <= c; ++r) {
+                        double t = 0.0;
+                        for (int l = 0; l < c; ++l) t += H[(size_t)l * ldh + r] * Rfull[(size_t)col * rows + l];
+                        rhs[(size_t)col * rows + r] -= t;
+                    }
+            // X Rk_bot = rhs with Rk_bot = Rfull[c .. c+nh-1, 0 .. nh-1] upper triangular
+            for (int r = 0; r < rows; ++r)
+                for (int col = 0; col < nh; ++col) {
+                    double t = rhs[(size_t)col * rows + r];
+                    for (int l = 0; l < col; ++l) t -= H[(size_t)(c + l) * ldh + r] * Rfull[(size_t)col * rows + c + l];
+                    H[(size_t)(c + col) * ldh + r] = t / Rfull[(size_t)col * rows + c + col];
+                }
+            c += nh;
+            // least squares min ||beta e_0 - H y|| and its residual (Alg. 3c's check)
+            const int hr = rows;
+            std::vector<double> Hc((size_t)hr * c), e(hr, 0.0);
+            for (int col = 0; col < c; ++col)
+                for (int r = 0; r < hr; ++r) Hc[(size_t)col * hr + r] = H[(size_t)col * ldh + r];
+            e[0] = beta;
+            std::vector<double> y = least_squares(Hc, hr, c, e);
+            double rho2 = 0.0;
+            for (int r = 0; r < hr; ++r) {
+                double t = e[r];
+                for (int col = 0; col < c; ++col) t -= Hc[(size_t)col * hr + r] * y[col];
+                rho2 += t * t;
+            }
+            if (dep || c >= m || std::sqrt(rho2) <= target) {
+                // x += s(A) Q_{0..c-1} y
+                if (c > 0) {
+                    s_ = lincomb(nullptr, 0.0, Q(0), c, y, 1, vec(L.z), 2);
+                    if (s_ != MPK_OK) return s_;
+                    s_ = precondition(vec(L.z), vec(L.t));
+                    if (s_ != MPK_OK) return s_;
+                    s_ = lincomb(x, 1.0, vec(L.t), 1, std::vector<double>{1.0}, 1, x, 3);
+                    if (s_ != MPK_OK) return s_;
+                }
+                *cols_out = c;
+                return MPK_OK;
+            }
+        }
+    }
+};
+
+bool params_ok(int32_t s, int32_t m, int32_t degree) {
+    return s >= 1 && s <= kMaxS && m >= s && m <= kMaxM && degree >= 1 && degree <= 4096;
+}
+
+}  // namespace
+
+MPK_API mpk_status mpk_sstep_gmres_work_bytes(mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, uint32_t flags,
+                                              size_t* bytes) {
+    if (!lo || !bytes) return mpk::set_error(MPK_ERR_ARG, "null argument");
+    if (!params_ok(s, m, degree))
+        return mpk::set_error(MPK_ERR_ARG, "need 1 <= s <= %d, s <= m <= %d, 1 <= degree <= 4096", kMaxS, kMaxM);
+    int64_t n = 0;
+    mpk_status st = mpk_plan_info(lo, &n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (st != MPK_OK) return st;
+    size_t pb = 0;
+    st = mpk_work_bytes(lo, MPK_CALL_POLY, degree, MPK_IO_PERMUTED, &pb);
+    if (st != MPK_OK) return st;
+    *bytes = layout(n, s, m, pb, flags & MPK_IO_PERMUTED).total;
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, double lmin,
+                                   double lmax, const double* b, double* x, double tol, int32_t max_cycles,
+                                   uint32_t flags, void* work, size_t work_bytes, int32_t* iters_out,
+                                   int32_t* cycles_out, double* relres_out, void* stream) {
+    if (iters_out) *iters_out = 0;
+    if (cycles_out) *cycles_out = 0;
+    if (relres_out) *relres_out = 0.0;
+    if (!hi || !lo) return mpk::set_error(MPK_ERR_ARG, "null plan");
+    if (!mpk::plan_is_f64(hi)) return mpk::set_error(MPK_ERR_ARG, "hi must store FP64 values");
+    if (!mpk::plans_match(hi, lo))
+        return mpk::set_error(MPK_ERR_ARG, "hi and lo must be plans of the same matrix with the same level order");
+    if (!params_ok(s, m, degree))
+        return mpk::set_error(MPK_ERR_ARG, "need 1 <= s <= %d, s <= m <= %d, 1 <= degree <= 4096", kMaxS, kMaxM);
+    if (!(lmin > 0.0) || !(lmax > lmin)) return mpk::set_error(MPK_ERR_ARG, "need 0 < lmin < lmax");
+    if (!(tol >= 0.0)) return mpk::set_error(MPK_ERR_ARG, "tol must be >= 0");
+    if (max_cycles < 0) return mpk::set_error(MPK_ERR_ARG, "max_cycles must be >= 0");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return mpk::set_error(MPK_ERR_ARG, "unknown flag bits");
+    int64_t n64 = 0;
+    mpk_status st = mpk_plan_info(hi, &n64, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (st != MPK_OK) return st;
+    if (n64 > 0 && (!b || !x)) return mpk::set_error(MPK_ERR_ARG, "b or x is null");
+    size_t need = 0;
+    st = mpk_sstep_gmres_work_bytes(lo, s, m, degree, flags, &need);
+    if (st != MPK_OK) return st;
+    if (!work || work_bytes < need)
+        return mpk::set_error(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    if (((uintptr_t)work) % 256) return mpk::set_error(MPK_ERR_ARG, "work must be 256-byte aligned");
+    st = mpk::plan_uploaded(hi);
+    if (st == MPK_OK) st = mpk::plan_uploaded(lo);
+    if (st != MPK_OK) return st;
+    if (n64 == 0) return MPK_OK;
+    try {
+        Solver S;
+        S.hi = hi;
+        S.lo = lo;
+        S.n = (int32_t)n64;
+        S.s = s;
+        S.m = m;
+        S.degree = degree;
+        S.theta = 0.5 * (lmax + lmin);
+        S.delta = 0.5 * (lmax - lmin);
+        S.tcheb = std::cosh(degree * std::acosh(S.theta / S.delta));
+        S.poly_flags = MPK_IO_PERMUTED | (flags & (MPK_PLAIN | MPK_STAGED));
+        size_t pb = 0;
+        mpk_work_bytes(lo, MPK_CALL_POLY, degree, MPK_IO_PERMUTED, &pb);
+        const bool permuted = flags & MPK_IO_PERMUTED;
+        S.L = layout(n64, s, m, pb, permuted);
+        S.base = (double*)work;
+        S.st = (hipStream_t)stream;
+        // s: the Chebyshev interpolant of 1/lambda at the zeros of T_d (its residual
+        // polynomial is T_d((theta - lambda)/delta) / T_d(theta/delta))
+        S.coef.assign(degree, 0.0);
+        for (int j = 0; j < degree; ++j) {
+            const double ang = 3.14159265358979323846 * (j + 0.5) / degree;
+            const double inv = 1.0 / (S.theta + S.delta * std::cos(ang));
+            for (int k = 0; k < degree; ++k) S.coef[k] += std::cos(k * ang) * inv;
+        }
+        for (int k = 0; k < degree; ++k) S.coef[k] *= (k == 0 ? 1.0 : 2.0) / degree;
+        // Newton shifts: the s Chebyshev points of [1 - eps, 1 + eps] (M's spectrum for
+        // A's spectrum in [lmin, lmax]) in Leja order, columns scaled by eps / 2
+        const double eps = 1.0 / S.tcheb;
+        std::vector<double> pts(s);
+        for (int i = 0; i < s; ++i) pts[i] = 1.0 + eps * std::cos(3.14159265358979323846 * (2 * i + 1) / (2.0 * s));
+        std::vector<bool> used(s, false);
+        for (int t = 0; t < s; ++t) {
+            int best = -1;
+            double best_val = -1.0;
+            for (int i = 0; i < s; ++i) {
+                if (used[i]) continue;
+                double v = 1.0;
+                if (t == 0)
+                    v = std::fabs(pts[i]);
+                else
+                    for (double z : S.lam) v *= std::fabs(pts[i] - z);
+                if (v > best_val) {
+                    best = i;
+                    best_val = v;
+                }
+            }
+            used[best] = true;
+            S.lam.push_back(pts[best]);
+        }
+        S.sig.assign(s, 0.5 * eps);
+        // level-order copies of b and x when the caller's vectors are in original order
+        const double* bp = b;
+        double* xp = x;
+        if (!permuted) {
+            double* io = S.vec(S.L.io);
+            st = mpk_permute(hi, b, io, 0, stream);
+            if (st == MPK_OK) st = mpk_permute(hi, x, io + S.L.ld, 0, stream);
+            if (st != MPK_OK) return st;
+            bp = io;
+            xp = io + S.L.ld;
+        }
+        std::vector<double> g;
+        st = S.gram(bp, 1, bp, 1, g);
+        if (st != MPK_OK) return st;
+        const double nb = std::sqrt(g[0]);
+        int iters = 0, cyc = 0;
+        double rel = 0.0;
+        for (;; ++cyc) {
+            double rr = 0.0;
+            st = S.residual(bp, xp, &rr);
+            if (st != MPK_OK) return st;
+            const double beta = std::sqrt(rr);
+            rel = nb > 0.0 ? beta / nb : beta;
+            if (rel <= tol || cyc == max_cycles || beta == 0.0) break;
+            std::vector<double> inv{1.0 / beta};
+            st = S.lincomb(nullptr, 0.0, S.Q(0), 1, inv, 1, S.Q(0), 0);
+            if (st != MPK_OK) return st;
+            int cols = 0;
+            st = S.cycle(beta, tol * nb, xp, &cols);
+            if (st != MPK_OK) return st;
+            iters += cols;
+        }
+        if (!permuted) {
+            st = mpk_permute(hi, xp, x, 1, stream);
+            if (st != MPK_OK) return st;
+        }
+        if (iters_out) *iters_out = iters;
+        if (cycles_out) *cycles_out = cyc;
+        if (relres_out) *relres_out = rel;
+        return MPK_OK;
+    } catch (const std::bad_alloc&) {
+        return mpk::set_error(MPK_ERR_NOMEM, "out of host memory");
+    }
+}

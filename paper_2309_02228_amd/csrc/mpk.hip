@@ -932,6 +932,14 @@ mpk_status mpk::set_error(mpk_status s, const char* fmt, ...) {
     return s;
 }
 
+mpk_status mpk::plan_uploaded(mpk_plan_t p) { return check_uploaded(p); }
+
+bool mpk::plan_is_f64(mpk_plan_t p) { return p && p->H.value_type == MPK_VALUES_F64; }
+
+bool mpk::plans_match(mpk_plan_t a, mpk_plan_t b) {
+    return a && b && a->H.n == b->H.n && a->H.nnz == b->H.nnz && a->H.perm == b->H.perm;
+}
+
 MPK_API void mpk_options_default(mpk_options* opt) {
     if (opt) memset(opt, 0, sizeof *opt);
 }

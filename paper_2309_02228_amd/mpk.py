@@ -32,7 +32,7 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_get_schedule",
            "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy",
            "mpk_server_create", "mpk_server_submit_apply", "mpk_server_submit_solve",
-           "mpk_server_wait", "mpk_server_destroy"]
+           "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes"]
 
 
 class MPKError(RuntimeError):
@@ -93,6 +93,9 @@ def _load():
         "mpk_server_wait": (I32, [P, I64, pI32, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double), pI32, ctypes.POINTER(ctypes.c_double)]),
         "mpk_server_destroy": (None, [P]),
+        "mpk_sstep_gmres": (I32, [P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double, P, P, ctypes.c_double,
+                                  I32, U32, P, SZ, pI32, pI32, ctypes.POINTER(ctypes.c_double), P]),
+        "mpk_sstep_gmres_work_bytes": (I32, [P, I32, I32, I32, U32, pSZ]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -307,6 +310,33 @@ class Plan:
                                      float(tol), int(max_iter), flags, _dptr(w), nb, ctypes.byref(it),
                                      ctypes.byref(rel), _stream(stream)))
         return x, it.value, rel.value
+
+    def gmres_work_bytes(self, s, m, degree, permuted=True):
+        nb = ctypes.c_size_t()
+        _check(_lib.mpk_sstep_gmres_work_bytes(self._h, int(s), int(m), int(degree),
+                                               MPK_IO_PERMUTED if permuted else 0, ctypes.byref(nb)))
+        return nb.value
+
+    def sstep_gmres(self, lo, b, s, m, degree, lmin, lmax, tol=1e-10, max_cycles=100, x=None, permuted=True,
+                    plain=False, staged=False, stream=None, work=None):
+        """Solve A x = b by restarted s-step GMRES (blocks of ``s``, restart ``m``) with the
+        right degree-``degree`` Chebyshev polynomial preconditioner on [lmin, lmax]:
+        FP64 residuals with this plan, basis and preconditioner with ``lo`` (the same
+        matrix, FP32 or FP64 values).  Returns (x, basis vectors built, cycles, final
+        ||r|| / ||b||)."""
+        import torch
+        if x is None:
+            x = torch.zeros_like(b)
+        flags = self._flags(permuted, plain, staged)
+        nb = lo.gmres_work_bytes(s, m, degree, permuted)
+        if work is None:
+            work = torch.empty(nb // 8 + 64, dtype=torch.float64, device=b.device)
+        it, cy, rel = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.mpk_sstep_gmres(self._h, lo._h, int(s), int(m), int(degree), float(lmin), float(lmax), _dptr(b),
+                                    _dptr(x), float(tol), int(max_cycles), flags, _dptr(work),
+                                    work.numel() * work.element_size(), ctypes.byref(it), ctypes.byref(cy),
+                                    ctypes.byref(rel), _stream(stream)))
+        return x, it.value, cy.value, rel.value
 
     def permute(self, x, direction=0, out=None, stream=None):
         import torch

@@ -257,3 +257,38 @@ def test_server_argument_errors_without_gpu():
                                        1, ctypes.byref(t)) == -1
     assert lib.mpk_server_wait(None, 1, None, None, None, None, None) == -1
     lib.mpk_server_destroy(None)  # no-op
+
+
+def test_sstep_gmres_argument_errors_without_gpu():
+    lib = M.lib()
+    A = S.laplacian_2d(8)
+    hi = M.Plan.from_csr(A)
+    lo = M.Plan.from_csr(A, values="f32")
+    other = M.Plan.from_csr(S.laplacian_2d(9))
+    nb = ctypes.c_size_t()
+    assert lib.mpk_sstep_gmres_work_bytes(hi._h, 8, 32, 8, 1, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert lib.mpk_sstep_gmres_work_bytes(hi._h, 0, 32, 8, 1, ctypes.byref(nb)) == -1   # s < 1
+    assert lib.mpk_sstep_gmres_work_bytes(hi._h, 17, 32, 8, 1, ctypes.byref(nb)) == -1  # s > 16
+    assert lib.mpk_sstep_gmres_work_bytes(hi._h, 8, 4, 8, 1, ctypes.byref(nb)) == -1    # m < s
+    assert lib.mpk_sstep_gmres_work_bytes(hi._h, 8, 257, 8, 1, ctypes.byref(nb)) == -1  # m > 256
+    assert lib.mpk_sstep_gmres_work_bytes(hi._h, 8, 32, 0, 1, ctypes.byref(nb)) == -1   # d < 1
+    need = nb.value
+    fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails first
+
+    def call(h=hi, l=lo, s=8, m=32, d=8, lmin=0.1, lmax=8.0, b=fake, x=fake, tol=1e-10, cyc=10, flags=1,
+             work=fake, nbytes=None):
+        return lib.mpk_sstep_gmres(h._h if h else None, l._h if l else None, s, m, d, lmin, lmax, b, x, tol, cyc,
+                                   flags, work, need if nbytes is None else nbytes, None, None, None, None)
+
+    assert call(h=None) == -1
+    assert call(h=lo, l=lo) == -1                  # hi must hold FP64 values
+    assert call(l=other) == -1                     # plans of different matrices
+    assert call(s=0) == -1 and call(m=7) == -1 and call(d=0) == -1
+    assert call(lmin=0.0) == -1 and call(lmin=2.0, lmax=1.0) == -1
+    assert call(tol=-1.0) == -1 and call(cyc=-1) == -1
+    assert call(flags=64) == -1                    # unknown flag bit
+    assert call(b=None) == -1 and call(x=None) == -1
+    assert call(nbytes=need - 1) == -1             # work too small
+    assert call(work=ctypes.c_void_p((1 << 20) + 8)) == -1  # misaligned
+    assert call() == -6                            # not uploaded
+    assert "upload" in lib.mpk_last_error().decode()

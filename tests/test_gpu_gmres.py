@@ -1,0 +1,180 @@
+"""GPU parity of the s-step GMRES solve (Sec. 4, Alg. 3a/3c, with the right Chebyshev
+polynomial preconditioner of Sec. 5; readings R17-R19) through the C ABI.
+
+The GPU computes a Newton basis step (M - lambda I) v / sigma as one Chebyshev
+polynomial of degree d in A (M = I - T_d((theta I - A)/delta) / T_d(theta/delta)),
+the oracle as A (s(A) v); Gram products, Cholesky factors and least squares differ
+from the oracle's only in rounding order.  So after a fixed number of cycles the
+iterates agree to a tolerance derived from that rounding: each basis vector differs
+by O(d eps) relative, the least-squares problem of a cycle of m columns amplifies it
+by at most its condition (here below 1e3), hence the bound 1e-9 relative below.
+Blocked, plain and staged polynomial launches give bitwise equal vectors, and every
+sum is reduced in a fixed order, so those runs and repeated runs are bitwise equal."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth as S
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():  # collected on CPU-only hosts, never run there
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2309_02228_amd import Plan, MPKError  # noqa: E402
+
+DEV = "cuda:0"
+FIXED_CYCLE_RTOL = 1e-9
+
+
+def lap_bounds(dims):
+    return (sum(2 - 2 * math.cos(math.pi / (m + 1)) for m in dims),
+            sum(2 + 2 * math.cos(math.pi / (m + 1)) for m in dims))
+
+
+def knn_problem(n, seed):
+    A = S.knn_graph_laplacian(n, k=26, seed=seed)
+    lmax = 2.0 * np.max(np.diff(A.rowptr)) + 0.1  # Gershgorin; lmin = 0.1 is the shift
+    return A, 0.1, lmax, S.uniform_vector(A.n, seed + 1)
+
+
+def solve(hi, lo, b, s, m, d, lmin, lmax, tol, cycles, x0=None, **kw):
+    """Runs the GPU solve in original row order; returns (x, iters, cycles, relres)."""
+    perm = hi.levels()["perm"].astype(np.int64)
+    xd = None if x0 is None else torch.tensor(x0[perm], device=DEV)
+    x, it, cy, rel = hi.sstep_gmres(lo, torch.tensor(b[perm], device=DEV), s, m, d, lmin, lmax, tol=tol,
+                                    max_cycles=cycles, x=xd, **kw)
+    hi.check()
+    lo.check()
+    out = np.empty(b.size)
+    out[perm] = x.cpu().numpy()
+    return out, it, cy, rel
+
+
+@pytest.mark.parametrize("s,m,d", [(1, 8, 4), (4, 16, 8), (8, 32, 8), (5, 12, 3), (8, 24, 1), (16, 48, 2)])
+def test_fixed_cycle_matches_oracle_on_ragged_stencil(s, m, d):
+    dims = (37, 29)
+    A = S.laplacian_2d(*dims)
+    lmin, lmax = lap_bounds(dims)
+    b = S.uniform_vector(A.n, 3)
+    hi = Plan.from_csr(A, p_block=4).upload(DEV)
+    x, it, cy, rel = solve(hi, hi, b, s, m, d, lmin, lmax, 0.0, 1)
+    xo, hist, ito = O.sstep_gmres(A, b, np.zeros(A.n), s, m, d, lmin, lmax, 0.0, 1)
+    assert it == ito == m and cy == 1
+    assert np.linalg.norm(x - xo) <= FIXED_CYCLE_RTOL * np.linalg.norm(xo)
+    assert abs(rel - hist[-1]) <= 1e-6 * hist[-1] + 1e-13  # absolute floor: FP64 rounding of b - A x
+
+
+@pytest.mark.parametrize("values", ["f64", "f32"])
+def test_two_cycles_match_oracle_on_knn(values):
+    A, lmin, lmax, b = knn_problem(20000, 0)
+    hi = Plan.from_csr(A).upload(DEV)
+    lo = hi if values == "f64" else Plan.from_csr(A, values="f32").upload(DEV)
+    x, it, cy, rel = solve(hi, lo, b, 8, 16, 8, lmin, lmax, 0.0, 2)
+    xo, hist, ito = O.sstep_gmres(A, b, np.zeros(A.n), 8, 16, 8, lmin, lmax, 0.0, 2,
+                                  values=None if values == "f64" else np.float32)
+    assert it == ito == 32 and cy == 2
+    assert np.linalg.norm(x - xo) <= FIXED_CYCLE_RTOL * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("values", ["f64", "f32"])
+def test_solve_to_1e10_like_oracle(values):
+    A, lmin, lmax, b = knn_problem(20000, 3)
+    hi = Plan.from_csr(A).upload(DEV)
+    lo = hi if values == "f64" else Plan.from_csr(A, values="f32").upload(DEV)
+    x, it, cy, rel = solve(hi, lo, b, 8, 32, 8, lmin, lmax, 1e-10, 50)
+    xo, hist, ito = O.sstep_gmres(A, b, np.zeros(A.n), 8, 32, 8, lmin, lmax, 1e-10, 50,
+                                  values=None if values == "f64" else np.float32)
+    assert rel <= 1e-10 and cy == len(hist) - 1 and abs(it - ito) <= 8
+    # the true residual, in FP64 on the host
+    assert np.linalg.norm(b - O.spmv(A, x)) <= 1.0000001e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xo) <= 2e-10 * (lmax / lmin) * np.linalg.norm(xo)
+
+
+def test_blocked_plain_staged_bitwise_and_io_orders():
+    dims = (20, 18, 16)
+    A = S.laplacian_3d(*dims)
+    lmin, lmax = lap_bounds(dims)
+    b = S.uniform_vector(A.n, 5)
+    hi = Plan.from_csr(A, p_block=8).upload(DEV)
+    xb, ib, cb, rb = solve(hi, hi, b, 8, 32, 8, lmin, lmax, 1e-10, 30)
+    xp, ip, cp, rp = solve(hi, hi, b, 8, 32, 8, lmin, lmax, 1e-10, 30, plain=True)
+    xs, is_, cs, rs = solve(hi, hi, b, 8, 32, 8, lmin, lmax, 1e-10, 30, staged=True)
+    assert rb <= 1e-10 and np.array_equal(xb, xp) and np.array_equal(xb, xs) and ib == ip == is_
+    # original-order I/O: the library permutes in and out
+    x, it, cy, rel = hi.sstep_gmres(hi, torch.tensor(b, device=DEV), 8, 32, 8, lmin, lmax, tol=1e-10,
+                                    max_cycles=30, permuted=False)
+    assert np.array_equal(x.cpu().numpy(), xb) and it == ib
+    # repeated calls are identical
+    xr, ir, cr, rr = solve(hi, hi, b, 8, 32, 8, lmin, lmax, 1e-10, 30)
+    assert np.array_equal(xr, xb) and rr == rb
+
+
+def test_dependent_column_ends_cycle_exactly():
+    # M has 3 distinct eigenvalues (d = 3): the 4th column of the first block is
+    # dependent, the cycle ends with 3 columns and the solution is exact
+    diag = np.repeat([1.0, 2.5, 4.0], 700)
+    A = S.diagonal(diag)
+    b = S.uniform_vector(A.n, 1)
+    hi = Plan.from_csr(A).upload(DEV)
+    x, it, cy, rel = solve(hi, hi, b, 4, 8, 3, 1.0, 4.0, 1e-13, 2)
+    assert it == 3 and cy == 1 and rel <= 1e-13
+    np.testing.assert_allclose(x, b / diag, rtol=1e-12)
+    # an eigenvector right-hand side: one column
+    n = 1000
+    A = S.laplacian_1d(n)
+    j = 600
+    lam = 2 - 2 * math.cos(j * math.pi / (n + 1))
+    b = np.sin(j * math.pi * np.arange(1, n + 1) / (n + 1))
+    hi = Plan.from_csr(A).upload(DEV)
+    x, it, cy, rel = solve(hi, hi, b, 4, 8, 4, *lap_bounds((n,)), 1e-11, 2)
+    assert it == 1
+    np.testing.assert_allclose(x, b / lam, atol=1e-11 * np.abs(b / lam).max())
+
+
+def test_edge_cases():
+    A = S.laplacian_2d(9, 7)
+    lmin, lmax = lap_bounds((9, 7))
+    hi = Plan.from_csr(A).upload(DEV)
+    b = S.uniform_vector(A.n, 2)
+    x0 = S.uniform_vector(A.n, 4)
+    # no cycle: the initial guess comes back, with its residual
+    x, it, cy, rel = solve(hi, hi, b, 4, 8, 4, lmin, lmax, 1e-10, 0, x0=x0)
+    assert np.array_equal(x, x0) and it == 0 and cy == 0
+    assert abs(rel - np.linalg.norm(b - O.spmv(A, x0)) / np.linalg.norm(b)) <= 1e-12
+    # b = 0 from x0 = 0: nothing to do
+    x, it, cy, rel = solve(hi, hi, np.zeros(A.n), 4, 8, 4, lmin, lmax, 1e-10, 5)
+    assert not x.any() and it == 0 and rel == 0.0
+    # a nonzero initial guess converges like the oracle
+    x, it, cy, rel = solve(hi, hi, b, 3, 9, 5, lmin, lmax, 0.0, 1, x0=x0)
+    xo, hist, ito = O.sstep_gmres(A, b, x0, 3, 9, 5, lmin, lmax, 0.0, 1)
+    assert np.linalg.norm(x - xo) <= FIXED_CYCLE_RTOL * np.linalg.norm(xo)
+    # N = 1
+    one = S.diagonal(np.array([3.0]))
+    h1 = Plan.from_csr(one).upload(DEV)
+    x, it, cy, rel = solve(h1, h1, np.array([6.0]), 2, 4, 2, 1.0, 5.0, 1e-12, 3)
+    assert abs(x[0] - 2.0) <= 1e-14 and it == 1
+    # a work buffer that is too small is refused
+    with pytest.raises(MPKError):
+        hi.sstep_gmres(hi, torch.tensor(b, device=DEV), 4, 8, 4, lmin, lmax,
+                       work=torch.empty(16, dtype=torch.float64, device=DEV))
+
+
+@pytest.mark.slow
+def test_full_size_160_cubed_mixed_precision_solve():
+    # 3D 7-point 160^3 with FP32-valued basis and preconditioner, FP64 residuals, to 1e-10;
+    # the true residual is recomputed on the host in FP64
+    from scipy.sparse import csr_matrix
+    n1 = 160
+    A = S.laplacian_3d(n1)
+    lmin, lmax = lap_bounds((n1, n1, n1))
+    b = S.uniform_vector(A.n, 11)
+    hi = Plan.from_csr(A, p_block=8).upload(DEV)
+    lo = Plan.from_csr(A, p_block=8, values="f32").upload(DEV)
+    x, it, cy, rel = solve(hi, lo, b, 8, 64, 32, lmin, lmax, 1e-10, 40)
+    M = csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
+    true = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
+    assert rel <= 1e-10 and true <= 1.0000001e-10 and abs(true - rel) <= 1e-12
