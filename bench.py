@@ -73,8 +73,9 @@ def cpu_baseline(A, x, p, budget_s):
 def serving_bench(args, A160, plan160, dev):
     """Open-loop serving of a mixed request stream through the library's request
     server: Poisson arrivals of matrix powers y_p = A^p x (p uniform in 2..10,
-    FP64 or FP32 matrix values) and refinement solves to 1e-8 (FP64 residuals,
-    FP32 Chebyshev corrections) on a catalogue of 2D/3D Laplacians and 26-NN
+    FP64 or FP32 matrix values) and s-step GMRES solves to 1e-8 with a Chebyshev
+    polynomial preconditioner (FP64 residuals and orthogonalisation, FP32-valued basis
+    and preconditioner) on a catalogue of 2D/3D Laplacians and 26-NN
     graph Laplacians with N from 1e4 to 4.1e6.  Requests carry host vectors
     (pinned), so latencies include the PCIe copies.  Every request is first run
     alone (one worker, one request at a time); its alone latency sets the
@@ -108,7 +109,9 @@ def serving_bench(args, A160, plan160, dev):
             lmin, lmax = 0.1, 2.0 * float(np.max(np.diff(A.rowptr))) + 0.1
         hi = plan160 if make is None else Plan.from_csr(A, p_block=4).upload(dev)
         lo = Plan.from_csr(A, p_block=4, values="f32").upload(dev)
-        deg = int(min(256, max(16, np.ceil(1.2 * np.sqrt(lmax / lmin)))))
+        # preconditioner degree: about a third of sqrt(kappa), 4..32, so that GMRES
+        # needs a few dozen basis vectors
+        deg = int(min(32, max(4, np.ceil(np.sqrt(lmax / lmin) / 3))))
         cat.append({"name": name, "n": A.n, "hi": hi, "lo": lo, "lmin": lmin, "lmax": lmax, "degree": deg,
                     "x": synth.uniform_vector(A.n, 10), "b": synth.uniform_vector(A.n, 11)})
     torch.cuda.synchronize()
@@ -141,8 +144,8 @@ def serving_bench(args, A160, plan160, dev):
             plan = c["hi"] if r[3] == "f64" else c["lo"]
             return srv.submit_apply(plan, c["x"], r[2], permuted=False, last_only=True, Y=outs[i])
         outs[i][:] = 0.0
-        return srv.submit_solve(c["hi"], c["lo"], c["b"], c["degree"], c["lmin"], c["lmax"], tol=1e-8,
-                                max_iter=400, x0=outs[i], permuted=False)
+        return srv.submit_gmres(c["hi"], c["lo"], c["b"], 8, 64, c["degree"], c["lmin"], c["lmax"], tol=1e-8,
+                                max_cycles=50, x0=outs[i], permuted=False)
 
     pool = args.serve_pool_gib << 30
     # alone: one worker, one request at a time
@@ -218,8 +221,10 @@ def serving_bench(args, A160, plan160, dev):
     out = {
         "workload": f"{nreq} requests, Poisson arrivals at {rate:.1f}/s ({args.serve_load:.2f} x the alone "
                     f"service rate); matrices: " + ", ".join(f"{c['name']} (N={c['n']})" for c in cat) +
-                    "; 75% y_p = A^p x (p uniform 2..10, FP64 or FP32 values, y_p returned), 25% refinement "
-                    "solves to 1e-8 (FP32 Chebyshev corrections of degree min(256, 1.2 sqrt(kappa)))",
+                    "; 75% y_p = A^p x (p uniform 2..10, FP64 or FP32 values, y_p returned), 25% s-step GMRES "
+                    "solves to 1e-8 (s = 8, m = 64; right Chebyshev preconditioner of degree "
+                    "min(32, max(4, sqrt(kappa) / 3)) through FP32-valued launches; FP64 residuals and "
+                    "orthogonalisation)",
         "workers": args.serve_workers, "pool_gib": args.serve_pool_gib,
         "throughput_req_s": round(nreq / makespan, 2), "makespan_s": round(makespan, 3),
         "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "queue_p50_ms": pct(queue, 50),
@@ -261,6 +266,9 @@ def main():
     ap.add_argument("--serve-pool-gib", type=int, default=8)
     ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--solve-degree", type=int, default=256)
+    ap.add_argument("--gmres-s", type=int, default=8)
+    ap.add_argument("--gmres-m", type=int, default=64)
+    ap.add_argument("--gmres-degree", type=int, default=32)
     ap.add_argument("--only", choices=["both", "blocked", "plain"], default="both",
                     help="restrict the launches (for profiler runs)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -516,11 +524,58 @@ def main():
                                            "(continuously batched) solve is not built"}
         log(f"solve: mixed {mixed['p50_ms']:.1f} ms p50 ({mixed['corrections']} corrections), fp64 plain "
             f"{fp64_plain['p50_ms']:.1f} ms p50")
+    if not args.no_solve and args.only == "both":
+        # the same system by s-step GMRES (blocks of s, restart m) with the right
+        # degree-d Chebyshev polynomial preconditioner: FP64 residuals and orthogonalisation;
+        # basis and preconditioner through FP32-valued blocked launches (mixed), or FP64
+        # values with plain SpMV launches (the FP64 plain path)
+        gs, gm, gd = args.gmres_s, args.gmres_m, args.gmres_degree
+        cg = np.cos(np.pi / (g + 1))
+        lmin, lmax = 3 * (2 - 2 * cg), 3 * (2 + 2 * cg)
+        bvec = plan.permute(torch.tensor(synth.uniform_vector(n, 1), device=dev), 0)
+        hi8 = Plan.from_csr(A, p_block=8).upload(dev)
+        lo8 = Plan.from_csr(A, p_block=8, values="f32").upload(dev)
+        work = torch.empty(lo8.gmres_work_bytes(gs, gm, gd) // 8 + 64, dtype=torch.float64, device=dev)
+
+        def gmres_solves(lo, plain):
+            lat, res = [], None
+            for r in range(args.solve_reps + 1):
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                res = hi8.sstep_gmres(lo, bvec, gs, gm, gd, lmin, lmax, tol=1e-10, max_cycles=200, plain=plain,
+                                      work=work)
+                torch.cuda.synchronize()
+                if r > 0:
+                    lat.append(time.perf_counter() - t0)
+            lo.check()
+            xs = res[0]
+            # true residual of the returned solution, FP64 SpMV on the GPU
+            true = float(torch.linalg.norm(bvec - hi8.apply(xs, 1)[0]) / torch.linalg.norm(bvec))
+            lat = np.array(lat) * 1e3
+            return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                    "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                    "basis_vectors": res[1], "cycles": res[2], "final_rel_residual": res[3],
+                    "true_rel_residual": true, "powers_per_solve": res[1] * gd + res[2] * (gd - 1) + res[2] + 1}
+        gm_mixed = gmres_solves(lo8, False)
+        gm_plain = gmres_solves(hi8, True)
+        out["solve_gmres"] = {
+            "workload": f"A x = b, 3D 7-point Laplacian {g}^3, b uniform[-1,1] seed 1 (level order), x0 = 0, "
+                        f"tol 1e-10 relative residual; s-step GMRES (s = {gs}, restart m = {gm}) with the right "
+                        f"degree-{gd} Chebyshev polynomial preconditioner on [{lmin:.6g}, {lmax:.6g}]",
+            "mixed_f32_blocked": gm_mixed,
+            "fp64_plain": gm_plain,
+            "speedup_p50": round(gm_plain["p50_ms"] / gm_mixed["p50_ms"], 3),
+            "note": f"{args.solve_reps} sequential solves of one system after one warm-up",
+        }
+        log(f"gmres: mixed {gm_mixed['p50_ms']:.1f} ms p50 ({gm_mixed['basis_vectors']} vectors, "
+            f"{gm_mixed['cycles']} cycles, true residual {gm_mixed['true_rel_residual']:.2e}), fp64 plain "
+            f"{gm_plain['p50_ms']:.1f} ms p50")
+        del hi8, lo8, work
     if not args.no_serve and args.only == "both":
         out["serving"] = serving_bench(args, A, plan, dev)
         sv = out["serving"]["by_kind"]["solve"]
         out["solve_latency_ms"] = {"p50": sv["p50_ms"], "p99": sv["p99_ms"],
-                                   "note": "served refinement solves to 1e-8 in the mixed request stream "
+                                   "note": "served s-step GMRES solves to 1e-8 in the mixed request stream "
                                            "(serving.workload), PCIe copies included"}
     if not args.no_cpu_baseline and args.only == "both":
         log("cpu baseline: FP64 oracle on the host ...")

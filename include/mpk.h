@@ -409,8 +409,8 @@ void mpk_destroy(mpk_plan_t plan);
 
 /*
  * ---- Request server ----------------------------------------------------
- * Serves matrix power requests (mpk_apply) and refinement solves
- * (mpk_refine_solve) submitted from host memory by any number of host
+ * Serves matrix power requests (mpk_apply), refinement solves
+ * (mpk_refine_solve) and s-step GMRES solves (mpk_sstep_gmres) submitted from host memory by any number of host
  * threads, on the device that is current at mpk_server_create.  Each of
  * `workers` threads owns a HIP stream and runs one request at a time: copy
  * in, compute, copy out, mpk_check_device.  Requests are admitted in arrival
@@ -446,6 +446,19 @@ mpk_status mpk_server_submit_apply(mpk_server_t server, mpk_plan_t plan, const d
 mpk_status mpk_server_submit_solve(mpk_server_t server, mpk_plan_t hi, mpk_plan_t lo, const double* b,
                                    double* x, int32_t degree, double lmin, double lmax, double tol,
                                    int32_t max_iter, uint32_t flags, int64_t* ticket);
+
+/*
+ * Queues mpk_sstep_gmres(hi, lo, s, m, degree, lmin, lmax, b, x, tol,
+ * max_cycles, flags): b (host, n doubles) is the right-hand side, x (host, n
+ * doubles) holds the initial guess on entry and the solution when the request
+ * is done; mpk_server_wait reports the basis vectors built as `iters`.
+ * Device memory taken: 2n doubles plus mpk_sstep_gmres_work_bytes(lo, s, m,
+ * degree, flags).  Errors at submit: MPK_ERR_ARG (null, unknown flag, s, m or
+ * degree out of range), MPK_ERR_NOMEM; the solve's own errors at wait.
+ */
+mpk_status mpk_server_submit_gmres(mpk_server_t server, mpk_plan_t hi, mpk_plan_t lo, const double* b,
+                                   double* x, int32_t s, int32_t m, int32_t degree, double lmin, double lmax,
+                                   double tol, int32_t max_cycles, uint32_t flags, int64_t* ticket);
 
 /*
  * Blocks until request `ticket` is done and releases it (a ticket may be

@@ -1,5 +1,5 @@
-// Request server of the MPK library: MPK applications and refinement solves
-// submitted from the host run on a pool of worker threads, each with its own
+// Request server of the MPK library: MPK applications, refinement solves and
+// s-step GMRES solves submitted from the host run on a pool of worker threads, each with its own
 // HIP stream, and are admitted in arrival order as soon as their device
 // memory fits in the server's budget.  Work of different requests overlaps on
 // the GPU; blocked (persistent) launches take turns, as everywhere in the
@@ -66,12 +66,12 @@ struct Pool {
     }
 };
 
-enum { kApply = 0, kSolve = 1 };
+enum { kApply = 0, kSolve = 1, kGmres = 2 };
 
 struct Request {
     int type = kApply;
     mpk_plan_t plan = nullptr, lo = nullptr;
-    int32_t n = 0, p = 0, degree = 0, max_iter = 0;
+    int32_t n = 0, p = 0, degree = 0, max_iter = 0, s = 0, m = 0;
     double lmin = 0, lmax = 0, tol = 0;
     uint32_t flags = 0;
     const double* in = nullptr;  // host: x (apply) or b (solve)
@@ -137,9 +137,16 @@ void execute(Request* r, char* d, hipStream_t st) {
         void* w = d + 2 * round_up(n * 8);
         if (!hip(hipMemcpyAsync(b, r->in, n * 8, hipMemcpyHostToDevice, st), "copy b")) return;
         if (!hip(hipMemcpyAsync(x, r->out, n * 8, hipMemcpyHostToDevice, st), "copy x")) return;
-        if (!lib(mpk_refine_solve(r->plan, r->lo, r->degree, r->lmin, r->lmax, b, x, r->tol, r->max_iter, r->flags,
-                                  w, r->work, &r->iters, &r->relres, st)))
-            return;
+        if (r->type == kSolve) {
+            if (!lib(mpk_refine_solve(r->plan, r->lo, r->degree, r->lmin, r->lmax, b, x, r->tol, r->max_iter,
+                                      r->flags, w, r->work, &r->iters, &r->relres, st)))
+                return;
+        } else {
+            int32_t cycles = 0;
+            if (!lib(mpk_sstep_gmres(r->plan, r->lo, r->s, r->m, r->degree, r->lmin, r->lmax, b, x, r->tol,
+                                     r->max_iter, r->flags, w, r->work, &r->iters, &cycles, &r->relres, st)))
+                return;
+        }
         if (!hip(hipMemcpyAsync(r->out, x, n * 8, hipMemcpyDeviceToHost, st), "copy x back")) return;
         if (lib(mpk_check_device(r->plan, st))) lib(mpk_check_device(r->lo, st));
     }
@@ -279,6 +286,39 @@ MPK_API mpk_status mpk_server_submit_solve(mpk_server_t S, mpk_plan_t hi, mpk_pl
     if (s != MPK_OK) {
         delete r;
         return s;
+    }
+    r->bytes = 2 * round_up(n * 8) + round_up(r->work) + kAlign;
+    return submit(S, r, ticket);
+}
+
+MPK_API mpk_status mpk_server_submit_gmres(mpk_server_t S, mpk_plan_t hi, mpk_plan_t lo, const double* b, double* x,
+                                           int32_t s, int32_t m, int32_t degree, double lmin, double lmax, double tol,
+                                           int32_t max_cycles, uint32_t flags, int64_t* ticket) {
+    if (!S || !hi || !lo || !ticket) return mpk::set_error(MPK_ERR_ARG, "null argument");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return mpk::set_error(MPK_ERR_ARG, "unknown flag bits");
+    int64_t n = 0;
+    mpk_status st = mpk_plan_info(hi, &n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+    if (st != MPK_OK) return st;
+    if (n > 0 && (!b || !x)) return mpk::set_error(MPK_ERR_ARG, "b or x is null");
+    auto* r = new Request;
+    r->type = kGmres;
+    r->plan = hi;
+    r->lo = lo;
+    r->n = (int32_t)n;
+    r->s = s;
+    r->m = m;
+    r->degree = degree;
+    r->lmin = lmin;
+    r->lmax = lmax;
+    r->tol = tol;
+    r->max_iter = max_cycles;
+    r->flags = flags;
+    r->in = b;
+    r->out = x;
+    st = mpk_sstep_gmres_work_bytes(lo, s, m, degree, flags, &r->work);
+    if (st != MPK_OK) {
+        delete r;
+        return st;
     }
     r->bytes = 2 * round_up(n * 8) + round_up(r->work) + kAlign;
     return submit(S, r, ticket);

@@ -32,7 +32,8 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_get_schedule",
            "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy",
            "mpk_server_create", "mpk_server_submit_apply", "mpk_server_submit_solve",
-           "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes"]
+           "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes",
+           "mpk_server_submit_gmres"]
 
 
 class MPKError(RuntimeError):
@@ -96,6 +97,8 @@ def _load():
         "mpk_sstep_gmres": (I32, [P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double, P, P, ctypes.c_double,
                                   I32, U32, P, SZ, pI32, pI32, ctypes.POINTER(ctypes.c_double), P]),
         "mpk_sstep_gmres_work_bytes": (I32, [P, I32, I32, I32, U32, pSZ]),
+        "mpk_server_submit_gmres": (I32, [P, P, P, P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double,
+                                          ctypes.c_double, I32, U32, pI64]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -401,6 +404,22 @@ class Server:
         t = ctypes.c_int64()
         _check(_lib.mpk_server_submit_solve(self._h, hi._h, lo._h, _ptr(b), _ptr(x), int(degree), float(lmin),
                                             float(lmax), float(tol), int(max_iter),
+                                            Plan._flags(permuted, plain, staged), ctypes.byref(t)))
+        self._keep[t.value] = (hi, lo, b, x)
+        return t.value
+
+    def submit_gmres(self, hi, lo, b, s, m, degree, lmin, lmax, tol=1e-10, max_cycles=100, x0=None,
+                     permuted=True, plain=False, staged=False):
+        """Queues an s-step GMRES solve of A x = b (host vectors); ``x0`` (zeros if None) is
+        the initial guess and receives the solution.  Returns the ticket; the result's
+        "iters" counts basis vectors."""
+        b = self._host(b)
+        x = np.zeros_like(b) if x0 is None else x0
+        if x.shape != b.shape or x.dtype != np.float64 or not x.flags.c_contiguous:
+            raise ValueError("x0 must be a C-contiguous float64 array shaped like b (overwritten by the solution)")
+        t = ctypes.c_int64()
+        _check(_lib.mpk_server_submit_gmres(self._h, hi._h, lo._h, _ptr(b), _ptr(x), int(s), int(m), int(degree),
+                                            float(lmin), float(lmax), float(tol), int(max_cycles),
                                             Plan._flags(permuted, plain, staged), ctypes.byref(t)))
         self._keep[t.value] = (hi, lo, b, x)
         return t.value

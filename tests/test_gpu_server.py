@@ -5,7 +5,8 @@ call gives alone: every kernel's row arithmetic is fixed and the solve's
 reductions have a fixed order, so the comparison is bitwise.  One apply is
 also checked against the oracle's powers (Eq. 1 recursion), and the
 admission rules (arrival order, pool budget, per-request errors) are
-exercised with host-side conditions only."""
+exercised with host-side conditions only.  The mix holds matrix powers,
+refinement solves and s-step GMRES solves."""
 import threading
 
 import numpy as np
@@ -57,7 +58,15 @@ def alone_solve(hi, lo, b, d, lmin, lmax, tol, it):
     return x.cpu().numpy(), k, rel
 
 
-def request_mix(pr, seed, napply=20, nsolve=3):
+def alone_gmres(hi, lo, b, s, m, d, lmin, lmax, tol, cycles):
+    x, it, cy, rel = hi.sstep_gmres(lo, torch.tensor(b, device=DEV), s, m, d, lmin, lmax, tol=tol,
+                                    max_cycles=cycles)
+    hi.check()
+    lo.check()
+    return x.cpu().numpy(), it, rel
+
+
+def request_mix(pr, seed, napply=20, nsolve=3, ngmres=3):
     rng = np.random.default_rng(seed)
     reqs = []
     for i in range(napply):
@@ -67,6 +76,9 @@ def request_mix(pr, seed, napply=20, nsolve=3):
                      bool(rng.integers(2)), str(rng.choice(list(MODES)))))
     for i in range(nsolve):
         reqs.append(("solve", "hi", S.uniform_vector(pr["A"].n, seed * 100 + 50 + i), 8 + 4 * i))
+    for i in range(ngmres):
+        s = (4, 8, 5)[i % 3]
+        reqs.append(("gmres", "hi", S.uniform_vector(pr["A"].n, seed * 100 + 70 + i), s, 4 * s, 6 + 2 * i))
     rng.shuffle(reqs)
     return reqs
 
@@ -77,8 +89,10 @@ def expected(pr, reqs):
     for r in reqs:
         if r[0] == "apply":
             out.append(alone_apply(pr[r[1]], r[2], r[3], r[4], r[5]))
-        else:
+        elif r[0] == "solve":
             out.append(alone_solve(pr["hi"], pr["lo"], r[2], r[3], lmin, lmax, 1e-10, 300))
+        else:
+            out.append(alone_gmres(pr["hi"], pr["lo"], r[2], r[3], r[4], r[5], lmin, lmax, 1e-10, 60))
     return out
 
 
@@ -86,7 +100,9 @@ def submit(srv, pr, r):
     lmin, lmax = pr["bounds"]
     if r[0] == "apply":
         return srv.submit_apply(pr[r[1]], r[2], r[3], permuted=r[4], **MODES[r[5]])
-    return srv.submit_solve(pr["hi"], pr["lo"], r[2], r[3], lmin, lmax, tol=1e-10, max_iter=300)
+    if r[0] == "solve":
+        return srv.submit_solve(pr["hi"], pr["lo"], r[2], r[3], lmin, lmax, tol=1e-10, max_iter=300)
+    return srv.submit_gmres(pr["hi"], pr["lo"], r[2], r[3], r[4], r[5], lmin, lmax, tol=1e-10, max_cycles=60)
 
 
 def check(r, got, want):
@@ -132,7 +148,7 @@ def test_served_apply_matches_oracle(problems):
 
 
 def test_submit_and_wait_from_many_host_threads(problems):
-    reqs = request_mix(problems, seed=9, napply=24, nsolve=2)
+    reqs = request_mix(problems, seed=9, napply=24, nsolve=2, ngmres=2)
     want = expected(problems, reqs)
     srv = Server(workers=3, device_bytes=256 << 20)
     errors = []
