@@ -39,6 +39,9 @@ sparse iterative solvers on multi-core CPUs"):
   ``sstep_gmres``                   -- Sec. 4 (s-step GMRES, Alg. 3a/3c: Newton
   basis, BOrtho, TSQR) with the right polynomial preconditioner of Sec. 5,
   readings R17-R19
+* ``diagonal``, ``jacobi_precondition``, ``jacobi_mpk`` -- Sec. 5.1 (Jacobi
+  preconditioner, k iterations from zero) in the right-preconditioned MPK,
+  reading R20
 
 Parity status of each function is stated in its docstring.  The readings
 taken where the paper is silent are listed in ``mpk_oracle.READINGS``.

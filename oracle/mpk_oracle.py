@@ -11,6 +11,7 @@ Parity status
 -------------
 pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_coeffs, refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          leja_order, chebyshev_scale, newton_shifts, cholqr_truncated, sstep_cycle, sstep_gmres,
+         diagonal, jacobi_precondition, jacobi_mpk,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
          hop_min, window_ok, min_workers,
@@ -118,6 +119,11 @@ READINGS = {
     "R19": "The solve stops when the FP64 residual at the start of a cycle satisfies "
            "||b - A x|| <= tol ||b|| or after max_cycles cycles; with reduced-precision "
            "values (R11) only the basis and the preconditioner use the rounded matrix.",
+    "R20": "Jacobi-preconditioned MPK (Sec. 5.1, right preconditioning of Sec. 5): "
+           "w_j = A P^{-1} w_{j-1}, P^{-1} v the k-th Jacobi iterate z^k from z^0 = 0 "
+           "(k = 1: P^{-1} = D^{-1}, the fused A D^{-1} of the paper; k > 1: the "
+           "Neumann-series polynomial preconditioner the paper mentions). The two-stage "
+           "Gauss-Seidel preconditioner is not covered.",
     "R11": "Reduced-precision matrix storage (the paper works in FP64 only): each stored "
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
@@ -467,6 +473,45 @@ def sstep_gmres(A, b, x0, s, m, d, lmin, lmax, tol, max_cycles, values=None):
             z = z + y[j] * Q[j]
         x = x + poly_chebyshev(Alo, z, c, theta, delta)
     return x, hist, iters
+
+
+# --------------------------------------------------------------------------- #
+# Sec. 5.1 (Jacobi preconditioner): the preconditioned MPK (A P^{-1})^j x
+# --------------------------------------------------------------------------- #
+def diagonal(A):
+    """The stored diagonal of A; raises ValueError if an entry is missing or zero."""
+    n, rp, c, v = _arrays(A)
+    d = np.zeros(n)
+    for i in range(n):
+        hit = np.nonzero(c[rp[i]:rp[i + 1]] == i)[0]
+        if hit.size == 0 or v[rp[i] + hit[0]] == 0.0:
+            raise ValueError(f"row {i} has no nonzero diagonal entry")
+        d[i] = v[rp[i] + hit[0]]
+    return d
+
+
+def jacobi_precondition(A, v, k):
+    """Sec. 5.1, the Jacobi iteration z^{i+1} = D^{-1} v - D^{-1} (L + U) z^i from z^0 = 0,
+    k iterations: z^k ~ A^{-1} v (k = 1 is the diagonal scaling D^{-1} v)."""
+    d = diagonal(A)
+    v = np.asarray(v, dtype=np.float64)
+    z = np.zeros_like(v)
+    for _ in range(k):
+        offdiag = spmv(A, z) - d * z          # (L + U) z
+        z = v / d - offdiag / d
+    return z
+
+
+def jacobi_mpk(A, x, p, k):
+    """Reading R20: the Jacobi-preconditioned MPK of Sec. 5 with right preconditioning,
+    w_0 = x, w_j = A P^{-1} w_{j-1} for j = 1..p, P^{-1} the k-sweep Jacobi iteration of
+    jacobi_precondition.  Returns W with W[j-1] = w_j."""
+    w = np.asarray(x, dtype=np.float64)
+    out = np.empty((p, w.size))
+    for j in range(p):
+        w = spmv(A, jacobi_precondition(A, w, k))
+        out[j] = w
+    return out
 
 
 def chebyshev_basis(A, x, d, theta, delta):
