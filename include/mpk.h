@@ -79,6 +79,10 @@ typedef enum {
                                      fl32(a_ij / s_i); s_i q_ij is formed exactly
                                      in FP64 at every use                      */
 
+/* mpk_options.column_scaling */
+#define MPK_SCALE_NONE 0
+#define MPK_SCALE_JACOBI 1
+
 /* call kinds for mpk_work_bytes */
 #define MPK_CALL_APPLY 0
 #define MPK_CALL_POLY 1
@@ -126,7 +130,15 @@ typedef struct {
                                 last-level cache the paper blocks for)        */
     int32_t min_group_rows;  /* row floor below which a level group is never
                                 closed (>= 0)                                 */
-    int32_t reserved[6];     /* must be zero                                  */
+    int32_t column_scaling;  /* MPK_SCALE_NONE (0): the plan holds A;
+                                MPK_SCALE_JACOBI (1): it holds B = A D^{-1},
+                                each value divided by its column's diagonal
+                                entry in FP64 before any rounding of
+                                value_type (the fused diagonally preconditioned
+                                operator of Sec. 5.1; every call then applies
+                                to B).  Needs a stored nonzero diagonal entry
+                                in every row (else MPK_ERR_CSR)               */
+    int32_t reserved[5];     /* must be zero                                  */
 } mpk_options;
 
 /* Fills *opt with the defaults (all zero). */
@@ -376,6 +388,28 @@ mpk_status mpk_sstep_gmres_work_bytes(mpk_plan_t lo, int32_t s, int32_t m, int32
 mpk_status sstep_basis(mpk_plan_t plan, int32_t s, const double* lambda, const double* sigma,
                        const double* v, double* V, int64_t ldv, uint32_t flags, void* work,
                        size_t work_bytes, void* stream);
+
+/*
+ * Jacobi-preconditioned matrix power kernel (Sec. 5.1 with the right
+ * preconditioning of Sec. 5): Y[(j-1)*ldy + i] = ((A P^{-1})^j x)[i] for
+ * j = 1..p, where P^{-1} v is the k-th Jacobi iterate
+ * z^{i+1} = D^{-1} v - D^{-1} (L + U) z^i from z^0 = 0.  The plan must hold
+ * B = A D^{-1} (column_scaling = MPK_SCALE_JACOBI).  Since
+ * A P^{-1} = I - (I - B)^k, k = 1 is the MPK of B (the fused A D^{-1} of the
+ * paper, blocked over all p powers), and k > 1 (the Neumann-series polynomial
+ * preconditioner) applies the Newton polynomial v - (-1)^k (B - I)^k v once per
+ * power, its k sub-powers blocked in one launch sequence (poly_apply).
+ * x (device, n) is only read; Y (device, p*ldy, ldy >= n) must not overlap x.
+ * Perm space with MPK_IO_PERMUTED.  work: mpk_jacobi_work_bytes(plan, k, p,
+ * flags) bytes.  Errors: MPK_ERR_ARG (plan without Jacobi scaling, k outside
+ * 1..64, p < 1, ldy < n, null pointers, work too small), MPK_ERR_STATE,
+ * MPK_ERR_HIP.
+ */
+mpk_status mpk_jacobi_apply(mpk_plan_t plan, int32_t k, const double* x, double* Y, int64_t ldy,
+                            int32_t p, uint32_t flags, void* work, size_t work_bytes, void* stream);
+
+/* Work bytes mpk_jacobi_apply needs for k sweeps, p powers and `flags`. */
+mpk_status mpk_jacobi_work_bytes(mpk_plan_t plan, int32_t k, int32_t p, uint32_t flags, size_t* bytes);
 
 /*
  * Permutes a device vector into the plan's level order, x_perm[i] = x[perm[i]]

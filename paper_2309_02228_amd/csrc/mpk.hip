@@ -626,6 +626,7 @@ struct mpk_plan_s {
     int q_eff[3][2] = {};    // powers per launch meeting the deadlock bound
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
+    int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
     std::vector<std::vector<mpk::StageTask>> sched;  // wavefront schedule per q (lazy, under mu)
     std::mutex mu;
 };
@@ -958,8 +959,10 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
     if (n > 0 && rowptr[n] > 0 && (!col || !val)) return fail(MPK_ERR_ARG, "col or val is null");
     mpk_options o{};
     if (opt) o = *opt;
-    for (int i = 0; i < 6; ++i)
+    for (int i = 0; i < 5; ++i)
         if (o.reserved[i] != 0) return fail(MPK_ERR_ARG, "mpk_options.reserved must be zero");
+    if (o.column_scaling != MPK_SCALE_NONE && o.column_scaling != MPK_SCALE_JACOBI)
+        return fail(MPK_ERR_ARG, "column_scaling must be MPK_SCALE_NONE (0) or MPK_SCALE_JACOBI (1)");
     if (o.cache_mib < 0) return fail(MPK_ERR_ARG, "cache_mib must be >= 0");
     if (o.min_group_rows < 0) return fail(MPK_ERR_ARG, "min_group_rows must be >= 0");
     if (o.max_reg_slots != 0 && o.max_reg_slots != 4 && o.max_reg_slots != 7 && o.max_reg_slots != 8 &&
@@ -978,6 +981,25 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
         return fail(MPK_ERR_ARG, "chunks_per_worker must be 0, 1, 2 or 4");
     std::string why = mpk::validate_csr(n, rowptr, col);
     if (!why.empty()) return fail(MPK_ERR_CSR, "%s", why.c_str());
+    // B = A D^{-1}: every value divided by its column's diagonal entry, in FP64
+    std::vector<double> scaled;
+    if (o.column_scaling == MPK_SCALE_JACOBI) {
+        try {
+            std::vector<double> diag(n, 0.0);
+            for (int32_t i = 0; i < n; ++i) {
+                for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+                    if (col[e] == i) diag[i] = val[e];
+                if (diag[i] == 0.0)
+                    return fail(MPK_ERR_CSR, "row %d has no nonzero diagonal entry (needed by column_scaling)", i);
+            }
+            const int32_t nnz = n > 0 ? rowptr[n] : 0;
+            scaled.resize(nnz);
+            for (int32_t e = 0; e < nnz; ++e) scaled[e] = val[e] / diag[col[e]];
+        } catch (const std::bad_alloc&) {
+            return fail(MPK_ERR_NOMEM, "out of host memory");
+        }
+        val = scaled.data();
+    }
     mpk_plan_s* p = new (std::nothrow) mpk_plan_s;
     if (!p) return fail(MPK_ERR_NOMEM, "out of host memory");
     try {
@@ -992,6 +1014,7 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
         p->H.max_reg = o.max_reg_slots;
         p->H.cache_bytes = (int64_t)(o.cache_mib ? o.cache_mib : 256) << 20;
         p->H.min_group_rows = o.min_group_rows;
+        p->column_scaling = o.column_scaling;
         mpk::build_plan(p->H, n, rowptr, col, val);
         p->L = make_layout(p->H);
     } catch (const std::bad_alloc&) {
@@ -1458,6 +1481,38 @@ MPK_API mpk_status sstep_basis(mpk_plan_t p, int32_t sdeg, const double* lambda,
     if (s != MPK_OK) return s;
     if (!permuted) s = permute_vecs(p, st, Vp, ld, V, ldv, sdeg + 1, 1);
     return s;
+}
+
+MPK_API mpk_status mpk_jacobi_work_bytes(mpk_plan_t p, int32_t k, int32_t pw, uint32_t flags, size_t* bytes) {
+    if (!p || !bytes) return fail(MPK_ERR_ARG, "null argument");
+    if (k < 1 || k > 64) return fail(MPK_ERR_ARG, "k must be in 1..64 (got %d)", k);
+    if (pw < 1) return fail(MPK_ERR_ARG, "p must be >= 1 (got %d)", pw);
+    return k == 1 ? mpk_work_bytes(p, MPK_CALL_APPLY, pw, flags, bytes)
+                  : mpk_work_bytes(p, MPK_CALL_POLY, k, flags, bytes);
+}
+
+MPK_API mpk_status mpk_jacobi_apply(mpk_plan_t p, int32_t k, const double* x, double* Y, int64_t ldy, int32_t pw,
+                                    uint32_t flags, void* work, size_t work_bytes, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (p->column_scaling != MPK_SCALE_JACOBI)
+        return fail(MPK_ERR_ARG, "the plan must hold A D^{-1} (column_scaling = MPK_SCALE_JACOBI)");
+    if (k < 1 || k > 64) return fail(MPK_ERR_ARG, "k must be in 1..64 (got %d)", k);
+    if (pw < 1) return fail(MPK_ERR_ARG, "p must be >= 1 (got %d)", pw);
+    if (ldy < p->H.n) return fail(MPK_ERR_ARG, "ldy must be >= n");
+    if (p->H.n > 0 && (!x || !Y)) return fail(MPK_ERR_ARG, "x or Y is null");
+    if (k == 1) return mpk_apply(p, x, Y, ldy, pw, flags, work, work_bytes, stream);
+    // A P^{-1} = I - (I - B)^k = I - (-1)^k (B - I)^k: a Newton polynomial with all
+    // shifts 1, coefficients c_0 = 1 and c_k = -(-1)^k
+    std::vector<double> c(k + 1, 0.0), lam(k, 1.0);
+    c[0] = 1.0;
+    c[k] = (k % 2) ? 1.0 : -1.0;
+    for (int32_t j = 0; j < pw; ++j) {
+        const double* in = j == 0 ? x : Y + (int64_t)(j - 1) * ldy;
+        mpk_status s = poly_apply(p, MPK_POLY_NEWTON, k, c.data(), lam.data(), in, Y + (int64_t)j * ldy, flags,
+                                  work, work_bytes, stream);
+        if (s != MPK_OK) return s;
+    }
+    return MPK_OK;
 }
 
 MPK_API mpk_status mpk_permute(mpk_plan_t p, const double* in, double* out, int32_t direction, void* stream) {

@@ -33,7 +33,7 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy",
            "mpk_server_create", "mpk_server_submit_apply", "mpk_server_submit_solve",
            "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes",
-           "mpk_server_submit_gmres"]
+           "mpk_server_submit_gmres", "mpk_jacobi_apply", "mpk_jacobi_work_bytes"]
 
 
 class MPKError(RuntimeError):
@@ -48,7 +48,7 @@ class Options(ctypes.Structure):
                 ("watchdog_polls", ctypes.c_int32), ("chunks_per_worker", ctypes.c_int32),
                 ("value_type", ctypes.c_int32), ("max_reg_slots", ctypes.c_int32),
                 ("cache_mib", ctypes.c_int32), ("min_group_rows", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 6)]
+                ("column_scaling", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
 
 
 def _load():
@@ -97,6 +97,8 @@ def _load():
         "mpk_sstep_gmres": (I32, [P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double, P, P, ctypes.c_double,
                                   I32, U32, P, SZ, pI32, pI32, ctypes.POINTER(ctypes.c_double), P]),
         "mpk_sstep_gmres_work_bytes": (I32, [P, I32, I32, I32, U32, pSZ]),
+        "mpk_jacobi_apply": (I32, [P, I32, P, P, I64, I32, U32, P, SZ, P]),
+        "mpk_jacobi_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_server_submit_gmres": (I32, [P, P, P, P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, I32, U32, pI64]),
     }
@@ -146,7 +148,7 @@ class Plan:
 
     def __init__(self, n, rowptr, col, val, root=None, p_block=0, workers_per_xcd=0,
                  watchdog_polls=0, chunks_per_worker=0, values="f64", max_reg_slots=0, cache_mib=0,
-                 min_group_rows=0):
+                 min_group_rows=0, column_scaling=None):
         self._h = None
         self.n = int(n)
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
@@ -166,6 +168,10 @@ class Plan:
         opt.max_reg_slots = int(max_reg_slots)
         opt.cache_mib = int(cache_mib)
         opt.min_group_rows = int(min_group_rows)
+        if column_scaling not in (None, "jacobi"):
+            raise ValueError("column_scaling must be None or 'jacobi' (the plan then holds A D^-1)")
+        opt.column_scaling = 1 if column_scaling == "jacobi" else 0
+        self.column_scaling = column_scaling
         self.values = values
         h = ctypes.c_void_p()
         nbytes = ctypes.c_size_t()
@@ -313,6 +319,20 @@ class Plan:
                                      float(tol), int(max_iter), flags, _dptr(w), nb, ctypes.byref(it),
                                      ctypes.byref(rel), _stream(stream)))
         return x, it.value, rel.value
+
+    def jacobi_apply(self, x, p, k, Y=None, permuted=True, plain=False, staged=False, stream=None):
+        """W[j-1] = (A P^{-1})^j x, j = 1..p, with P^{-1} k Jacobi sweeps from zero; the
+        plan must hold A D^{-1} (column_scaling="jacobi").  Returns a (p, n) tensor."""
+        import torch
+        if Y is None:
+            Y = torch.empty((p, self.n), dtype=torch.float64, device=x.device)
+        flags = self._flags(permuted, plain, staged)
+        nb = ctypes.c_size_t()
+        _check(_lib.mpk_jacobi_work_bytes(self._h, int(k), int(p), flags, ctypes.byref(nb)))
+        w = torch.empty(nb.value // 8 + 1, dtype=torch.float64, device=x.device) if nb.value else None
+        _check(_lib.mpk_jacobi_apply(self._h, int(k), _dptr(x), _dptr(Y), Y.stride(0), int(p), flags,
+                                     _dptr(w) if w is not None else None, nb.value, _stream(stream)))
+        return Y
 
     def gmres_work_bytes(self, s, m, degree, permuted=True):
         nb = ctypes.c_size_t()

@@ -292,3 +292,40 @@ def test_sstep_gmres_argument_errors_without_gpu():
     assert call(work=ctypes.c_void_p((1 << 20) + 8)) == -1  # misaligned
     assert call() == -6                            # not uploaded
     assert "upload" in lib.mpk_last_error().decode()
+
+
+def test_jacobi_scaling_and_apply_argument_errors_without_gpu():
+    lib = M.lib()
+    # a row without a stored (or with a zero) diagonal entry is refused for column scaling
+    with pytest.raises(M.MPKError, match="MPK_ERR_CSR"):
+        M.Plan.from_csr(S.cyclic_shift(6), column_scaling="jacobi")
+    with pytest.raises(M.MPKError, match="MPK_ERR_CSR"):
+        M.Plan.from_csr(S.from_dense(np.array([[0.0, 1.0], [1.0, 2.0]]), keep_zeros=True),
+                        column_scaling="jacobi")
+    with pytest.raises(ValueError):
+        M.Plan.from_csr(S.laplacian_2d(4), column_scaling="gs2")
+    A = S.laplacian_2d(8)
+    plain = M.Plan.from_csr(A)
+    jac = M.Plan.from_csr(A, column_scaling="jacobi")
+    # the level structure does not depend on the values
+    assert np.array_equal(plain.levels()["perm"], jac.levels()["perm"])
+    nb = ctypes.c_size_t()
+    assert lib.mpk_jacobi_work_bytes(jac._h, 1, 4, 1, ctypes.byref(nb)) == 0
+    assert lib.mpk_jacobi_work_bytes(jac._h, 0, 4, 1, ctypes.byref(nb)) == -1
+    assert lib.mpk_jacobi_work_bytes(jac._h, 65, 4, 1, ctypes.byref(nb)) == -1
+    assert lib.mpk_jacobi_work_bytes(jac._h, 2, 0, 1, ctypes.byref(nb)) == -1
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.mpk_jacobi_apply(plain._h, 1, fake, fake, 64, 2, 1, None, 0, None) == -1  # not scaled
+    assert lib.mpk_jacobi_apply(jac._h, 0, fake, fake, 64, 2, 1, None, 0, None) == -1    # k < 1
+    assert lib.mpk_jacobi_apply(jac._h, 2, fake, fake, 64, 0, 1, None, 0, None) == -1    # p < 1
+    assert lib.mpk_jacobi_apply(jac._h, 2, fake, fake, 63, 2, 1, None, 0, None) == -1    # ldy < n
+    assert lib.mpk_jacobi_apply(jac._h, 2, None, fake, 64, 2, 1, None, 0, None) == -1    # null x
+    assert lib.mpk_jacobi_apply(jac._h, 2, fake, fake, 64, 2, 1, None, 0, None) == -1    # no ring work
+    assert lib.mpk_jacobi_apply(jac._h, 1, fake, fake, 64, 2, 1, None, 0, None) == -6    # not uploaded
+    opt = M.Options()
+    lib.mpk_options_default(ctypes.byref(opt))
+    opt.column_scaling = 2
+    h, nbytes = ctypes.c_void_p(), ctypes.c_size_t()
+    rp, c, v = (np.ascontiguousarray(a) for a in (A.rowptr, A.col, A.val))
+    assert lib.mpk_build_levels(A.n, M._ptr(rp), M._ptr(c), M._ptr(v), ctypes.byref(opt), ctypes.byref(h),
+                                ctypes.byref(nbytes)) == -1
