@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--serve-pool-gib", type=int, default=8)
     ap.add_argument("--serve-seed", type=int, default=5)
     ap.add_argument("--solve-degree", type=int, default=256)
+    ap.add_argument("--gmres-only", action="store_true",
+                    help="run only s-step GMRES solves of the 3D stencil (profiler target)")
     ap.add_argument("--gmres-s", type=int, default=8)
     ap.add_argument("--gmres-m", type=int, default=64)
     ap.add_argument("--gmres-degree", type=int, default=32)
@@ -289,6 +291,22 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = "cuda:0"
+    if args.gmres_only:
+        # profiler target: the s-step GMRES solve of the 3D 7-point Laplacian alone
+        g = args.grid
+        A = synth.laplacian_3d(g)
+        cg = np.cos(np.pi / (g + 1))
+        lmin, lmax = 3 * (2 - 2 * cg), 3 * (2 + 2 * cg)
+        hi8 = Plan.from_csr(A, p_block=8).upload(dev)
+        lo8 = Plan.from_csr(A, p_block=8, values="f32").upload(dev)
+        bvec = hi8.permute(torch.tensor(synth.uniform_vector(A.n, 1), device=dev), 0)
+        for r in range(args.solve_reps):
+            res = hi8.sstep_gmres(lo8, bvec, args.gmres_s, args.gmres_m, args.gmres_degree, lmin, lmax, tol=1e-10,
+                                  max_cycles=200)
+            log(f"gmres solve {r}: {res[1]} vectors, {res[2]} cycles, relres {res[3]:.3e}")
+        lo8.check()
+        print(json.dumps({"gmres_solves": args.solve_reps, "basis_vectors": res[1], "relres": res[3]}), flush=True)
+        return
     if args.calibrate_copy:
         nbytes = args.calibrate_copy << 20
         src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
@@ -445,6 +463,35 @@ def main():
         out["p_sweep"] = sweep
         log("p sweep: " + ", ".join(f"p={k}: {v['speedup']}x" for k, v in sweep.items()))
         del plan8, Y8
+    if args.only == "both" and not args.no_sweep:
+        # Jacobi-preconditioned MPK (A P^{-1})^j x, j = 1..p, with k Jacobi sweeps: the plan
+        # holds A D^{-1}; blocked against plain launches on the same layout
+        planj = Plan.from_csr(A, p_block=8, column_scaling="jacobi").upload(dev)
+        xj = planj.permute(torch.tensor(x, device=dev), 0)
+        Yj = torch.empty((p, n), dtype=torch.float64, device=dev)
+        jac = {}
+        for k in (1, 2, 4):
+            t = {}
+            for plain_ in (False, True):
+                for _ in range(3):
+                    planj.jacobi_apply(xj, p, k, Y=Yj, plain=plain_)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(10):
+                    planj.jacobi_apply(xj, p, k, Y=Yj, plain=plain_)
+                e1.record(stream)
+                e1.synchronize()
+                t[plain_] = e0.elapsed_time(e1) / 10 * 1e-3
+            planj.check()
+            f = 2.0 * nnz * p * k
+            jac[f"k={k}"] = {"blocked_us": round(t[False] * 1e6, 1), "plain_us": round(t[True] * 1e6, 1),
+                             "blocked_gflops": round(f / t[False] / 1e9, 1), "speedup": round(t[True] / t[False], 3),
+                             "sub_powers": p * k}
+        out["jacobi_mpk"] = {"workload": f"(A P^-1)^j x, j = 1..{p}, P^-1 = k Jacobi sweeps from zero, "
+                                         f"3D 7-point Laplacian {g}^3, plan of A D^-1 with blocks of up to 8",
+                             **jac}
+        log("jacobi: " + ", ".join(f"{kk}: {v['blocked_us']} us blocked, {v['speedup']}x" for kk, v in jac.items()))
+        del planj, Yj
     for vals in ([] if args.no_f32 or args.only != "both" else ["f32", "bf16"]):
         # reduced-precision storage of the matrix values (vectors, products and sums stay FP64)
         # with four chunks per wave: the narrow values leave registers for them (measured

@@ -50,7 +50,8 @@ __device__ __forceinline__ void halve(double* v, int lane) {
     }
 }
 
-// part[rb][j][k] = sum over rows r of block rb of X[j][r] * Y[k][r], j < a, k < b.
+// part[j][k][rb] = sum over rows r of block rb of X[j][r] * Y[k][r], j < a, k < b
+// (element-major, so that the reduction reads each element's partials contiguously).
 // A workgroup covers one row block and one JB x KB tile; workgroups of the same row
 // block sit on the same XCD (workgroup i runs on XCD i mod 8), so the tiles re-read
 // each other's rows from that XCD's L2.
@@ -70,6 +71,7 @@ __global__ __launch_bounds__(kThreads) void gram_partial_kernel(const double* __
     for (int e = 0; e < JB * KB; ++e) acc[e] = 0.0;
     const int r0 = rb * rows_per_blk;
     const int r1 = min(n, r0 + rows_per_blk);
+#pragma unroll 2
     for (int r = r0 + (int)threadIdx.x; r < r1; r += kThreads) {
         double xv[JB], yv[KB];
 #pragma unroll
@@ -107,17 +109,28 @@ __global__ __launch_bounds__(kThreads) void gram_partial_kernel(const double* __
         double sum = 0.0;
 #pragma unroll
         for (int w = 0; w < kThreads / 64; ++w) sum += red[w][e];
-        if (j0 + j < a && k0 + k < b) part[((int64_t)rb * a + j0 + j) * b + k0 + k] = sum;
+        if (j0 + j < a && k0 + k < b) part[((int64_t)(j0 + j) * b + k0 + k) * nrb + rb] = sum;
     }
 }
 
-// out[e] = sum over row blocks, in order, of part[rb][e], e < count.
-__global__ void reduce_parts_kernel(const double* __restrict__ part, int nrb, int count, double* __restrict__ out) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= count) return;
+// out[e] = sum over the row blocks of part[e][rb]: one workgroup per element, each
+// thread a fixed strided subset of row blocks, then a fixed tree, so the order of the
+// additions never changes.
+__global__ __launch_bounds__(kThreads) void reduce_parts_kernel(const double* __restrict__ part, int nrb,
+                                                                double* __restrict__ out) {
+    const int e = blockIdx.x;
+    const double* src = part + (int64_t)e * nrb;
     double s = 0.0;
-    for (int rb = 0; rb < nrb; ++rb) s += part[(int64_t)rb * count + e];
-    out[e] = s;
+    for (int rb = threadIdx.x; rb < nrb; rb += kThreads) s += src[rb];
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    __shared__ double red[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+        out[e] = t;
+    }
 }
 
 // Y[k][r] = alpha X0[k][r] + sum_{j < a} Q[j][r] C[j b + k], k < b <= KB.
@@ -134,6 +147,7 @@ __global__ __launch_bounds__(kThreads) void lincomb_kernel(const double* X0, int
         double acc[KB];
 #pragma unroll
         for (int k = 0; k < KB; ++k) acc[k] = (k < b && X0) ? alpha * X0[k * ldx0 + r] : 0.0;
+#pragma unroll 4
         for (int j = 0; j < a; ++j) {
             const double q = Q[j * ldq + r];
 #pragma unroll
@@ -262,8 +276,7 @@ struct Solver {
         mpk_status s_ = hip(hipGetLastError(), "gram launch");
         if (s_ != MPK_OK) return s_;
         const int count = a * b;
-        hipLaunchKernelGGL(reduce_parts_kernel, dim3((count + 255) / 256), dim3(256), 0, st, part, L.nrb, count,
-                           vec(L.small));
+        hipLaunchKernelGGL(reduce_parts_kernel, dim3(count), dim3(kThreads), 0, st, part, L.nrb, vec(L.small));
         s_ = hip(hipGetLastError(), "reduce launch");
         if (s_ != MPK_OK) return s_;
         out.assign(count, 0.0);
