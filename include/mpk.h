@@ -396,9 +396,12 @@ mpk_status sstep_basis(mpk_plan_t plan, int32_t s, const double* lambda, const d
  * z^{i+1} = D^{-1} v - D^{-1} (L + U) z^i from z^0 = 0.  The plan must hold
  * B = A D^{-1} (column_scaling = MPK_SCALE_JACOBI).  Since
  * A P^{-1} = I - (I - B)^k, k = 1 is the MPK of B (the fused A D^{-1} of the
- * paper, blocked over all p powers), and k > 1 (the Neumann-series polynomial
- * preconditioner) applies the Newton polynomial v - (-1)^k (B - I)^k v once per
- * power, its k sub-powers blocked in one launch sequence (poly_apply).
+ * paper, blocked over all p powers).  For k > 1 (the Neumann-series polynomial
+ * preconditioner) the p k sub-powers u = (B - I) u_prev form one chain in
+ * which every k-th sub-power closes a link, w_j = w_{j-1} - (-1)^k u; with
+ * MPK_IO_PERMUTED the chain is blocked across links like any matrix power
+ * (the P^{-1} -> A -> P^{-1} dependencies of Sec. 5), otherwise each power is
+ * one Newton polynomial through poly_apply; both give bitwise equal results.
  * x (device, n) is only read; Y (device, p*ldy, ldy >= n) must not overlap x.
  * Perm space with MPK_IO_PERMUTED.  work: mpk_jacobi_work_bytes(plan, k, p,
  * flags) bytes.  Errors: MPK_ERR_ARG (plan without Jacobi scaling, k outside

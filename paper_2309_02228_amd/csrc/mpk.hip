@@ -49,7 +49,12 @@ constexpr uint32_t kEpochLimit = 1u << 27; // done words hold epoch * 16 + power
 // invalidate the line under the other chunks' pollers.
 constexpr int kFlagStride = 32;
 
-enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2 };
+// KIND_JCHAIN: the Jacobi-preconditioned chain w_j = w_{j-1} + c (B - I)^k w_{j-1}
+// (c = -(-1)^k) as one sequence of sub-powers u = (B - I) u_prev; every k-th
+// sub-power closes a link with w_j = fma(c, u, w_{j-1}), which is stored both in the
+// ring (the next sub-power's input) and as output column j.
+enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2, KIND_JCHAIN = 3 };
+constexpr int kKinds = 4;
 
 // ------------------------------------------------------------------ device
 struct DevPlan {
@@ -76,6 +81,8 @@ struct Coefs {
     double sig[kMaxQ];  // Newton column scaling
     double c[kMaxQ];    // polynomial coefficient of the power
     double theta, delta;
+    int jk;             // KIND_JCHAIN: sub-powers per link
+    double jc;          // KIND_JCHAIN: coefficient of (B - I)^k at the end of a link
 };
 
 __device__ __forceinline__ double load_coherent(const double* p) {
@@ -89,11 +96,16 @@ __device__ __forceinline__ uint32_t load_word(const uint32_t* p) {
 }
 
 // Operator kind applied to s = (A y_{k-1})_i with the row's own y_{k-1}, y_{k-2}.
+// `link0` is the chain's value at the start of the current link (KIND_JCHAIN).
 template <int KIND>
-__device__ __forceinline__ double finish(double s, double prev, double prev2, int gk, int kl,
+__device__ __forceinline__ double finish(double s, double prev, double prev2, double link0, int gk, int kl,
                                          const Coefs& C) {
     if (KIND == KIND_MONO) return s;
     if (KIND == KIND_NEWTON) return fma(-C.lam[kl], prev, s) / C.sig[kl];
+    if (KIND == KIND_JCHAIN) {
+        const double u = s - prev;
+        return gk % C.jk == 0 ? fma(C.jc, u, link0) : u;
+    }
     const double t = fma(-C.theta, prev, s);
     return gk == 1 ? t / C.delta : (2.0 * t) / C.delta - prev2;
 }
@@ -108,6 +120,9 @@ struct SpmvArgs {
     double* acc_out;      // polynomial accumulator after this power (null: none)
     double c0;
     int gk;               // global power index of this launch
+    const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link
+    double* link_out;       // KIND_JCHAIN: output column j - 1 receives w_j
+    int64_t link_ld;
     Coefs C;              // entry 0 describes this power
 };
 
@@ -176,8 +191,11 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
         if (row < a.P.n) {
             const double prev = (KIND != KIND_MONO || POLY) ? a.in[row] : 0.0;
             const double prev2 = (KIND == KIND_CHEB && a.prev2) ? a.prev2[row] : 0.0;
-            const double y = finish<KIND>(s, prev, prev2, a.gk, 0, a.C);
+            const double link0 = KIND == KIND_JCHAIN ? a.link_in[row] : 0.0;
+            const double y = finish<KIND>(s, prev, prev2, link0, a.gk, 0, a.C);
             a.out[row] = y;
+            if (KIND == KIND_JCHAIN && a.gk % a.C.jk == 0)
+                a.link_out[(int64_t)(a.gk / a.C.jk - 1) * a.link_ld + row] = y;
             if (POLY) {
                 const double acc = a.acc_in ? a.acc_in[row] : a.c0 * prev;
                 a.acc_out[row] = fma(a.C.c[0], y, acc);
@@ -205,6 +223,9 @@ struct BlockArgs {
     int spin_limit;       // watchdog polls; negative: give up at once
     int plain_gather;     // 1: powers written in this launch may be read with plain loads
     uint32_t epoch;
+    const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link of y_{base+1}
+    double* link_out;       // KIND_JCHAIN: output column j - 1 receives w_j
+    int64_t link_ld;
     Coefs C;
 };
 
@@ -328,11 +349,12 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
         // the row's own previous value is needed by the shifted kinds, the
         // polynomial accumulator and the basis copy only
         const bool need_prev = KIND != KIND_MONO || POLY || a.copy0 != nullptr;
-        double prev[G], prev2[G], acc[G];
+        double prev[G], prev2[G], acc[G], link0[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const bool act = c[g] >= 0 && row[g] < a.P.n;
             prev[g] = (act && need_prev) ? a.in[row[g]] : 0.0;
+            link0[g] = (KIND == KIND_JCHAIN && act) ? a.link_in[row[g]] : 0.0;
             prev2[g] = (KIND == KIND_CHEB && act && a.prev2) ? a.prev2[row[g]] : 0.0;
             if (a.copy0 && act) a.copy0[row[g]] = prev[g];
             acc[g] = 0.0;
@@ -391,10 +413,15 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
             const bool last = kl + 1 == a.q;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const double y = finish<KIND>(s[g], prev[g], prev2[g], a.base + kl + 1, kl, a.C);
+                const double y = finish<KIND>(s[g], prev[g], prev2[g], link0[g], a.base + kl + 1, kl, a.C);
                 if (c[g] >= 0 && row[g] < a.P.n) {
                     if (!last) store_coherent(dst + row[g], y);
                     else dst[row[g]] = y;  // nobody reads the last power in this launch
+                }
+                if (KIND == KIND_JCHAIN && (a.base + kl + 1) % a.C.jk == 0) {
+                    link0[g] = y;  // the link closes: w_j starts the next one
+                    if (c[g] >= 0 && row[g] < a.P.n)
+                        a.link_out[(int64_t)((a.base + kl + 1) / a.C.jk - 1) * a.link_ld + row[g]] = y;
                 }
                 if (POLY) acc[g] = fma(a.C.c[kl], y, acc[g]);
                 prev2[g] = prev[g];
@@ -425,6 +452,7 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
 struct StageTaskDev {
     const double* in;     // y_{gk-1}
     const double* prev2;  // y_{gk-2} (Chebyshev), null for gk < 2
+    const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link
     double* out;          // y_gk
     int c0, nchunks;      // chunks covering rows [r0, r1)
     int r0, r1;
@@ -437,6 +465,8 @@ struct StageArgs {
     int ntasks;
     double* acc;  // polynomial accumulator, updated in place (null: none)
     double c0;
+    double* link_out;  // KIND_JCHAIN: output column j - 1 receives w_j
+    int64_t link_ld;
     Coefs C;
 };
 
@@ -458,8 +488,11 @@ __global__ __launch_bounds__(kBlockThreads) void stage_kernel(StageArgs a) {
         if (row >= T.r0 && row < T.r1) {
             const double prev = (KIND != KIND_MONO || POLY) ? T.in[row] : 0.0;
             const double prev2 = (KIND == KIND_CHEB && T.prev2) ? T.prev2[row] : 0.0;
-            const double y = finish<KIND>(s, prev, prev2, T.gk, T.kl, a.C);
+            const double link0 = KIND == KIND_JCHAIN ? T.link_in[row] : 0.0;
+            const double y = finish<KIND>(s, prev, prev2, link0, T.gk, T.kl, a.C);
             T.out[row] = y;
+            if (KIND == KIND_JCHAIN && T.gk % a.C.jk == 0)
+                a.link_out[(int64_t)(T.gk / a.C.jk - 1) * a.link_ld + row] = y;
             if (POLY) {
                 const double acc = T.gk == 1 ? a.c0 * prev : a.acc[row];
                 a.acc[row] = fma(a.C.c[T.kl], y, acc);
@@ -621,9 +654,9 @@ struct mpk_plan_s {
     uint32_t epoch = 0;
     // blocked launch shape per operator variant [kind][poly]: every workgroup
     // must be resident at once, so the grid is the variant's occupancy limit
-    int workers[3][2] = {};  // waves per partition
-    int grid_block[3][2] = {};
-    int q_eff[3][2] = {};    // powers per launch meeting the deadlock bound
+    int workers[kKinds][2] = {};  // waves per partition
+    int grid_block[kKinds][2] = {};
+    int q_eff[kKinds][2] = {};    // powers per launch meeting the deadlock bound
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
     int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
@@ -653,6 +686,7 @@ BlockFn block_fn(int reg) {
 
 template <int G, typename VT>
 BlockFn pick_block_g(int reg, int kind, bool poly) {
+    if (kind == KIND_JCHAIN) return block_fn<G, KIND_JCHAIN, false, VT>(reg);  // never polynomial
     if (kind == KIND_MONO)
         return poly ? block_fn<G, KIND_MONO, true, VT>(reg) : block_fn<G, KIND_MONO, false, VT>(reg);
     if (kind == KIND_NEWTON)
@@ -676,6 +710,7 @@ BlockFn pick_block(const mpk::HostPlan& H, int kind, bool poly) {
 
 template <typename VT>
 SpmvFn pick_spmv_vt(int kind, bool poly) {
+    if (kind == KIND_JCHAIN) return spmv_kernel<KIND_JCHAIN, false, VT>;
     if (kind == KIND_MONO) return poly ? spmv_kernel<KIND_MONO, true, VT> : spmv_kernel<KIND_MONO, false, VT>;
     if (kind == KIND_NEWTON) return poly ? spmv_kernel<KIND_NEWTON, true, VT> : spmv_kernel<KIND_NEWTON, false, VT>;
     return poly ? spmv_kernel<KIND_CHEB, true, VT> : spmv_kernel<KIND_CHEB, false, VT>;
@@ -684,6 +719,7 @@ SpmvFn pick_spmv_vt(int kind, bool poly) {
 using StageFn = void (*)(StageArgs);
 template <typename VT>
 StageFn pick_stage_vt(int kind, bool poly) {
+    if (kind == KIND_JCHAIN) return stage_kernel<KIND_JCHAIN, false, VT>;
     if (kind == KIND_MONO) return poly ? stage_kernel<KIND_MONO, true, VT> : stage_kernel<KIND_MONO, false, VT>;
     if (kind == KIND_NEWTON)
         return poly ? stage_kernel<KIND_NEWTON, true, VT> : stage_kernel<KIND_NEWTON, false, VT>;
@@ -785,10 +821,23 @@ struct PowerJob {
     double* acc = nullptr;
     std::vector<double> lam, sig, c;  // per global power k (index k-1); c[0] = c_0
     double theta = 0, delta = 1;
+    int jk = 1;                 // KIND_JCHAIN: sub-powers per link
+    double jc = 0;              // KIND_JCHAIN: coefficient of (B - I)^k closing a link
+    double* link_out = nullptr; // KIND_JCHAIN: w_j (j = 1..p / jk) at link_out + (j-1) * link_ld
+    int64_t link_ld = 0;
 };
 
 double* job_dest(const PowerJob& j, int k) { return j.out0 + (int64_t)((k - 1) % j.mod) * j.ld; }
 const double* job_vec(const PowerJob& j, int k) { return k == 0 ? j.x : job_dest(j, k); }
+// KIND_JCHAIN: the chain's value at the start of the link that holds sub-power k
+const double* link_start(const PowerJob& j, int k) {
+    const int t = (k - 1) / j.jk * j.jk;
+    return t == 0 ? j.x : j.link_out + (int64_t)(t / j.jk - 1) * j.link_ld;
+}
+void set_chain(const PowerJob& j, Coefs& C) {
+    C.jk = j.jk;
+    C.jc = j.jc;
+}
 
 const std::vector<mpk::StageTask>& schedule(mpk_plan_t p, int q) {
     std::lock_guard<std::mutex> lk(p->mu);  // sched is sized at plan creation: no reallocation
@@ -811,6 +860,9 @@ mpk_status run_staged(mpk_plan_t p, hipStream_t st, const PowerJob& j) {
             a.c0 = j.poly ? j.c[0] : 0.0;
             a.C.theta = j.theta;
             a.C.delta = j.delta;
+            set_chain(j, a.C);
+            a.link_out = j.link_out;
+            a.link_ld = j.link_ld;
             int total = 0;
             size_t t1 = t0;
             for (; t1 < tasks.size() && tasks[t1].stage == tasks[t0].stage; ++t1) {
@@ -819,6 +871,7 @@ mpk_status run_staged(mpk_plan_t p, hipStream_t st, const PowerJob& j) {
                 StageTaskDev& d = a.t[a.ntasks++];
                 d.in = job_vec(j, gk - 1);
                 d.prev2 = (j.kind == KIND_CHEB && gk >= 2) ? job_vec(j, gk - 2) : nullptr;
+                d.link_in = j.kind == KIND_JCHAIN ? link_start(j, gk) : nullptr;
                 d.out = job_dest(j, gk);
                 d.r0 = T.row_begin;
                 d.r1 = T.row_end;
@@ -855,6 +908,10 @@ mpk_status plain_power(mpk_plan_t p, hipStream_t st, const PowerJob& j, int k) {
     a.C.c[0] = j.poly ? j.c[k] : 0.0;
     a.C.theta = j.theta;
     a.C.delta = j.delta;
+    set_chain(j, a.C);
+    a.link_in = j.kind == KIND_JCHAIN ? link_start(j, k) : nullptr;
+    a.link_out = j.link_out;
+    a.link_ld = j.link_ld;
     if (k == 1 && j.copy0) {
         HIP_TRY(hipMemcpyAsync(j.copy0, j.x, sizeof(double) * p->H.n, hipMemcpyDeviceToDevice, st));
     }
@@ -914,6 +971,10 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
         }
         a.C.theta = j.theta;
         a.C.delta = j.delta;
+        set_chain(j, a.C);
+        a.link_in = j.kind == KIND_JCHAIN ? link_start(j, base + 1) : nullptr;
+        a.link_out = j.link_out;
+        a.link_ld = j.link_ld;
         mpk_status s = launch_block(p, st, j.kind, j.poly, a);
         if (s != MPK_OK) return s;
     }
@@ -1174,7 +1235,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     int maxlen = 0;
     for (int x = 0; x < kParts; ++x) maxlen = std::max(maxlen, H.seq_ptr[x + 1] - H.seq_ptr[x]);
     const int maxunits = (maxlen + H.group - 1) / H.group;
-    for (int kind = 0; kind < 3; ++kind)
+    for (int kind = 0; kind < kKinds; ++kind)
         for (int poly = 0; poly < 2; ++poly) {
             int occ = 0;
             if (!pick_block(H, kind, poly)) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this plan");
@@ -1501,11 +1562,36 @@ MPK_API mpk_status mpk_jacobi_apply(mpk_plan_t p, int32_t k, const double* x, do
     if (ldy < p->H.n) return fail(MPK_ERR_ARG, "ldy must be >= n");
     if (p->H.n > 0 && (!x || !Y)) return fail(MPK_ERR_ARG, "x or Y is null");
     if (k == 1) return mpk_apply(p, x, Y, ldy, pw, flags, work, work_bytes, stream);
-    // A P^{-1} = I - (I - B)^k = I - (-1)^k (B - I)^k: a Newton polynomial with all
-    // shifts 1, coefficients c_0 = 1 and c_k = -(-1)^k
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    size_t need = 0;
+    mpk_jacobi_work_bytes(p, k, pw, flags, &need);
+    if (need > 0 && (!work || work_bytes < need))
+        return fail(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    // A P^{-1} = I - (I - B)^k = I - (-1)^k (B - I)^k.  In level order the p k
+    // sub-powers run as one chain (KIND_JCHAIN), blocked across the links.
+    const double cjk = (k % 2) ? 1.0 : -1.0;  // -(-1)^k
+    if (flags & MPK_IO_PERMUTED) {
+        mpk_status s = check_uploaded(p);
+        if (s != MPK_OK) return s;
+        if (p->H.n == 0) return MPK_OK;
+        PowerJob j;
+        j.kind = KIND_JCHAIN;
+        j.p = pw * k;
+        j.x = x;
+        j.out0 = (double*)work;  // ring of sub-powers
+        j.ld = p->H.n;
+        j.mod = poly_ring(p);
+        j.jk = k;
+        j.jc = cjk;
+        j.link_out = Y;
+        j.link_ld = ldy;
+        return run_powers(p, (hipStream_t)stream, j, flags & MPK_PLAIN, flags & MPK_STAGED);
+    }
+    // original row order: one Newton polynomial per power (all shifts 1, c_0 = 1,
+    // c_k = -(-1)^k) through poly_apply, which permutes; the same arithmetic
     std::vector<double> c(k + 1, 0.0), lam(k, 1.0);
     c[0] = 1.0;
-    c[k] = (k % 2) ? 1.0 : -1.0;
+    c[k] = cjk;
     for (int32_t j = 0; j < pw; ++j) {
         const double* in = j == 0 ? x : Y + (int64_t)(j - 1) * ldy;
         mpk_status s = poly_apply(p, MPK_POLY_NEWTON, k, c.data(), lam.data(), in, Y + (int64_t)j * ldy, flags,

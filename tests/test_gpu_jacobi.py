@@ -68,14 +68,17 @@ def test_jacobi_mpk_matches_oracle(mk, k):
     assert rel_err(W, R) <= TOL
 
 
-@pytest.mark.parametrize("k", [1, 3])
-def test_blocked_plain_staged_and_io_orders_bitwise(k):
+@pytest.mark.parametrize("k,q", [(1, 4), (3, 4), (2, 3), (5, 4), (4, 8), (2, 15)])
+def test_blocked_plain_staged_and_io_orders_bitwise(k, q):
+    # in level order the k p sub-powers run as one chain blocked across links (links
+    # straddle launches when q is not a multiple of k); original-order I/O applies one
+    # Newton polynomial per power: the same arithmetic, so all four agree bitwise
     A = S.laplacian_2d(61, 47)
     x = S.uniform_vector(A.n, 6)
-    Wb = run(A, x, 5, k, p_block=4)
-    Wp = run(A, x, 5, k, p_block=4, plain=True)
-    Ws = run(A, x, 5, k, p_block=4, staged=True)
-    Wo = run(A, x, 5, k, p_block=4, permuted=False)
+    Wb = run(A, x, 5, k, p_block=q)
+    Wp = run(A, x, 5, k, p_block=q, plain=True)
+    Ws = run(A, x, 5, k, p_block=q, staged=True)
+    Wo = run(A, x, 5, k, p_block=q, permuted=False)
     assert np.array_equal(Wb, Wp) and np.array_equal(Wb, Ws) and np.array_equal(Wb, Wo)
 
 
