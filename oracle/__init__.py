@@ -42,6 +42,9 @@ sparse iterative solvers on multi-core CPUs"):
 * ``diagonal``, ``jacobi_precondition``, ``jacobi_mpk`` -- Sec. 5.1 (Jacobi
   preconditioner, k iterations from zero) in the right-preconditioned MPK,
   reading R20
+* ``spmv_lower``, ``gs2_precondition``, ``gs2_mpk`` -- Sec. 5.1 (two-stage
+  Gauss-Seidel, one outer iteration from zero, gamma inner sweeps) in the
+  right-preconditioned MPK, reading R21
 
 Parity status of each function is stated in its docstring.  The readings
 taken where the paper is silent are listed in ``mpk_oracle.READINGS``.

@@ -11,7 +11,7 @@ Parity status
 -------------
 pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_coeffs, refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          leja_order, chebyshev_scale, newton_shifts, cholqr_truncated, sstep_cycle, sstep_gmres,
-         diagonal, jacobi_precondition, jacobi_mpk,
+         diagonal, jacobi_precondition, jacobi_mpk, spmv_lower, gs2_precondition, gs2_mpk,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
          hop_min, window_ok, min_workers,
@@ -124,6 +124,13 @@ READINGS = {
            "(k = 1: P^{-1} = D^{-1}, the fused A D^{-1} of the paper; k > 1: the "
            "Neumann-series polynomial preconditioner the paper mentions). The two-stage "
            "Gauss-Seidel preconditioner is not covered.",
+    "R21": "Two-stage Gauss-Seidel preconditioner (Sec. 5.1, Alg. 4a): the listing's "
+           "superscripts are garbled and its update z^{k+1} = z^k + g_gamma is only "
+           "consistent with g_0 = D^{-1}(v - U z^k) when z^k = 0; the paper states that "
+           "one outer iteration from z^0 = 0 is the common use and that it then reduces to "
+           "g_0 = D^{-1} v and z^1 = g_gamma. That is the form taken: g_j = g_0 - D^{-1} L "
+           "g_{j-1}, j = 1..gamma, P^{-1} v = g_gamma, with L the strictly lower triangle "
+           "in the original numbering; the MPK is w_j = A P^{-1} w_{j-1}.",
     "R11": "Reduced-precision matrix storage (the paper works in FP64 only): each stored "
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
@@ -510,6 +517,46 @@ def jacobi_mpk(A, x, p, k):
     out = np.empty((p, w.size))
     for j in range(p):
         w = spmv(A, jacobi_precondition(A, w, k))
+        out[j] = w
+    return out
+
+
+def spmv_lower(A, x):
+    """(L x)_i = sum over the stored entries a_ij with j < i (the strictly lower triangle in
+    the original numbering), in stored order."""
+    n, rp, c, v = _arrays(A)
+    x = np.asarray(x, dtype=np.float64)
+    y = np.zeros(n)
+    for i in range(n):
+        s = 0.0
+        for e in range(rp[i], rp[i + 1]):
+            if c[e] < i:
+                s += v[e] * x[c[e]]
+        y[i] = s
+    return y
+
+
+def gs2_precondition(A, v, gamma):
+    """Reading R21, the two-stage Gauss-Seidel preconditioner of Sec. 5.1 (Alg. 4a) in the
+    form the paper uses it: one outer iteration from z^0 = 0, so that g_0 = D^{-1} v,
+    g_j = g_0 - D^{-1} L g_{j-1} for j = 1..gamma (inner Jacobi-Richardson sweeps for
+    (D + L) g = v), and P^{-1} v = z^1 = g_gamma."""
+    d = diagonal(A)
+    g0 = np.asarray(v, dtype=np.float64) / d
+    g = g0
+    for _ in range(gamma):
+        g = g0 - spmv_lower(A, g) / d
+    return g
+
+
+def gs2_mpk(A, x, p, gamma):
+    """Reading R21: the GS2-preconditioned MPK, w_j = A P^{-1} w_{j-1} for j = 1..p with
+    P^{-1} of gs2_precondition (gamma + 2 sub-powers per power: D^{-1}, gamma sweeps with
+    L, then A).  Returns W with W[j-1] = w_j."""
+    w = np.asarray(x, dtype=np.float64)
+    out = np.empty((p, w.size))
+    for j in range(p):
+        w = spmv(A, gs2_precondition(A, w, gamma))
         out[j] = w
     return out
 
