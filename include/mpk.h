@@ -138,7 +138,14 @@ typedef struct {
                                 operator of Sec. 5.1; every call then applies
                                 to B).  Needs a stored nonzero diagonal entry
                                 in every row (else MPK_ERR_CSR)               */
-    int32_t reserved[5];     /* must be zero                                  */
+    int32_t split_lower;     /* 1: also record, per row, which stored entries
+                                lie in the strictly lower triangle L (original
+                                numbering) and which is the diagonal, for the
+                                GS2-preconditioned MPK (mpk_gs2_apply).  Needs
+                                a stored nonzero diagonal entry in every row
+                                (else MPK_ERR_CSR) and at most 32 entries per
+                                row (else MPK_ERR_UNSUPPORTED)                */
+    int32_t reserved[4];     /* must be zero                                  */
 } mpk_options;
 
 /* Fills *opt with the defaults (all zero). */
@@ -413,6 +420,32 @@ mpk_status mpk_jacobi_apply(mpk_plan_t plan, int32_t k, const double* x, double*
 
 /* Work bytes mpk_jacobi_apply needs for k sweeps, p powers and `flags`. */
 mpk_status mpk_jacobi_work_bytes(mpk_plan_t plan, int32_t k, int32_t p, uint32_t flags, size_t* bytes);
+
+/*
+ * GS2-preconditioned matrix power kernel (Sec. 5.1, two-stage Gauss-Seidel
+ * with the right preconditioning of Sec. 5): Y[(j-1)*ldy + i] =
+ * ((A P^{-1})^j x)[i] for j = 1..p, where P^{-1} v is one outer GS2 iteration
+ * from z^0 = 0 with gamma inner Jacobi-Richardson sweeps:
+ *   g_0 = D^{-1} v, g_r = g_0 - D^{-1} L g_{r-1} (r = 1..gamma), P^{-1} v = g_gamma,
+ * L the strictly lower triangle of A in the original numbering (the form the
+ * paper uses, with its short-circuit for z^0 = 0).  Each power is gamma + 2
+ * sub-powers (D^{-1}, gamma sweeps with L, then A), and the sub-powers of all
+ * p powers run as one chain blocked across powers; each row keeps g_0 and its
+ * diagonal entry in registers, and a sweep sums the row's lower entries during
+ * the same gather as the full row.  The plan must be built with
+ * split_lower = 1.  x (device, n) is only read; Y (device, p*ldy, ldy >= n).
+ * Perm space with MPK_IO_PERMUTED (the fast path), otherwise permuted through
+ * `work`.  work: device, 256-byte aligned, mpk_gs2_work_bytes(plan, gamma, p,
+ * flags) bytes.  MPK_PLAIN / MPK_STAGED select the executor; all executors
+ * give bitwise equal results.  Errors: MPK_ERR_ARG (plan without split_lower,
+ * gamma outside 0..16, p < 1, ldy < n, null pointers, work too small or
+ * misaligned), MPK_ERR_STATE, MPK_ERR_HIP.
+ */
+mpk_status mpk_gs2_apply(mpk_plan_t plan, int32_t gamma, const double* x, double* Y, int64_t ldy, int32_t p,
+                         uint32_t flags, void* work, size_t work_bytes, void* stream);
+
+/* Work bytes mpk_gs2_apply needs for gamma, p powers and `flags`. */
+mpk_status mpk_gs2_work_bytes(mpk_plan_t plan, int32_t gamma, int32_t p, uint32_t flags, size_t* bytes);
 
 /*
  * Permutes a device vector into the plan's level order, x_perm[i] = x[perm[i]]

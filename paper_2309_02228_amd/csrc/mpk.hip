@@ -53,8 +53,11 @@ constexpr int kFlagStride = 32;
 // (c = -(-1)^k) as one sequence of sub-powers u = (B - I) u_prev; every k-th
 // sub-power closes a link with w_j = fma(c, u, w_{j-1}), which is stored both in the
 // ring (the next sub-power's input) and as output column j.
-enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2, KIND_JCHAIN = 3 };
-constexpr int kKinds = 4;
+// KIND_GS2: the GS2-preconditioned chain, gl = gamma + 2 sub-powers per power: r = 0
+// gives g_0 = D^{-1} w_{j-1}, r = 1..gamma the sweeps g_r = g_0 - D^{-1} L g_{r-1}, and
+// r = gamma + 1 closes the power with w_j = A g_gamma (also stored as output column j).
+enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2, KIND_JCHAIN = 3, KIND_GS2 = 4 };
+constexpr int kKinds = 5;
 
 // ------------------------------------------------------------------ device
 struct DevPlan {
@@ -72,6 +75,8 @@ struct DevPlan {
     uint32_t* done;
     uint32_t* tickets;  // [4 launch slots][kParts], one per 128-byte line
     int32_t* status;    // [0] code, [1] chunk, [2] power
+    const uint32_t* lmask;  // per permuted row: slots of the strictly lower triangle (split plans)
+    const int32_t* dslot;   // per permuted row: slot of the diagonal entry (split plans)
     int32_t n;
 };
 
@@ -81,9 +86,18 @@ struct Coefs {
     double sig[kMaxQ];  // Newton column scaling
     double c[kMaxQ];    // polynomial coefficient of the power
     double theta, delta;
-    int jk;             // KIND_JCHAIN: sub-powers per link
+    int jk;             // KIND_JCHAIN: sub-powers per link; KIND_GS2: sub-powers per power
     double jc;          // KIND_JCHAIN: coefficient of (B - I)^k at the end of a link
 };
+
+// GS2 sub-power r of a power from the row's full sum sA = (A g)_i, its strictly lower
+// part sL = (L g)_i, its own previous value, g_0 and the diagonal entry d.
+__device__ __forceinline__ double gs2_value(double sA, double sL, double prev, double g0, double d, int r,
+                                            int gl) {
+    if (r == 0) return prev / d;
+    if (r < gl - 1) return g0 - sL / d;
+    return sA;
+}
 
 __device__ __forceinline__ double load_coherent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -176,6 +190,30 @@ __device__ __forceinline__ double row_sum_mem(const DevPlan& P, const double* in
     return s;
 }
 
+// Both sums of a GS2 row in slot order: sA over all slots, sL over the strictly lower
+// ones (lm), and the diagonal entry (slot ds).
+template <typename VT>
+__device__ __forceinline__ void row_sums_gs2(const DevPlan& P, const double* in, int64_t off, int width,
+                                             int lane, int row, double& sA, double& sL, double& d) {
+    const VT* val = (const VT*)P.val;
+    const float sc = row_scale<VT>(P, row);
+    const uint32_t lm = row < P.n ? P.lmask[row] : 0u;
+    const int ds = row < P.n ? P.dslot[row] : -1;
+    sA = 0.0;
+    sL = 0.0;
+    d = 1.0;
+    for (int j = 0; j < width; ++j) {
+        const int64_t slot = off + (int64_t)j * kChunkRows + lane;
+        const int cj = P.col[slot];
+        if (cj < 0) continue;
+        const double v = decode<VT>(val[slot], sc);
+        const double x = in[cj];
+        sA = fma(v, x, sA);
+        if ((lm >> j) & 1u) sL = fma(v, x, sL);
+        if (j == ds) d = v;
+    }
+}
+
 // Waves take chunks c = wave, wave + W, ... (a streaming pass; the matrix is
 // not reused within a launch, so no XCD partition is needed).
 template <int KIND, bool POLY, typename VT>
@@ -187,6 +225,17 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
         const int row = c * kChunkRows + lane;
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
+        if constexpr (KIND == KIND_GS2) {
+            double sA, sL, d;
+            row_sums_gs2<VT>(a.P, a.in, off, width, lane, row, sA, sL, d);
+            if (row < a.P.n) {
+                const int r = (a.gk - 1) % a.C.jk;
+                const double y = gs2_value(sA, sL, a.in[row], a.link_in[row], d, r, a.C.jk);
+                a.out[row] = y;
+                if (r == a.C.jk - 1) a.link_out[(int64_t)((a.gk - 1) / a.C.jk) * a.link_ld + row] = y;
+            }
+            continue;
+        }
         const double s = row_sum_mem<VT>(a.P, a.in, off, width, lane, row);
         if (row < a.P.n) {
             const double prev = (KIND != KIND_MONO || POLY) ? a.in[row] : 0.0;
@@ -350,11 +399,19 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
         // polynomial accumulator and the basis copy only
         const bool need_prev = KIND != KIND_MONO || POLY || a.copy0 != nullptr;
         double prev[G], prev2[G], acc[G], link0[G];
+        uint32_t lm[G];  // KIND_GS2: strictly lower slots of the row
+        double dg[G];    // KIND_GS2: the row's diagonal entry
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const bool act = c[g] >= 0 && row[g] < a.P.n;
             prev[g] = (act && need_prev) ? a.in[row[g]] : 0.0;
-            link0[g] = (KIND == KIND_JCHAIN && act) ? a.link_in[row[g]] : 0.0;
+            link0[g] = ((KIND == KIND_JCHAIN || KIND == KIND_GS2) && act) ? a.link_in[row[g]] : 0.0;
+            lm[g] = 0u;
+            dg[g] = 1.0;
+            if (KIND == KIND_GS2 && act) {
+                lm[g] = a.P.lmask[row[g]];
+                dg[g] = decode<VT>(val[off[g] + (int64_t)a.P.dslot[row[g]] * kChunkRows + lane], rsc[g]);
+            }
             prev2[g] = (KIND == KIND_CHEB && act && a.prev2) ? a.prev2[row[g]] : 0.0;
             if (a.copy0 && act) a.copy0[row[g]] = prev[g];
             acc[g] = 0.0;
@@ -381,10 +438,11 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                 }
                 asm volatile("" ::: "memory");
             }
-            double s[G];
+            double s[G], sl[G];
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 s[g] = 0.0;
+                sl[g] = 0.0;
                 double xv[REG];
 #pragma unroll
                 for (int j = 0; j < REG; ++j)
@@ -398,6 +456,7 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                         // instead of letting the compiler hoist a widened copy
                         if constexpr (sizeof(VT) < 8) asm volatile("" : "+v"(r));
                         s[g] = fma(decode<VT>(r, rsc[g]), xv[j], s[g]);
+                        if (KIND == KIND_GS2 && ((lm[g] >> j) & 1u)) sl[g] = fma(decode<VT>(r, rsc[g]), xv[j], sl[g]);
                     }
             }
 #pragma unroll
@@ -405,15 +464,27 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                 for (int j = REG; j < width[g]; ++j) {  // slots beyond the register cache
                     const int64_t slot = off[g] + (int64_t)j * kChunkRows + lane;
                     const int cj = a.P.col[slot];
-                    if (cj >= 0)
-                        s[g] = fma(decode<VT>(val[slot], rsc[g]),
-                                   kl == 0 || a.plain_gather ? src[cj] : load_coherent(src + cj), s[g]);
+                    if (cj >= 0) {
+                        const double vj = decode<VT>(val[slot], rsc[g]);
+                        const double xj = kl == 0 || a.plain_gather ? src[cj] : load_coherent(src + cj);
+                        s[g] = fma(vj, xj, s[g]);
+                        if (KIND == KIND_GS2 && j < 32 && ((lm[g] >> j) & 1u)) sl[g] = fma(vj, xj, sl[g]);
+                    }
                 }
             double* dst = dest(a, kl);
             const bool last = kl + 1 == a.q;
 #pragma unroll
             for (int g = 0; g < G; ++g) {
-                const double y = finish<KIND>(s[g], prev[g], prev2[g], link0[g], a.base + kl + 1, kl, a.C);
+                double y;
+                if constexpr (KIND == KIND_GS2) {
+                    const int r = (a.base + kl) % a.C.jk;
+                    y = gs2_value(s[g], sl[g], prev[g], link0[g], dg[g], r, a.C.jk);
+                    if (r == 0) link0[g] = y;  // g_0 of this power
+                    if (r == a.C.jk - 1 && c[g] >= 0 && row[g] < a.P.n)
+                        a.link_out[(int64_t)((a.base + kl) / a.C.jk) * a.link_ld + row[g]] = y;
+                } else {
+                    y = finish<KIND>(s[g], prev[g], prev2[g], link0[g], a.base + kl + 1, kl, a.C);
+                }
                 if (c[g] >= 0 && row[g] < a.P.n) {
                     if (!last) store_coherent(dst + row[g], y);
                     else dst[row[g]] = y;  // nobody reads the last power in this launch
@@ -484,6 +555,17 @@ __global__ __launch_bounds__(kBlockThreads) void stage_kernel(StageArgs a) {
         const int row = c * kChunkRows + lane;
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
+        if constexpr (KIND == KIND_GS2) {
+            double sA, sL, d;
+            row_sums_gs2<VT>(a.P, T.in, off, width, lane, row, sA, sL, d);
+            if (row >= T.r0 && row < T.r1) {
+                const int r = (T.gk - 1) % a.C.jk;
+                const double y = gs2_value(sA, sL, T.in[row], T.link_in[row], d, r, a.C.jk);
+                T.out[row] = y;
+                if (r == a.C.jk - 1) a.link_out[(int64_t)((T.gk - 1) / a.C.jk) * a.link_ld + row] = y;
+            }
+            continue;
+        }
         const double s = row_sum_mem<VT>(a.P, T.in, off, width, lane, row);
         if (row >= T.r0 && row < T.r1) {
             const double prev = (KIND != KIND_MONO || POLY) ? T.in[row] : 0.0;
@@ -613,7 +695,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, dep_ptr, dep_idx, done, tickets,
-        status, total;
+        status, lmask, dslot, total;
 };
 
 Layout make_layout(const mpk::HostPlan& H) {
@@ -640,6 +722,8 @@ Layout make_layout(const mpk::HostPlan& H) {
     L.done = take(std::max<size_t>(1, H.nchunks) * 4 * kFlagStride);
     L.tickets = take(4 * kParts * 4 * kFlagStride);
     L.status = take(16);
+    L.lmask = take(H.lmask.size() * 4);
+    L.dslot = take(H.dslot.size() * 4);
     L.total = o;
     return L;
 }
@@ -687,6 +771,7 @@ BlockFn block_fn(int reg) {
 template <int G, typename VT>
 BlockFn pick_block_g(int reg, int kind, bool poly) {
     if (kind == KIND_JCHAIN) return block_fn<G, KIND_JCHAIN, false, VT>(reg);  // never polynomial
+    if (kind == KIND_GS2) return block_fn<G, KIND_GS2, false, VT>(reg);
     if (kind == KIND_MONO)
         return poly ? block_fn<G, KIND_MONO, true, VT>(reg) : block_fn<G, KIND_MONO, false, VT>(reg);
     if (kind == KIND_NEWTON)
@@ -711,6 +796,7 @@ BlockFn pick_block(const mpk::HostPlan& H, int kind, bool poly) {
 template <typename VT>
 SpmvFn pick_spmv_vt(int kind, bool poly) {
     if (kind == KIND_JCHAIN) return spmv_kernel<KIND_JCHAIN, false, VT>;
+    if (kind == KIND_GS2) return spmv_kernel<KIND_GS2, false, VT>;
     if (kind == KIND_MONO) return poly ? spmv_kernel<KIND_MONO, true, VT> : spmv_kernel<KIND_MONO, false, VT>;
     if (kind == KIND_NEWTON) return poly ? spmv_kernel<KIND_NEWTON, true, VT> : spmv_kernel<KIND_NEWTON, false, VT>;
     return poly ? spmv_kernel<KIND_CHEB, true, VT> : spmv_kernel<KIND_CHEB, false, VT>;
@@ -720,6 +806,7 @@ using StageFn = void (*)(StageArgs);
 template <typename VT>
 StageFn pick_stage_vt(int kind, bool poly) {
     if (kind == KIND_JCHAIN) return stage_kernel<KIND_JCHAIN, false, VT>;
+    if (kind == KIND_GS2) return stage_kernel<KIND_GS2, false, VT>;
     if (kind == KIND_MONO) return poly ? stage_kernel<KIND_MONO, true, VT> : stage_kernel<KIND_MONO, false, VT>;
     if (kind == KIND_NEWTON)
         return poly ? stage_kernel<KIND_NEWTON, true, VT> : stage_kernel<KIND_NEWTON, false, VT>;
@@ -829,9 +916,12 @@ struct PowerJob {
 
 double* job_dest(const PowerJob& j, int k) { return j.out0 + (int64_t)((k - 1) % j.mod) * j.ld; }
 const double* job_vec(const PowerJob& j, int k) { return k == 0 ? j.x : job_dest(j, k); }
-// KIND_JCHAIN: the chain's value at the start of the link that holds sub-power k
+// KIND_JCHAIN: the chain's value at the start of the link that holds sub-power k.
+// KIND_GS2: g_0 of the power that holds sub-power k (the ring slot of the power's
+// first sub-power; any valid vector when k is itself that first sub-power).
 const double* link_start(const PowerJob& j, int k) {
     const int t = (k - 1) / j.jk * j.jk;
+    if (j.kind == KIND_GS2) return t + 1 < k ? job_dest(j, t + 1) : job_vec(j, t);
     return t == 0 ? j.x : j.link_out + (int64_t)(t / j.jk - 1) * j.link_ld;
 }
 void set_chain(const PowerJob& j, Coefs& C) {
@@ -871,7 +961,7 @@ mpk_status run_staged(mpk_plan_t p, hipStream_t st, const PowerJob& j) {
                 StageTaskDev& d = a.t[a.ntasks++];
                 d.in = job_vec(j, gk - 1);
                 d.prev2 = (j.kind == KIND_CHEB && gk >= 2) ? job_vec(j, gk - 2) : nullptr;
-                d.link_in = j.kind == KIND_JCHAIN ? link_start(j, gk) : nullptr;
+                d.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, gk) : nullptr;
                 d.out = job_dest(j, gk);
                 d.r0 = T.row_begin;
                 d.r1 = T.row_end;
@@ -909,7 +999,7 @@ mpk_status plain_power(mpk_plan_t p, hipStream_t st, const PowerJob& j, int k) {
     a.C.theta = j.theta;
     a.C.delta = j.delta;
     set_chain(j, a.C);
-    a.link_in = j.kind == KIND_JCHAIN ? link_start(j, k) : nullptr;
+    a.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, k) : nullptr;
     a.link_out = j.link_out;
     a.link_ld = j.link_ld;
     if (k == 1 && j.copy0) {
@@ -972,7 +1062,7 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
         a.C.theta = j.theta;
         a.C.delta = j.delta;
         set_chain(j, a.C);
-        a.link_in = j.kind == KIND_JCHAIN ? link_start(j, base + 1) : nullptr;
+        a.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, base + 1) : nullptr;
         a.link_out = j.link_out;
         a.link_ld = j.link_ld;
         mpk_status s = launch_block(p, st, j.kind, j.poly, a);
@@ -1020,8 +1110,9 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
     if (n > 0 && rowptr[n] > 0 && (!col || !val)) return fail(MPK_ERR_ARG, "col or val is null");
     mpk_options o{};
     if (opt) o = *opt;
-    for (int i = 0; i < 5; ++i)
+    for (int i = 0; i < 4; ++i)
         if (o.reserved[i] != 0) return fail(MPK_ERR_ARG, "mpk_options.reserved must be zero");
+    if (o.split_lower != 0 && o.split_lower != 1) return fail(MPK_ERR_ARG, "split_lower must be 0 or 1");
     if (o.column_scaling != MPK_SCALE_NONE && o.column_scaling != MPK_SCALE_JACOBI)
         return fail(MPK_ERR_ARG, "column_scaling must be MPK_SCALE_NONE (0) or MPK_SCALE_JACOBI (1)");
     if (o.cache_mib < 0) return fail(MPK_ERR_ARG, "cache_mib must be >= 0");
@@ -1042,6 +1133,16 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
         return fail(MPK_ERR_ARG, "chunks_per_worker must be 0, 1, 2 or 4");
     std::string why = mpk::validate_csr(n, rowptr, col);
     if (!why.empty()) return fail(MPK_ERR_CSR, "%s", why.c_str());
+    if (o.split_lower) {  // GS2 needs every diagonal entry and at most 32 entries per row
+        for (int32_t i = 0; i < n; ++i) {
+            if (rowptr[i + 1] - rowptr[i] > 32)
+                return fail(MPK_ERR_UNSUPPORTED, "split_lower supports rows of at most 32 entries (row %d has %d)", i,
+                            rowptr[i + 1] - rowptr[i]);
+            bool diag = false;
+            for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) diag = diag || (col[e] == i && val[e] != 0.0);
+            if (!diag) return fail(MPK_ERR_CSR, "row %d has no nonzero diagonal entry (needed by split_lower)", i);
+        }
+    }
     // B = A D^{-1}: every value divided by its column's diagonal entry, in FP64
     std::vector<double> scaled;
     if (o.column_scaling == MPK_SCALE_JACOBI) {
@@ -1076,6 +1177,7 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
         p->H.cache_bytes = (int64_t)(o.cache_mib ? o.cache_mib : 256) << 20;
         p->H.min_group_rows = o.min_group_rows;
         p->column_scaling = o.column_scaling;
+        p->H.split_lower = o.split_lower;
         mpk::build_plan(p->H, n, rowptr, col, val);
         p->L = make_layout(p->H);
     } catch (const std::bad_alloc&) {
@@ -1197,6 +1299,8 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     HIP_TRY(put(L.unit_rec, H.unit_rec.data(), H.unit_rec.size() * 4));
     HIP_TRY(put(L.dep_ptr, H.dep_ptr.data(), H.dep_ptr.size() * 4));
     HIP_TRY(put(L.dep_idx, H.dep_idx.data(), H.dep_idx.size() * 4));
+    HIP_TRY(put(L.lmask, H.lmask.data(), H.lmask.size() * 4));
+    HIP_TRY(put(L.dslot, H.dslot.data(), H.dslot.size() * 4));
     const int64_t nd = (int64_t)std::max<int32_t>(1, H.nchunks) * kFlagStride;
     fill_u32_kernel<<<grid_1d(nd), 256, 0, st>>>((uint32_t*)(d + L.done), nd, 0u);
     HIP_TRY(hipGetLastError());
@@ -1220,6 +1324,8 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     D.dep_ptr = (const int32_t*)(d + L.dep_ptr);
     D.dep_idx = (const int32_t*)(d + L.dep_idx);
     D.done = (uint32_t*)(d + L.done);
+    D.lmask = (const uint32_t*)(d + L.lmask);
+    D.dslot = (const int32_t*)(d + L.dslot);
     D.tickets = (uint32_t*)(d + L.tickets);
     D.status = (int32_t*)(d + L.status);
     D.n = H.n;
@@ -1599,6 +1705,66 @@ MPK_API mpk_status mpk_jacobi_apply(mpk_plan_t p, int32_t k, const double* x, do
         if (s != MPK_OK) return s;
     }
     return MPK_OK;
+}
+
+MPK_API mpk_status mpk_gs2_work_bytes(mpk_plan_t p, int32_t gamma, int32_t pw, uint32_t flags, size_t* bytes) {
+    if (!p || !bytes) return fail(MPK_ERR_ARG, "null argument");
+    if (gamma < 0 || gamma > 16) return fail(MPK_ERR_ARG, "gamma must be in 0..16 (got %d)", gamma);
+    if (pw < 1) return fail(MPK_ERR_ARG, "p must be >= 1 (got %d)", pw);
+    const size_t v = (size_t)(p->H.n + 31) / 32 * 32 * 8;  // one vector, 256-byte multiple
+    // ring: every sub-power a launch writes, plus the g_0 and input it reads
+    const size_t ring = (size_t)(p->H.p_block + gamma + 2);
+    *bytes = v * (ring + ((flags & MPK_IO_PERMUTED) ? 0 : 1 + (size_t)pw));
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_gs2_apply(mpk_plan_t p, int32_t gamma, const double* x, double* Y, int64_t ldy, int32_t pw,
+                                 uint32_t flags, void* work, size_t work_bytes, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (!p->H.split_lower) return fail(MPK_ERR_ARG, "the plan must be built with split_lower = 1");
+    if (gamma < 0 || gamma > 16) return fail(MPK_ERR_ARG, "gamma must be in 0..16 (got %d)", gamma);
+    if (pw < 1) return fail(MPK_ERR_ARG, "p must be >= 1 (got %d)", pw);
+    if (ldy < p->H.n) return fail(MPK_ERR_ARG, "ldy must be >= n");
+    if (p->H.n > 0 && (!x || !Y)) return fail(MPK_ERR_ARG, "x or Y is null");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    size_t need = 0;
+    mpk_gs2_work_bytes(p, gamma, pw, flags, &need);
+    if (!work || work_bytes < need) return fail(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    if (((uintptr_t)work) & 255) return fail(MPK_ERR_ARG, "work must be 256-byte aligned");
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    const int32_t n = p->H.n;
+    if (n == 0) return MPK_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const bool permuted = flags & MPK_IO_PERMUTED;
+    const int64_t ld = (n + 31) / 32 * 32;
+    double* w = (double*)work;
+    const int ring = p->H.p_block + gamma + 2;
+    const double* xin = x;
+    double* yout = Y;
+    int64_t yld = ldy;
+    if (!permuted) {  // level-order copies after the ring
+        double* xp = w + (int64_t)ring * ld;
+        s = permute_vecs(p, st, x, 0, xp, 0, 1, 0);
+        if (s != MPK_OK) return s;
+        xin = xp;
+        yout = xp + ld;
+        yld = ld;
+    }
+    PowerJob j;
+    j.kind = KIND_GS2;
+    j.p = pw * (gamma + 2);
+    j.x = xin;
+    j.out0 = w;
+    j.ld = ld;
+    j.mod = ring;
+    j.jk = gamma + 2;
+    j.link_out = yout;
+    j.link_ld = yld;
+    s = run_powers(p, st, j, flags & MPK_PLAIN, flags & MPK_STAGED);
+    if (s != MPK_OK) return s;
+    if (!permuted) s = permute_vecs(p, st, yout, ld, Y, ldy, pw, 1);
+    return s;
 }
 
 MPK_API mpk_status mpk_permute(mpk_plan_t p, const double* in, double* out, int32_t direction, void* stream) {

@@ -202,6 +202,10 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
     const int64_t slots = P.chunk_off[P.nchunks];
     P.sell_val.assign(slots, 0.0);
     P.sell_col.assign(slots, -1);
+    if (P.split_lower) {
+        P.lmask.assign((size_t)P.nchunks * kChunkRows, 0u);
+        P.dslot.assign((size_t)P.nchunks * kChunkRows, 0);
+    }
     {
         std::vector<std::pair<int32_t, double>> row;
         for (int32_t i = 0; i < n; ++i) {
@@ -218,6 +222,10 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
                 int64_t s = P.chunk_off[c] + (int64_t)j * kChunkRows + lane;
                 P.sell_col[s] = row[j].first;
                 P.sell_val[s] = row[j].second;
+                if (P.split_lower) {
+                    if (P.perm[row[j].first] < o) P.lmask[i] |= 1u << j;
+                    if (row[j].first == i) P.dslot[i] = (int32_t)j;
+                }
             }
         }
     }

@@ -23,6 +23,7 @@ struct HostPlan {
     int32_t max_reg = 0;     // cap on register slots (0 = automatic)
     int64_t cache_bytes = 256ll << 20;  // C of the level groups (R14)
     int32_t min_group_rows = 0;         // row floor of a level group (R14)
+    int32_t split_lower = 0;            // also record the strictly lower slots of each row
 
     // Sec. 3 level structure
     int32_t nlevels = 0;
@@ -39,6 +40,11 @@ struct HostPlan {
     std::vector<int32_t> sell_col;   // slots, -1 = padding
     int32_t max_width = 0;
     int32_t reg_slots = 8;  // slots per row the blocked kernel keeps in registers
+    // with split_lower (rows of at most 32 slots): per permuted row, bit s of lmask is
+    // set when slot s holds a column that precedes the row in the original numbering
+    // (the strictly lower triangle L of A), and dslot is the slot of the diagonal entry
+    std::vector<uint32_t> lmask;        // nchunks * 64
+    std::vector<int32_t> dslot;         // nchunks * 64
 
     // partition and dependencies
     std::vector<int32_t> owner;          // nchunks

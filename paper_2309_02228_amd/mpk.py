@@ -33,7 +33,8 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_permute", "mpk_check_device", "mpk_plan_info", "mpk_destroy",
            "mpk_server_create", "mpk_server_submit_apply", "mpk_server_submit_solve",
            "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes",
-           "mpk_server_submit_gmres", "mpk_jacobi_apply", "mpk_jacobi_work_bytes"]
+           "mpk_server_submit_gmres", "mpk_jacobi_apply", "mpk_jacobi_work_bytes",
+           "mpk_gs2_apply", "mpk_gs2_work_bytes"]
 
 
 class MPKError(RuntimeError):
@@ -48,7 +49,8 @@ class Options(ctypes.Structure):
                 ("watchdog_polls", ctypes.c_int32), ("chunks_per_worker", ctypes.c_int32),
                 ("value_type", ctypes.c_int32), ("max_reg_slots", ctypes.c_int32),
                 ("cache_mib", ctypes.c_int32), ("min_group_rows", ctypes.c_int32),
-                ("column_scaling", ctypes.c_int32), ("reserved", ctypes.c_int32 * 5)]
+                ("column_scaling", ctypes.c_int32), ("split_lower", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 4)]
 
 
 def _load():
@@ -99,6 +101,8 @@ def _load():
         "mpk_sstep_gmres_work_bytes": (I32, [P, I32, I32, I32, U32, pSZ]),
         "mpk_jacobi_apply": (I32, [P, I32, P, P, I64, I32, U32, P, SZ, P]),
         "mpk_jacobi_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
+        "mpk_gs2_apply": (I32, [P, I32, P, P, I64, I32, U32, P, SZ, P]),
+        "mpk_gs2_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_server_submit_gmres": (I32, [P, P, P, P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, I32, U32, pI64]),
     }
@@ -148,7 +152,7 @@ class Plan:
 
     def __init__(self, n, rowptr, col, val, root=None, p_block=0, workers_per_xcd=0,
                  watchdog_polls=0, chunks_per_worker=0, values="f64", max_reg_slots=0, cache_mib=0,
-                 min_group_rows=0, column_scaling=None):
+                 min_group_rows=0, column_scaling=None, split_lower=False):
         self._h = None
         self.n = int(n)
         rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
@@ -171,6 +175,7 @@ class Plan:
         if column_scaling not in (None, "jacobi"):
             raise ValueError("column_scaling must be None or 'jacobi' (the plan then holds A D^-1)")
         opt.column_scaling = 1 if column_scaling == "jacobi" else 0
+        opt.split_lower = 1 if split_lower else 0
         self.column_scaling = column_scaling
         self.values = values
         h = ctypes.c_void_p()
@@ -332,6 +337,20 @@ class Plan:
         w = torch.empty(nb.value // 8 + 1, dtype=torch.float64, device=x.device) if nb.value else None
         _check(_lib.mpk_jacobi_apply(self._h, int(k), _dptr(x), _dptr(Y), Y.stride(0), int(p), flags,
                                      _dptr(w) if w is not None else None, nb.value, _stream(stream)))
+        return Y
+
+    def gs2_apply(self, x, p, gamma, Y=None, permuted=True, plain=False, staged=False, stream=None):
+        """W[j-1] = (A P^{-1})^j x, j = 1..p, with P^{-1} one GS2 iteration from zero with
+        ``gamma`` inner sweeps; the plan must be built with split_lower=True."""
+        import torch
+        if Y is None:
+            Y = torch.empty((p, self.n), dtype=torch.float64, device=x.device)
+        flags = self._flags(permuted, plain, staged)
+        nb = ctypes.c_size_t()
+        _check(_lib.mpk_gs2_work_bytes(self._h, int(gamma), int(p), flags, ctypes.byref(nb)))
+        w = torch.empty(nb.value // 8 + 64, dtype=torch.float64, device=x.device)
+        _check(_lib.mpk_gs2_apply(self._h, int(gamma), _dptr(x), _dptr(Y), Y.stride(0), int(p), flags, _dptr(w),
+                                  w.numel() * 8, _stream(stream)))
         return Y
 
     def gmres_work_bytes(self, s, m, degree, permuted=True):

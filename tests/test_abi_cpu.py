@@ -329,3 +329,32 @@ def test_jacobi_scaling_and_apply_argument_errors_without_gpu():
     rp, c, v = (np.ascontiguousarray(a) for a in (A.rowptr, A.col, A.val))
     assert lib.mpk_build_levels(A.n, M._ptr(rp), M._ptr(c), M._ptr(v), ctypes.byref(opt), ctypes.byref(h),
                                 ctypes.byref(nbytes)) == -1
+
+
+def test_gs2_split_plan_and_apply_argument_errors_without_gpu():
+    lib = M.lib()
+    with pytest.raises(M.MPKError, match="MPK_ERR_CSR"):
+        M.Plan.from_csr(S.cyclic_shift(6), split_lower=True)          # no diagonal
+    wide = S.from_dense(np.ones((40, 40)))                             # 40 entries per row
+    with pytest.raises(M.MPKError, match="MPK_ERR_UNSUPPORTED"):
+        M.Plan.from_csr(wide, split_lower=True)
+    A = S.laplacian_2d(8)
+    plain = M.Plan.from_csr(A)
+    split = M.Plan.from_csr(A, split_lower=True)
+    assert np.array_equal(plain.levels()["perm"], split.levels()["perm"])
+    nb = ctypes.c_size_t()
+    assert lib.mpk_gs2_work_bytes(split._h, 2, 4, 1, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert lib.mpk_gs2_work_bytes(split._h, -1, 4, 1, ctypes.byref(nb)) == -1
+    assert lib.mpk_gs2_work_bytes(split._h, 17, 4, 1, ctypes.byref(nb)) == -1
+    assert lib.mpk_gs2_work_bytes(split._h, 2, 0, 1, ctypes.byref(nb)) == -1
+    need = nb.value
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.mpk_gs2_apply(plain._h, 1, fake, fake, 64, 2, 1, fake, need, None) == -1   # not split
+    assert lib.mpk_gs2_apply(split._h, 17, fake, fake, 64, 2, 1, fake, need, None) == -1  # gamma
+    assert lib.mpk_gs2_apply(split._h, 1, fake, fake, 63, 2, 1, fake, need, None) == -1   # ldy < n
+    assert lib.mpk_gs2_apply(split._h, 1, None, fake, 64, 2, 1, fake, need, None) == -1   # null x
+    assert lib.mpk_gs2_apply(split._h, 1, fake, fake, 64, 2, 64, fake, need, None) == -1  # flag bit
+    assert lib.mpk_gs2_apply(split._h, 2, fake, fake, 64, 4, 1, fake, need - 8, None) == -1  # work
+    assert lib.mpk_gs2_apply(split._h, 2, fake, fake, 64, 4, 1, ctypes.c_void_p((1 << 20) + 8), need,
+                             None) == -1                                                  # misaligned
+    assert lib.mpk_gs2_apply(split._h, 2, fake, fake, 64, 4, 1, fake, need, None) == -6    # not uploaded
