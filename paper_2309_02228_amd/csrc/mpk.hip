@@ -226,10 +226,16 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
         if constexpr (KIND == KIND_GS2) {
-            double sA, sL, d;
-            row_sums_gs2<VT>(a.P, a.in, off, width, lane, row, sA, sL, d);
+            const int r = (a.gk - 1) % a.C.jk;
+            double sA = 0.0, sL = 0.0, d = 1.0;
+            if (r == 0) {  // g_0 = D^{-1} w: row-local, only the diagonal entry is read
+                if (row < a.P.n)
+                    d = decode<VT>(((const VT*)a.P.val)[off + (int64_t)a.P.dslot[row] * kChunkRows + lane],
+                                   row_scale<VT>(a.P, row));
+            } else {
+                row_sums_gs2<VT>(a.P, a.in, off, width, lane, row, sA, sL, d);
+            }
             if (row < a.P.n) {
-                const int r = (a.gk - 1) % a.C.jk;
                 const double y = gs2_value(sA, sL, a.in[row], a.link_in[row], d, r, a.C.jk);
                 a.out[row] = y;
                 if (r == a.C.jk - 1) a.link_out[(int64_t)((a.gk - 1) / a.C.jk) * a.link_ld + row] = y;
@@ -419,7 +425,10 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
         }
         for (int kl = 0; kl < a.q; ++kl) {
             const double* src = kl == 0 ? a.in : dest(a, kl - 1);
-            if (kl > 0) {
+            // the first sub-power of a GS2 power (g_0 = D^{-1} w) is row-local: no
+            // dependency wait and no gather
+            const bool local = KIND == KIND_GS2 && (a.base + kl) % a.C.jk == 0;
+            if (kl > 0 && !local) {
                 const uint32_t target = a.epoch * 16u + (uint32_t)kl;
                 bool ok[G];
 #pragma unroll
@@ -443,6 +452,7 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
             for (int g = 0; g < G; ++g) {
                 s[g] = 0.0;
                 sl[g] = 0.0;
+                if (local) continue;
                 double xv[REG];
 #pragma unroll
                 for (int j = 0; j < REG; ++j)
@@ -461,7 +471,7 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
             }
 #pragma unroll
             for (int g = 0; g < G; ++g)
-                for (int j = REG; j < width[g]; ++j) {  // slots beyond the register cache
+                for (int j = REG; j < (local ? 0 : width[g]); ++j) {  // slots beyond the register cache
                     const int64_t slot = off[g] + (int64_t)j * kChunkRows + lane;
                     const int cj = a.P.col[slot];
                     if (cj >= 0) {
@@ -556,10 +566,16 @@ __global__ __launch_bounds__(kBlockThreads) void stage_kernel(StageArgs a) {
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
         if constexpr (KIND == KIND_GS2) {
-            double sA, sL, d;
-            row_sums_gs2<VT>(a.P, T.in, off, width, lane, row, sA, sL, d);
+            const int r = (T.gk - 1) % a.C.jk;
+            double sA = 0.0, sL = 0.0, d = 1.0;
+            if (r == 0) {  // g_0 = D^{-1} w: row-local, only the diagonal entry is read
+                if (row < a.P.n)
+                    d = decode<VT>(((const VT*)a.P.val)[off + (int64_t)a.P.dslot[row] * kChunkRows + lane],
+                                   row_scale<VT>(a.P, row));
+            } else {
+                row_sums_gs2<VT>(a.P, T.in, off, width, lane, row, sA, sL, d);
+            }
             if (row >= T.r0 && row < T.r1) {
-                const int r = (T.gk - 1) % a.C.jk;
                 const double y = gs2_value(sA, sL, T.in[row], T.link_in[row], d, r, a.C.jk);
                 T.out[row] = y;
                 if (r == a.C.jk - 1) a.link_out[(int64_t)((T.gk - 1) / a.C.jk) * a.link_ld + row] = y;
