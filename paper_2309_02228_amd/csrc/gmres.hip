@@ -595,6 +595,9 @@ MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int3
             st = mpk_permute(hi, xp, x, 1, stream);
             if (st != MPK_OK) return st;
         }
+        // the coefficient staging vectors of the last copies are freed on return
+        st = S.hip(hipStreamSynchronize(S.st), "synchronize");
+        if (st != MPK_OK) return st;
         if (iters_out) *iters_out = iters;
         if (cycles_out) *cycles_out = cyc;
         if (relres_out) *relres_out = rel;
