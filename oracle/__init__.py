@@ -45,6 +45,9 @@ sparse iterative solvers on multi-core CPUs"):
 * ``spmv_lower``, ``gs2_precondition``, ``gs2_mpk`` -- Sec. 5.1 (two-stage
   Gauss-Seidel, one outer iteration from zero, gamma inner sweeps) in the
   right-preconditioned MPK, reading R21
+* ``interval_shifts``, ``sstep_gmres_precond`` -- s-step GMRES without a
+  preconditioner or with the diagonal (Jacobi) one, a blocked Newton MPK per
+  block of s vectors, reading R22
 
 Parity status of each function is stated in its docstring.  The readings
 taken where the paper is silent are listed in ``mpk_oracle.READINGS``.

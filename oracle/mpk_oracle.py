@@ -12,6 +12,7 @@ Parity status
 pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_coeffs, refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          leja_order, chebyshev_scale, newton_shifts, cholqr_truncated, sstep_cycle, sstep_gmres,
          diagonal, jacobi_precondition, jacobi_mpk, spmv_lower, gs2_precondition, gs2_mpk,
+         interval_shifts, sstep_gmres_precond,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
          hop_min, window_ok, min_workers,
@@ -131,6 +132,12 @@ READINGS = {
            "g_0 = D^{-1} v and z^1 = g_gamma. That is the form taken: g_j = g_0 - D^{-1} L "
            "g_{j-1}, j = 1..gamma, P^{-1} v = g_gamma, with L the strictly lower triangle "
            "in the original numbering; the MPK is w_j = A P^{-1} w_{j-1}.",
+    "R22": "s-step GMRES without a preconditioner (M = A) or with the diagonal Jacobi "
+           "preconditioner from the right (M = A D^{-1}, x = x0 + D^{-1} Q y; Sec. 4 and 5.1): "
+           "each block of s basis vectors is one Newton MPK of s powers (Alg. 3c's "
+           "back-to-back SpMVs replaced by an MPK). The shifts are the s Chebyshev points of "
+           "a caller-given interval [lmin, lmax] holding M's spectrum, in Leja order, each "
+           "column scaled by (lmax - lmin)/4; the paper takes Ritz values instead.",
     "R11": "Reduced-precision matrix storage (the paper works in FP64 only): each stored "
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
@@ -444,6 +451,50 @@ def sstep_cycle(apply_M, q0, m, s, lambdas, sigmas, beta, target):
         rho = float(np.linalg.norm(e0 - H @ y)) if c > 0 else beta
         if dep or c >= m or rho <= target:
             return Q[:max(c, 1)], H, y, rho
+
+
+def interval_shifts(s, lo, hi):
+    """Reading R22: Newton shifts for an operator whose spectrum lies in [lo, hi]: the s
+    Chebyshev points of the interval in Leja order, every column scaled by a quarter of
+    the interval's width (half its half-width, as in R18)."""
+    c, h = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    i = np.arange(s)
+    return leja_order(c + h * np.cos(np.pi * (2 * i + 1) / (2 * s))), np.full(s, 0.5 * h)
+
+
+def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, values=None):
+    """Reading R22: s-step GMRES (Alg. 3a/3c) without a preconditioner (M = A, x = x0 + Q y)
+    or with the diagonal (one-sweep Jacobi) preconditioner from the right (M = A D^{-1},
+    x = x0 + D^{-1} Q y, Sec. 5.1); [lmin, lmax] holds the spectrum of M, the shifts are
+    those of interval_shifts, and the cycle is sstep_cycle.  With ``values`` the basis uses
+    the rounded matrix (M = round(A) or round(A D^{-1})).  Returns (x, history, iters)."""
+    if precond not in ("none", "jacobi"):
+        raise ValueError("precond must be 'none' or 'jacobi'")
+    d = diagonal(A) if precond == "jacobi" else None
+    if precond == "jacobi":
+        n, rp, c, v = _arrays(A)
+        Mmat = type(A)(n, rp, c, v / d[c]) if hasattr(type(A), "_fields") else (n, rp, c, v / d[c])
+    else:
+        Mmat = A
+    Mlo = Mmat if values is None else round_values(Mmat, values)
+    lambdas, sigmas = interval_shifts(s, lmin, lmax)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64)
+    nb = float(np.linalg.norm(b))
+    hist, iters = [], 0
+    for cyc in range(max_cycles + 1):
+        r = b - spmv(A, x)
+        beta = float(np.linalg.norm(r))
+        hist.append(beta / nb if nb > 0 else beta)
+        if hist[-1] <= tol or cyc == max_cycles or beta == 0.0:
+            break
+        Q, H, y, rho = sstep_cycle(lambda w: spmv(Mlo, w), r / beta, m, s, lambdas, sigmas, beta, tol * nb)
+        iters += H.shape[1]
+        z = np.zeros_like(x)
+        for j in range(y.size):
+            z = z + y[j] * Q[j]
+        x = x + (z / d if d is not None else z)
+    return x, hist, iters
 
 
 def sstep_gmres(A, b, x0, s, m, d, lmin, lmax, tol, max_cycles, values=None):

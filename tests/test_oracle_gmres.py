@@ -266,3 +266,53 @@ def test_max_cycles_zero_returns_the_initial_guess():
     x0 = S.uniform_vector(36, 2)
     x, hist, iters = O.sstep_gmres(A, b, x0, 4, 8, 4, *lap_bounds((6, 6)), 1e-12, 0)
     assert np.array_equal(x, x0) and iters == 0 and len(hist) == 1
+
+
+# ------------------------------------------- without / with the Jacobi preconditioner (R22)
+def test_interval_shifts_polynomial_bounded():
+    # the shift polynomial over [lo, hi] is 2 T_s((mu - c)/h) with the column scaling h/2
+    lo, hi = 0.3, 7.9
+    c, h = 0.5 * (hi + lo), 0.5 * (hi - lo)
+    for s in (1, 3, 8):
+        lam, sig = O.interval_shifts(s, lo, hi)
+        mu = np.linspace(lo, hi, 33)
+        prod = np.ones_like(mu)
+        for k in range(s):
+            prod *= (mu - lam[k]) / sig[k]
+        np.testing.assert_allclose(prod, 2.0 * cheb_T(s, (mu - c) / h), atol=1e-9)
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+@pytest.mark.parametrize("s,m", [(1, 10), (3, 12), (4, 12), (5, 10)])
+def test_preconditioned_cycle_equals_textbook_gmres(precond, s, m):
+    # one cycle equals textbook GMRES (Alg. 3b) on the dense operator M = A or A D^{-1},
+    # mapped back by x = Q y or D^{-1} Q y
+    # catches: a missing D^{-1} in the final map, the operator without the column scaling
+    A = S.random_pattern(60, 5, 13, symmetric=False)
+    Ad = dense(A)
+    Ad[np.arange(60), np.arange(60)] = 2.0 + np.abs(Ad).sum(axis=1) * np.linspace(1, 3, 60)
+    A = S.from_dense(Ad)
+    dg = np.diag(Ad)
+    M = Ad / dg[None, :] if precond == "jacobi" else Ad
+    b = S.uniform_vector(60, 4)
+    ev = np.linalg.eigvals(M)
+    lo, hi = float(ev.real.min()) * 0.9, float(ev.real.max()) * 1.1
+    x1, hist, iters = O.sstep_gmres_precond(A, b, np.zeros(60), s, m, precond, lo, hi, 0.0, 1)
+    u = textbook_gmres_cycle(M, b, m)
+    x_ref = u / dg if precond == "jacobi" else u
+    assert iters == m
+    np.testing.assert_allclose(x1, x_ref, rtol=0, atol=1e-9 * np.abs(x_ref).max())
+
+
+@pytest.mark.parametrize("values", [None, np.float32])
+def test_jacobi_gmres_solves_knn_laplacian(values):
+    # converged solution against SciPy's direct solve; Jacobi bounds: B = A D^{-1} is similar
+    # to D^{-1/2} A D^{-1/2}, whose spectrum lies in (0, 2) by Gershgorin for this Laplacian
+    A = S.knn_graph_laplacian(1500, seed=2)
+    n, rp, c, v = A
+    b = S.uniform_vector(n, 5)
+    x, hist, iters = O.sstep_gmres_precond(A, b, np.zeros(n), 8, 48, "jacobi", 0.002, 2.0, 1e-10, 60,
+                                           values=values)
+    ref = spla.spsolve(csr_matrix((v, c, rp), shape=(n, n)).tocsc(), b)
+    assert hist[-1] <= 1e-10
+    assert np.linalg.norm(x - ref) <= 2e-10 * 2000 * np.linalg.norm(ref)
