@@ -387,8 +387,34 @@ mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, i
                            uint32_t flags, void* work, size_t work_bytes, int32_t* iters_out,
                            int32_t* cycles_out, double* relres_out, void* stream);
 
-/* Device work bytes that mpk_sstep_gmres needs for these arguments (n, s, m, d
- * and MPK_IO_PERMUTED in flags).  Errors: MPK_ERR_ARG. */
+/* preconditioners of mpk_sstep_gmres_ex */
+#define MPK_PRECOND_CHEBYSHEV 0 /* P^{-1} = s(A) of degree d - 1 (as mpk_sstep_gmres)     */
+#define MPK_PRECOND_NONE 1      /* M = A, x = x0 + Q y                                     */
+#define MPK_PRECOND_JACOBI 2    /* M = A D^{-1}, x = x0 + D^{-1} Q y (Sec. 5.1, fused)     */
+
+/*
+ * mpk_sstep_gmres with a choice of right preconditioner (Sec. 4 and Sec. 5.1).
+ * MPK_PRECOND_CHEBYSHEV is mpk_sstep_gmres.  With MPK_PRECOND_NONE and
+ * MPK_PRECOND_JACOBI each block of s basis vectors is one blocked Newton MPK of
+ * s powers (sstep_basis on `lo`: Alg. 3c's back-to-back SpMVs replaced by an
+ * MPK); [lmin, lmax] must then hold the spectrum of M (A, or A D^{-1}, which
+ * is similar to D^{-1/2} A D^{-1/2}) and gives the shifts: its s Chebyshev
+ * points in Leja order, each column scaled by (lmax - lmin) / 4.  `lo` holds
+ * A (MPK_PRECOND_NONE) or A D^{-1} (column_scaling = MPK_SCALE_JACOBI for
+ * MPK_PRECOND_JACOBI), with FP64 or FP32 values; `hi` holds A in FP64 and gives
+ * the residuals and, for Jacobi, the diagonal.  `degree` is used by
+ * MPK_PRECOND_CHEBYSHEV only (pass 1 otherwise); lmin may be <= 0 for the other
+ * two.  Errors as mpk_sstep_gmres, plus MPK_ERR_ARG for an unknown
+ * preconditioner or a `lo` plan of the wrong form.
+ */
+mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t precond, int32_t s, int32_t m, int32_t degree,
+                              double lmin, double lmax, const double* b, double* x, double tol,
+                              int32_t max_cycles, uint32_t flags, void* work, size_t work_bytes,
+                              int32_t* iters_out, int32_t* cycles_out, double* relres_out, void* stream);
+
+/* Device work bytes that mpk_sstep_gmres or mpk_sstep_gmres_ex needs for these
+ * arguments (n, s, m, d and MPK_IO_PERMUTED in flags; the same for every
+ * preconditioner).  Errors: MPK_ERR_ARG. */
 mpk_status mpk_sstep_gmres_work_bytes(mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, uint32_t flags,
                                       size_t* bytes);
 

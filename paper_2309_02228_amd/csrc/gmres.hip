@@ -160,6 +160,12 @@ __global__ __launch_bounds__(kThreads) void lincomb_kernel(const double* X0, int
     }
 }
 
+// x += z / d (the diagonal preconditioner applied to the correction)
+__global__ void add_div_kernel(double* __restrict__ x, const double* __restrict__ z, const double* __restrict__ d,
+                               int n) {
+    for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) x[i] = x[i] + z[i] / d[i];
+}
+
 // r = b - t
 __global__ void sub_kernel(const double* __restrict__ b, const double* __restrict__ t, double* __restrict__ r, int n) {
     for (int i = blockIdx.x * kThreads + threadIdx.x; i < n; i += gridDim.x * kThreads) r[i] = b[i] - t[i];
@@ -171,7 +177,7 @@ int grid_rows(int64_t n) { return (int)std::max<int64_t>(1, std::min<int64_t>(81
 struct Layout {
     int64_t ld = 0;          // doubles between vectors (256-byte multiple)
     int rows_per_blk = 0, nrb = 0;
-    size_t q = 0, w = 0, t = 0, z = 0, part = 0, small = 0, cbuf = 0, io = 0, poly = 0, total = 0;
+    size_t q = 0, w = 0, t = 0, z = 0, diag = 0, part = 0, small = 0, cbuf = 0, io = 0, poly = 0, total = 0;
     size_t poly_bytes = 0;
 };
 
@@ -188,9 +194,10 @@ Layout layout(int64_t n, int s, int m, size_t poly_bytes, bool permuted) {
         return here;
     };
     L.q = take((size_t)(m + 1) * L.ld);
-    L.w = take((size_t)s * L.ld);
+    L.w = take((size_t)(s + 1) * L.ld);  // the block's first vector, then W_1..W_s
     L.t = take(L.ld);
     L.z = take(L.ld);
+    L.diag = take(L.ld);
     L.part = take((size_t)L.nrb * (m + 1) * s);
     L.small = take((size_t)(m + 1) * s);
     L.cbuf = take((size_t)4 * kMaxC);
@@ -243,6 +250,7 @@ struct Solver {
     int s, m, degree;
     double theta, delta, tcheb;
     uint32_t poly_flags;
+    int precond;                         // MPK_PRECOND_*
     Layout L;
     double* base;
     hipStream_t st;
@@ -253,7 +261,8 @@ struct Solver {
 
     double* vec(size_t off) const { return base + off; }
     double* Q(int j) const { return base + L.q + (size_t)j * L.ld; }
-    double* W(int k) const { return base + L.w + (size_t)k * L.ld; }  // W_{k+1}
+    double* W(int k) const { return base + L.w + (size_t)(k + 1) * L.ld; }  // W_{k+1}
+    double* V0() const { return base + L.w; }                               // W_0 (a copy)
 
     mpk_status hip(hipError_t e, const char* what) {
         if (e == hipSuccess) return MPK_OK;
@@ -348,9 +357,17 @@ struct Solver {
         std::vector<double> rprev, G;
         for (;;) {
             const int sb = std::min(s, m - c);
-            // Newton basis of the block (Sec. 4): W_k = (M - lambda_k I) W_{k-1} / sigma_k
-            for (int k = 1; k <= sb; ++k) {
-                mpk_status s_ = newton_step(k == 1 ? Q(c) : W(k - 2), W(k - 1), lam[k - 1], sig[k - 1]);
+            // Newton basis of the block (Sec. 4): W_k = (M - lambda_k I) W_{k-1} / sigma_k,
+            // with the Chebyshev preconditioner one polynomial launch sequence per vector,
+            // otherwise one blocked MPK of sb powers for the whole block (Alg. 3c)
+            if (precond == MPK_PRECOND_CHEBYSHEV) {
+                for (int k = 1; k <= sb; ++k) {
+                    mpk_status s_ = newton_step(k == 1 ? Q(c) : W(k - 2), W(k - 1), lam[k - 1], sig[k - 1]);
+                    if (s_ != MPK_OK) return s_;
+                }
+            } else {
+                mpk_status s_ = sstep_basis(lo, sb, lam.data(), sig.data(), Q(c), V0(), L.ld, poly_flags, nullptr, 0,
+                                            st);
                 if (s_ != MPK_OK) return s_;
             }
             // BOrtho: R_prev = Q_{0..c}^T W, W' = W - Q R_prev
@@ -439,14 +456,24 @@ struct Solver {
                 rho2 += t * t;
             }
             if (dep || c >= m || std::sqrt(rho2) <= target) {
-                // x += s(A) Q_{0..c-1} y
-                if (c > 0) {
+                // x += P^{-1} Q_{0..c-1} y with P^{-1} = s(A), I or D^{-1}
+                if (c > 0 && precond == MPK_PRECOND_NONE) {
+                    s_ = lincomb(x, 1.0, Q(0), c, y, 1, x, 2);
+                    if (s_ != MPK_OK) return s_;
+                } else if (c > 0) {
                     s_ = lincomb(nullptr, 0.0, Q(0), c, y, 1, vec(L.z), 2);
                     if (s_ != MPK_OK) return s_;
-                    s_ = precondition(vec(L.z), vec(L.t));
-                    if (s_ != MPK_OK) return s_;
-                    s_ = lincomb(x, 1.0, vec(L.t), 1, std::vector<double>{1.0}, 1, x, 3);
-                    if (s_ != MPK_OK) return s_;
+                    if (precond == MPK_PRECOND_JACOBI) {
+                        hipLaunchKernelGGL(add_div_kernel, dim3(grid_rows(n)), dim3(kThreads), 0, st, x,
+                                           (const double*)vec(L.z), (const double*)vec(L.diag), n);
+                        s_ = hip(hipGetLastError(), "update launch");
+                        if (s_ != MPK_OK) return s_;
+                    } else {
+                        s_ = precondition(vec(L.z), vec(L.t));
+                        if (s_ != MPK_OK) return s_;
+                        s_ = lincomb(x, 1.0, vec(L.t), 1, std::vector<double>{1.0}, 1, x, 3);
+                        if (s_ != MPK_OK) return s_;
+                    }
                 }
                 *cols_out = c;
                 return MPK_OK;
@@ -476,20 +503,29 @@ MPK_API mpk_status mpk_sstep_gmres_work_bytes(mpk_plan_t lo, int32_t s, int32_t 
     return MPK_OK;
 }
 
-MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, double lmin,
-                                   double lmax, const double* b, double* x, double tol, int32_t max_cycles,
-                                   uint32_t flags, void* work, size_t work_bytes, int32_t* iters_out,
-                                   int32_t* cycles_out, double* relres_out, void* stream) {
+MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t precond, int32_t s, int32_t m,
+                                      int32_t degree, double lmin, double lmax, const double* b, double* x,
+                                      double tol, int32_t max_cycles, uint32_t flags, void* work, size_t work_bytes,
+                                      int32_t* iters_out, int32_t* cycles_out, double* relres_out, void* stream) {
     if (iters_out) *iters_out = 0;
     if (cycles_out) *cycles_out = 0;
     if (relres_out) *relres_out = 0.0;
     if (!hi || !lo) return mpk::set_error(MPK_ERR_ARG, "null plan");
-    if (!mpk::plan_is_f64(hi)) return mpk::set_error(MPK_ERR_ARG, "hi must store FP64 values");
+    if (precond < MPK_PRECOND_CHEBYSHEV || precond > MPK_PRECOND_JACOBI)
+        return mpk::set_error(MPK_ERR_ARG, "unknown preconditioner %d", precond);
+    if (!mpk::plan_is_f64(hi) || mpk::plan_column_scaling(hi) != MPK_SCALE_NONE)
+        return mpk::set_error(MPK_ERR_ARG, "hi must store the FP64 values of A");
     if (!mpk::plans_match(hi, lo))
         return mpk::set_error(MPK_ERR_ARG, "hi and lo must be plans of the same matrix with the same level order");
+    if (mpk::plan_column_scaling(lo) != (precond == MPK_PRECOND_JACOBI ? MPK_SCALE_JACOBI : MPK_SCALE_NONE))
+        return mpk::set_error(MPK_ERR_ARG, precond == MPK_PRECOND_JACOBI
+                                               ? "lo must hold A D^{-1} (column_scaling = MPK_SCALE_JACOBI)"
+                                               : "lo must hold A (column_scaling = MPK_SCALE_NONE)");
     if (!params_ok(s, m, degree))
         return mpk::set_error(MPK_ERR_ARG, "need 1 <= s <= %d, s <= m <= %d, 1 <= degree <= 4096", kMaxS, kMaxM);
-    if (!(lmin > 0.0) || !(lmax > lmin)) return mpk::set_error(MPK_ERR_ARG, "need 0 < lmin < lmax");
+    if (precond == MPK_PRECOND_CHEBYSHEV && !(lmin > 0.0))
+        return mpk::set_error(MPK_ERR_ARG, "need 0 < lmin < lmax");
+    if (!(lmax > lmin)) return mpk::set_error(MPK_ERR_ARG, "need lmin < lmax");
     if (!(tol >= 0.0)) return mpk::set_error(MPK_ERR_ARG, "tol must be >= 0");
     if (max_cycles < 0) return mpk::set_error(MPK_ERR_ARG, "max_cycles must be >= 0");
     if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return mpk::set_error(MPK_ERR_ARG, "unknown flag bits");
@@ -519,6 +555,7 @@ MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int3
         S.delta = 0.5 * (lmax - lmin);
         S.tcheb = std::cosh(degree * std::acosh(S.theta / S.delta));
         S.poly_flags = MPK_IO_PERMUTED | (flags & (MPK_PLAIN | MPK_STAGED));
+        S.precond = precond;
         size_t pb = 0;
         mpk_work_bytes(lo, MPK_CALL_POLY, degree, MPK_IO_PERMUTED, &pb);
         const bool permuted = flags & MPK_IO_PERMUTED;
@@ -534,11 +571,13 @@ MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int3
             for (int k = 0; k < degree; ++k) S.coef[k] += std::cos(k * ang) * inv;
         }
         for (int k = 0; k < degree; ++k) S.coef[k] *= (k == 0 ? 1.0 : 2.0) / degree;
-        // Newton shifts: the s Chebyshev points of [1 - eps, 1 + eps] (M's spectrum for
-        // A's spectrum in [lmin, lmax]) in Leja order, columns scaled by eps / 2
-        const double eps = 1.0 / S.tcheb;
+        // Newton shifts: the s Chebyshev points of the interval holding M's spectrum in Leja
+        // order, columns scaled by half its half-width: [1 - eps, 1 + eps] with the Chebyshev
+        // preconditioner (A's spectrum in [lmin, lmax]), else [lmin, lmax] itself
+        const double eps = precond == MPK_PRECOND_CHEBYSHEV ? 1.0 / S.tcheb : 0.5 * (lmax - lmin);
+        const double mid = precond == MPK_PRECOND_CHEBYSHEV ? 1.0 : 0.5 * (lmax + lmin);
         std::vector<double> pts(s);
-        for (int i = 0; i < s; ++i) pts[i] = 1.0 + eps * std::cos(3.14159265358979323846 * (2 * i + 1) / (2.0 * s));
+        for (int i = 0; i < s; ++i) pts[i] = mid + eps * std::cos(3.14159265358979323846 * (2 * i + 1) / (2.0 * s));
         std::vector<bool> used(s, false);
         for (int t = 0; t < s; ++t) {
             int best = -1;
@@ -569,6 +608,10 @@ MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int3
             if (st != MPK_OK) return st;
             bp = io;
             xp = io + S.L.ld;
+        }
+        if (precond == MPK_PRECOND_JACOBI) {  // D in level order, from the FP64 plan
+            st = mpk::plan_diagonal(hi, S.vec(S.L.diag), stream);
+            if (st != MPK_OK) return st;
         }
         std::vector<double> g;
         st = S.gram(bp, 1, bp, 1, g);
@@ -605,4 +648,12 @@ MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int3
     } catch (const std::bad_alloc&) {
         return mpk::set_error(MPK_ERR_NOMEM, "out of host memory");
     }
+}
+
+MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, double lmin,
+                                   double lmax, const double* b, double* x, double tol, int32_t max_cycles,
+                                   uint32_t flags, void* work, size_t work_bytes, int32_t* iters_out,
+                                   int32_t* cycles_out, double* relres_out, void* stream) {
+    return mpk_sstep_gmres_ex(hi, lo, MPK_PRECOND_CHEBYSHEV, s, m, degree, lmin, lmax, b, x, tol, max_cycles, flags,
+                              work, work_bytes, iters_out, cycles_out, relres_out, stream);
 }

@@ -12,6 +12,10 @@ mpk_status set_error(mpk_status s, const char* fmt, ...);
 bool plan_is_f64(mpk_plan_t p);
 // MPK_OK when the plan has been uploaded, else MPK_ERR_STATE (message set).
 mpk_status plan_uploaded(mpk_plan_t p);
+// MPK_SCALE_NONE or MPK_SCALE_JACOBI: whether the plan holds A or A D^{-1}.
+int plan_column_scaling(mpk_plan_t p);
+// out (device, n, level order) = the stored diagonal of the plan's matrix, on `stream`.
+mpk_status plan_diagonal(mpk_plan_t p, double* out, void* stream);
 // True when the two plans hold the same matrix size, pattern size and level order.
 bool plans_match(mpk_plan_t a, mpk_plan_t b);
 }  // namespace mpk

@@ -617,6 +617,25 @@ __global__ void permute_kernel(const double* in, int64_t ld_in, double* out, int
     }
 }
 
+// out[row] = the row's diagonal entry of P A P^T as stored (0 if none), level order
+template <typename VT>
+__global__ void diagonal_kernel(DevPlan P, double* out) {
+    const int lane = threadIdx.x & 63;
+    const int nchunks = (P.n + kChunkRows - 1) / kChunkRows;
+    for (int c = blockIdx.x * kWaves + (threadIdx.x >> 6); c < nchunks; c += gridDim.x * kWaves) {
+        const int row = c * kChunkRows + lane;
+        if (row >= P.n) continue;
+        const int64_t off = P.off[c];
+        const int width = (int)((P.off[c + 1] - off) / kChunkRows);
+        double d = 0.0;
+        for (int j = 0; j < width; ++j) {
+            const int64_t slot = off + (int64_t)j * kChunkRows + lane;
+            if (P.col[slot] == row) d = decode<VT>(((const VT*)P.val)[slot], row_scale<VT>(P, row));
+        }
+        out[row] = d;
+    }
+}
+
 __global__ void scale_kernel(const double* x, double* out, double a, int32_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -1101,6 +1120,23 @@ mpk_status mpk::set_error(mpk_status s, const char* fmt, ...) {
 }
 
 mpk_status mpk::plan_uploaded(mpk_plan_t p) { return check_uploaded(p); }
+
+int mpk::plan_column_scaling(mpk_plan_t p) { return p ? p->column_scaling : MPK_SCALE_NONE; }
+
+mpk_status mpk::plan_diagonal(mpk_plan_t p, double* out, void* stream) {
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK || p->H.n == 0) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int grid = std::max(1, std::min(p->cus * 8, (p->H.nchunks + kWaves - 1) / kWaves));
+    if (p->H.value_type == MPK_VALUES_BF16_ROWSCALE)
+        diagonal_kernel<uint16_t><<<grid, kBlockThreads, 0, st>>>(p->D, out);
+    else if (p->H.value_type == MPK_VALUES_F32)
+        diagonal_kernel<float><<<grid, kBlockThreads, 0, st>>>(p->D, out);
+    else
+        diagonal_kernel<double><<<grid, kBlockThreads, 0, st>>>(p->D, out);
+    HIP_TRY(hipGetLastError());
+    return MPK_OK;
+}
 
 bool mpk::plan_is_f64(mpk_plan_t p) { return p && p->H.value_type == MPK_VALUES_F64; }
 

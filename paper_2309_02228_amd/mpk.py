@@ -19,6 +19,7 @@ MPK_STAGED = 4
 MPK_LAST_POWER = 8  # server applies: return y_p only
 VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}  # bf16: BF16 values with a per-row FP32 scale
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
+PRECONDS = {"chebyshev": 0, "none": 1, "jacobi": 2}  # right preconditioners of sstep_gmres
 CALL_APPLY, CALL_POLY, CALL_SSTEP, CALL_SOLVE = 0, 1, 2, 3
 
 STATUS = {0: "MPK_OK", -1: "MPK_ERR_ARG", -2: "MPK_ERR_CSR", -3: "MPK_ERR_NOMEM",
@@ -34,7 +35,7 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_server_create", "mpk_server_submit_apply", "mpk_server_submit_solve",
            "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes",
            "mpk_server_submit_gmres", "mpk_jacobi_apply", "mpk_jacobi_work_bytes",
-           "mpk_gs2_apply", "mpk_gs2_work_bytes"]
+           "mpk_gs2_apply", "mpk_gs2_work_bytes", "mpk_sstep_gmres_ex"]
 
 
 class MPKError(RuntimeError):
@@ -99,6 +100,8 @@ def _load():
         "mpk_sstep_gmres": (I32, [P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double, P, P, ctypes.c_double,
                                   I32, U32, P, SZ, pI32, pI32, ctypes.POINTER(ctypes.c_double), P]),
         "mpk_sstep_gmres_work_bytes": (I32, [P, I32, I32, I32, U32, pSZ]),
+        "mpk_sstep_gmres_ex": (I32, [P, P, I32, I32, I32, I32, ctypes.c_double, ctypes.c_double, P, P,
+                                     ctypes.c_double, I32, U32, P, SZ, pI32, pI32, ctypes.POINTER(ctypes.c_double), P]),
         "mpk_jacobi_apply": (I32, [P, I32, P, P, I64, I32, U32, P, SZ, P]),
         "mpk_jacobi_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_gs2_apply": (I32, [P, I32, P, P, I64, I32, U32, P, SZ, P]),
@@ -360,7 +363,7 @@ class Plan:
         return nb.value
 
     def sstep_gmres(self, lo, b, s, m, degree, lmin, lmax, tol=1e-10, max_cycles=100, x=None, permuted=True,
-                    plain=False, staged=False, stream=None, work=None):
+                    plain=False, staged=False, stream=None, work=None, precond="chebyshev"):
         """Solve A x = b by restarted s-step GMRES (blocks of ``s``, restart ``m``) with the
         right degree-``degree`` Chebyshev polynomial preconditioner on [lmin, lmax]:
         FP64 residuals with this plan, basis and preconditioner with ``lo`` (the same
@@ -374,10 +377,12 @@ class Plan:
         if work is None:
             work = torch.empty(nb // 8 + 64, dtype=torch.float64, device=b.device)
         it, cy, rel = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-        _check(_lib.mpk_sstep_gmres(self._h, lo._h, int(s), int(m), int(degree), float(lmin), float(lmax), _dptr(b),
-                                    _dptr(x), float(tol), int(max_cycles), flags, _dptr(work),
-                                    work.numel() * work.element_size(), ctypes.byref(it), ctypes.byref(cy),
-                                    ctypes.byref(rel), _stream(stream)))
+        if precond not in PRECONDS:
+            raise ValueError(f"precond must be one of {sorted(PRECONDS)}")
+        _check(_lib.mpk_sstep_gmres_ex(self._h, lo._h, PRECONDS[precond], int(s), int(m), int(degree), float(lmin),
+                                       float(lmax), _dptr(b), _dptr(x), float(tol), int(max_cycles), flags,
+                                       _dptr(work), work.numel() * work.element_size(), ctypes.byref(it),
+                                       ctypes.byref(cy), ctypes.byref(rel), _stream(stream)))
         return x, it.value, cy.value, rel.value
 
     def permute(self, x, direction=0, out=None, stream=None):

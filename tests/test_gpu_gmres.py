@@ -28,6 +28,7 @@ from paper_2309_02228_amd import Plan, MPKError  # noqa: E402
 
 DEV = "cuda:0"
 FIXED_CYCLE_RTOL = 1e-9
+BLOCK_BASIS_RTOL = 1e-8
 
 
 def lap_bounds(dims):
@@ -178,3 +179,86 @@ def test_full_size_160_cubed_mixed_precision_solve():
     M = csr_matrix((A.val, A.col, A.rowptr), shape=(A.n, A.n))
     true = np.linalg.norm(b - M @ x) / np.linalg.norm(b)
     assert rel <= 1e-10 and true <= 1.0000001e-10 and abs(true - rel) <= 1e-12
+
+
+# ------------------------------- without a preconditioner and with Jacobi (reading R22)
+def jacobi_knn(n, seed, shift=0.1):
+    # A D^{-1} is similar to D^{-1/2} A D^{-1/2}, whose spectrum lies in (0, 2) by
+    # Gershgorin and above shift / (max degree + shift) since A >= shift I
+    A = S.knn_graph_laplacian(n, k=26, seed=seed, shift=shift)
+    dmax = float(np.max(np.diff(A.rowptr))) - 1.0
+    return A, shift / (dmax + shift), 2.0
+
+
+def gmres_plans(A, precond, values="f64", q=8):
+    hi = Plan.from_csr(A, p_block=q).upload(DEV)
+    if precond == "jacobi":
+        lo = Plan.from_csr(A, p_block=q, values=values, column_scaling="jacobi").upload(DEV)
+    else:
+        lo = hi if values == "f64" else Plan.from_csr(A, p_block=q, values=values).upload(DEV)
+    return hi, lo
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+@pytest.mark.parametrize("values", ["f64", "f32"])
+@pytest.mark.parametrize("s,m", [(1, 8), (4, 16), (8, 32), (5, 12)])
+def test_fixed_cycle_without_and_with_jacobi_matches_oracle(precond, values, s, m):
+    if precond == "none":
+        dims = (37, 29)
+        A = S.laplacian_2d(*dims)
+        lmin, lmax = lap_bounds(dims)
+    else:
+        # well-conditioned Newton blocks (shift 2): with the 0.1 shift an 8-column block
+        # over [0.003, 2] is so ill-conditioned that Cholesky QR, which squares the
+        # condition, lets two correct runs differ in the third digit after one cycle;
+        # that case is covered by the converged solve below
+        A, lmin, lmax = jacobi_knn(6000, 2, shift=2.0)
+    b = S.uniform_vector(A.n, 3)
+    hi, lo = gmres_plans(A, precond, values)
+    x, it, cy, rel = solve(hi, lo, b, s, m, 1, lmin, lmax, 0.0, 1, precond=precond)
+    xo, hist, ito = O.sstep_gmres_precond(A, b, np.zeros(A.n), s, m, precond, lmin, lmax, 0.0, 1,
+                                          values=None if values == "f64" else np.float32)
+    assert it == ito == m and cy == 1
+    # the block's basis comes from one MPK whose columns are only as independent as the
+    # Newton polynomials make them; Cholesky QR amplifies rounding by about kappa(W)^2,
+    # and for blocks of up to 8 columns over these intervals kappa(W) stays below ~1e4,
+    # so u kappa^2 ~ 1e-8 bounds the difference of two correct runs after one cycle
+    assert np.linalg.norm(x - xo) <= BLOCK_BASIS_RTOL * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_blocked_basis_solve_to_1e10(precond):
+    if precond == "none":
+        dims = (37, 29)
+        A = S.laplacian_2d(*dims)
+        lmin, lmax = lap_bounds(dims)
+    else:
+        A, lmin, lmax = jacobi_knn(20000, 3)
+    b = S.uniform_vector(A.n, 4)
+    hi, lo = gmres_plans(A, precond)
+    x, it, cy, rel = solve(hi, lo, b, 8, 64, 1, lmin, lmax, 1e-10, 80, precond=precond)
+    xo, hist, ito = O.sstep_gmres_precond(A, b, np.zeros(A.n), 8, 64, precond, lmin, lmax, 1e-10, 80)
+    assert rel <= 1e-10 and abs(cy - (len(hist) - 1)) <= 1 and abs(it - ito) <= 64
+    assert np.linalg.norm(b - O.spmv(A, x)) <= 1.0000001e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xo) <= 2e-10 * (lmax / lmin) * np.linalg.norm(xo)
+    # blocked, plain and staged bases give the same solution bitwise
+    xp, ip, cp, rp = solve(hi, lo, b, 8, 64, 1, lmin, lmax, 1e-10, 80, precond=precond, plain=True)
+    xs, is_, cs, rs = solve(hi, lo, b, 8, 64, 1, lmin, lmax, 1e-10, 80, precond=precond, staged=True)
+    assert np.array_equal(x, xp) and np.array_equal(x, xs) and it == ip == is_
+
+
+def test_preconditioner_plan_forms_are_checked():
+    A = S.laplacian_2d(9, 7)
+    lmin, lmax = lap_bounds((9, 7))
+    b = torch.tensor(S.uniform_vector(A.n, 2), device=DEV)
+    hi = Plan.from_csr(A).upload(DEV)
+    jac = Plan.from_csr(A, column_scaling="jacobi").upload(DEV)
+    with pytest.raises(MPKError, match="MPK_ERR_ARG"):
+        hi.sstep_gmres(hi, b, 4, 8, 1, lmin / 4, lmax / 4, precond="jacobi")   # lo must hold A D^-1
+    with pytest.raises(MPKError, match="MPK_ERR_ARG"):
+        hi.sstep_gmres(jac, b, 4, 8, 1, lmin, lmax, precond="none")           # lo must hold A
+    with pytest.raises(MPKError, match="MPK_ERR_ARG"):
+        jac.sstep_gmres(jac, b, 4, 8, 1, lmin, lmax, precond="jacobi")        # hi must hold A
+    # a nonpositive lmin is allowed without the Chebyshev preconditioner
+    x, it, cy, rel = hi.sstep_gmres(hi, b, 4, 8, 1, -1.0, lmax, tol=1e-10, max_cycles=40, precond="none")
+    assert rel <= 1e-10
