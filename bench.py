@@ -641,7 +641,33 @@ def main():
         log(f"gmres: mixed {gm_mixed['p50_ms']:.1f} ms p50 ({gm_mixed['basis_vectors']} vectors, "
             f"{gm_mixed['cycles']} cycles, true residual {gm_mixed['true_rel_residual']:.2e}), fp64 plain "
             f"{gm_plain['p50_ms']:.1f} ms p50")
-        del hi8, lo8, work
+        # s-step GMRES as in the paper's s-step experiments: a fixed amount of work (two
+        # cycles of m = 64, s = 8, FP64) with each block's basis from one MPK of 8 powers,
+        # blocked against plain launches; time per 1000 basis vectors
+        fixed = {}
+        jac8 = Plan.from_csr(A, p_block=8, column_scaling="jacobi").upload(dev)
+        for name, lo_, lmin_, lmax_ in (("none", hi8, lmin, lmax), ("jacobi", jac8, lmin / 6, lmax / 6)):
+            t = {}
+            for plain_ in (False, True):
+                hi8.sstep_gmres(lo_, bvec, 8, 64, 1, lmin_, lmax_, tol=0.0, max_cycles=2, plain=plain_, work=work,
+                                precond=name)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                for _ in range(3):
+                    res = hi8.sstep_gmres(lo_, bvec, 8, 64, 1, lmin_, lmax_, tol=0.0, max_cycles=2, plain=plain_,
+                                          work=work, precond=name)
+                torch.cuda.synchronize()
+                t[plain_] = (time.perf_counter() - t0) / 3 / res[1] * 1e3 * 1e3  # ms per 1000 vectors
+            fixed[name] = {"blocked_ms_per_1000_vectors": round(t[False], 2),
+                           "plain_ms_per_1000_vectors": round(t[True], 2), "speedup": round(t[True] / t[False], 3)}
+        jac8.check()
+        out["sstep_gmres_fixed_work"] = {
+            "workload": f"s-step GMRES on the 3D 7-point Laplacian {g}^3, s = 8, m = 64, two cycles (128 basis "
+                        "vectors), FP64; without a preconditioner and with the fused Jacobi A D^-1; each block's "
+                        "basis is one MPK of 8 powers (blocked) or 8 SpMV launches (plain)", **fixed}
+        log("s-step gmres: " + ", ".join(f"{k2}: {v['blocked_ms_per_1000_vectors']} ms/1000 vectors blocked, "
+                                           f"{v['speedup']}x" for k2, v in fixed.items()))
+        del hi8, lo8, work, jac8
     if not args.no_serve and args.only == "both":
         out["serving"] = serving_bench(args, A, plan, dev)
         sv = out["serving"]["by_kind"]["solve"]
