@@ -259,6 +259,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true", help="skip the p = 1..8 sweep")
     ap.add_argument("--solve-reps", type=int, default=10)
     ap.add_argument("--no-serve", action="store_true", help="skip the request-serving measurement")
+    ap.add_argument("--no-cold", action="store_true", help="skip the cold-cache timing (profiler runs)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-workers", type=int, default=4)
     ap.add_argument("--serve-load", type=float, default=0.8,
@@ -419,7 +420,8 @@ def main():
         "plan_build_s": round(t_plan, 3),
         "plan_upload_s": round(t_upload, 3),
     }
-    if args.only == "both":
+    res_cold = None
+    if args.only == "both" and not args.no_cold:
         # cold-cache protocol: a 2 GiB write before every run evicts the matrix from L2 and
         # the 256 MB Infinity Cache; 3 warm-ups, then 20 runs timed one by one
         scrub = torch.empty(1 << 28, dtype=torch.float64, device=dev)
@@ -446,6 +448,7 @@ def main():
                     "speedup_median": round(cold_p["median_us"] / cold_b["median_us"], 3),
                     "note": "each MPK call timed alone after writing 2 GiB (L2 and Infinity Cache evicted)"}
         log(f"cold caches: blocked {cold_b['median_us']} us, plain {cold_p['median_us']} us (median of 20)")
+    if args.only == "both":
         # the paper's level-group wavefront (one launch per stage) for comparison
         wall_s, _ = timed_staged()
         ng, tasks = plan.schedule(info["p_block"])
@@ -464,7 +467,8 @@ def main():
         out["roofline_equivalent_frac"] = round(value / (flops / (b_blk / (HBM_PEAK_GBS * 1e9)) / 1e9), 4)
     if args.only == "both":
         out["staged_wavefront"] = res_staged
-        out["cold_cache_timing"] = res_cold
+        if res_cold is not None:
+            out["cold_cache_timing"] = res_cold
     if args.only == "both" and not args.no_sweep:
         # p = 1..8 with one plan of blocks up to 8 powers (shorter jobs are one block)
         plan8 = Plan.from_csr(A, p_block=8).upload(dev)
