@@ -132,8 +132,9 @@ READINGS = {
            "g_0 = D^{-1} v and z^1 = g_gamma. That is the form taken: g_j = g_0 - D^{-1} L "
            "g_{j-1}, j = 1..gamma, P^{-1} v = g_gamma, with L the strictly lower triangle "
            "in the original numbering; the MPK is w_j = A P^{-1} w_{j-1}.",
-    "R22": "s-step GMRES without a preconditioner (M = A) or with the diagonal Jacobi "
-           "preconditioner from the right (M = A D^{-1}, x = x0 + D^{-1} Q y; Sec. 4 and 5.1): "
+    "R22": "s-step GMRES without a preconditioner (M = A), with the diagonal Jacobi "
+           "preconditioner from the right (M = A D^{-1}, x = x0 + D^{-1} Q y), or with GS2 "
+           "(M = A P^{-1} of R21, x = x0 + P^{-1} Q y; Sec. 4 and 5.1): "
            "each block of s basis vectors is one Newton MPK of s powers (Alg. 3c's "
            "back-to-back SpMVs replaced by an MPK). The shifts are the s Chebyshev points of "
            "a caller-given interval [lmin, lmax] holding M's spectrum, in Leja order, each "
@@ -462,14 +463,16 @@ def interval_shifts(s, lo, hi):
     return leja_order(c + h * np.cos(np.pi * (2 * i + 1) / (2 * s))), np.full(s, 0.5 * h)
 
 
-def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, values=None):
-    """Reading R22: s-step GMRES (Alg. 3a/3c) without a preconditioner (M = A, x = x0 + Q y)
-    or with the diagonal (one-sweep Jacobi) preconditioner from the right (M = A D^{-1},
-    x = x0 + D^{-1} Q y, Sec. 5.1); [lmin, lmax] holds the spectrum of M, the shifts are
-    those of interval_shifts, and the cycle is sstep_cycle.  With ``values`` the basis uses
-    the rounded matrix (M = round(A) or round(A D^{-1})).  Returns (x, history, iters)."""
-    if precond not in ("none", "jacobi"):
-        raise ValueError("precond must be 'none' or 'jacobi'")
+def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, values=None, gamma=1):
+    """Reading R22: s-step GMRES (Alg. 3a/3c) without a preconditioner (M = A, x = x0 + Q y),
+    with the diagonal (one-sweep Jacobi) preconditioner from the right (M = A D^{-1},
+    x = x0 + D^{-1} Q y, Sec. 5.1), or with the GS2 preconditioner of gs2_precondition
+    (M = A P^{-1}, x = x0 + P^{-1} Q y, ``gamma`` inner sweeps); [lmin, lmax] holds the
+    spectrum of M, the shifts are those of interval_shifts, and the cycle is sstep_cycle.
+    With ``values`` the basis and the preconditioner use the rounded matrix.
+    Returns (x, history, iters)."""
+    if precond not in ("none", "jacobi", "gs2"):
+        raise ValueError("precond must be 'none', 'jacobi' or 'gs2'")
     d = diagonal(A) if precond == "jacobi" else None
     if precond == "jacobi":
         n, rp, c, v = _arrays(A)
@@ -477,6 +480,12 @@ def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, va
     else:
         Mmat = A
     Mlo = Mmat if values is None else round_values(Mmat, values)
+    if precond == "gs2":
+        def apply_M(w):
+            return spmv(Mlo, gs2_precondition(Mlo, w, gamma))
+    else:
+        def apply_M(w):
+            return spmv(Mlo, w)
     lambdas, sigmas = interval_shifts(s, lmin, lmax)
     b = np.asarray(b, dtype=np.float64)
     x = np.array(x0, dtype=np.float64)
@@ -488,11 +497,13 @@ def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, va
         hist.append(beta / nb if nb > 0 else beta)
         if hist[-1] <= tol or cyc == max_cycles or beta == 0.0:
             break
-        Q, H, y, rho = sstep_cycle(lambda w: spmv(Mlo, w), r / beta, m, s, lambdas, sigmas, beta, tol * nb)
+        Q, H, y, rho = sstep_cycle(apply_M, r / beta, m, s, lambdas, sigmas, beta, tol * nb)
         iters += H.shape[1]
         z = np.zeros_like(x)
         for j in range(y.size):
             z = z + y[j] * Q[j]
+        if precond == "gs2":
+            z = gs2_precondition(Mlo, z, gamma)
         x = x + (z / d if d is not None else z)
     return x, hist, iters
 

@@ -316,3 +316,26 @@ def test_jacobi_gmres_solves_knn_laplacian(values):
     ref = spla.spsolve(csr_matrix((v, c, rp), shape=(n, n)).tocsc(), b)
     assert hist[-1] <= 1e-10
     assert np.linalg.norm(x - ref) <= 2e-10 * 2000 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("gamma", [0, 1, 2])
+@pytest.mark.parametrize("s,m", [(1, 9), (3, 12), (4, 12)])
+def test_gs2_cycle_equals_textbook_gmres(gamma, s, m):
+    # M = A P^{-1} with P^{-1} = sum_{i<=gamma} (-D^{-1} L)^i D^{-1} built densely; one
+    # cycle equals textbook GMRES on M, mapped back by x = P^{-1} Q y
+    # catches: the final map without P^{-1}, the operator without the preconditioner
+    A = S.random_pattern(50, 5, 17, symmetric=False)
+    Ad = dense(A)
+    Ad[np.arange(50), np.arange(50)] = 1.0 + np.abs(Ad).sum(axis=1)
+    A = S.from_dense(Ad)
+    D = np.diag(np.diag(Ad))
+    N = -np.linalg.solve(D, np.tril(Ad, -1))
+    P = sum(np.linalg.matrix_power(N, i) for i in range(gamma + 1)) @ np.linalg.inv(D)
+    M = Ad @ P
+    b = S.uniform_vector(50, 8)
+    ev = np.linalg.eigvals(M)
+    lo, hi = float(ev.real.min()) * 0.9, float(ev.real.max()) * 1.1
+    x1, hist, iters = O.sstep_gmres_precond(A, b, np.zeros(50), s, m, "gs2", lo, hi, 0.0, 1, gamma=gamma)
+    x_ref = P @ textbook_gmres_cycle(M, b, m)
+    assert iters == m
+    np.testing.assert_allclose(x1, x_ref, rtol=0, atol=1e-9 * np.abs(x_ref).max())
