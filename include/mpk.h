@@ -391,6 +391,8 @@ mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, i
 #define MPK_PRECOND_CHEBYSHEV 0 /* P^{-1} = s(A) of degree d - 1 (as mpk_sstep_gmres)     */
 #define MPK_PRECOND_NONE 1      /* M = A, x = x0 + Q y                                     */
 #define MPK_PRECOND_JACOBI 2    /* M = A D^{-1}, x = x0 + D^{-1} Q y (Sec. 5.1, fused)     */
+#define MPK_PRECOND_GS2 3       /* M = A P^{-1}, P^{-1} one GS2 iteration from zero with
+                                   gamma = degree inner sweeps, x = x0 + P^{-1} Q y        */
 
 /*
  * mpk_sstep_gmres with a choice of right preconditioner (Sec. 4 and Sec. 5.1).
@@ -402,9 +404,13 @@ mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, i
  * points in Leja order, each column scaled by (lmax - lmin) / 4.  `lo` holds
  * A (MPK_PRECOND_NONE) or A D^{-1} (column_scaling = MPK_SCALE_JACOBI for
  * MPK_PRECOND_JACOBI), with FP64 or FP32 values; `hi` holds A in FP64 and gives
- * the residuals and, for Jacobi, the diagonal.  `degree` is used by
- * MPK_PRECOND_CHEBYSHEV only (pass 1 otherwise); lmin may be <= 0 for the other
- * two.  Errors as mpk_sstep_gmres, plus MPK_ERR_ARG for an unknown
+ * the residuals and, for Jacobi, the diagonal.  With MPK_PRECOND_GS2, `lo` is
+ * built with split_lower, `degree` is gamma (0..16), each block's basis is one
+ * GS2 chain of s powers (s (gamma + 2) sub-powers blocked together, the Newton
+ * shift applied as each power closes; see mpk_gs2_apply), [lmin, lmax] holds
+ * the spectrum of A P^{-1}, and x = x0 + P^{-1} Q y with P^{-1} as a chain of
+ * gamma + 1 sub-powers.  `degree` is unused by MPK_PRECOND_NONE and
+ * MPK_PRECOND_JACOBI (pass 1); lmin may be <= 0 for all but Chebyshev.  Errors as mpk_sstep_gmres, plus MPK_ERR_ARG for an unknown
  * preconditioner or a `lo` plan of the wrong form.
  */
 mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t precond, int32_t s, int32_t m, int32_t degree,

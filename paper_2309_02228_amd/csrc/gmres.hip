@@ -365,6 +365,10 @@ struct Solver {
                     mpk_status s_ = newton_step(k == 1 ? Q(c) : W(k - 2), W(k - 1), lam[k - 1], sig[k - 1]);
                     if (s_ != MPK_OK) return s_;
                 }
+            } else if (precond == MPK_PRECOND_GS2) {  // one GS2 chain of sb powers, shifts at the closings
+                mpk_status s_ = mpk::gs2_chain(lo, degree, Q(c), W(0), L.ld, sb, lam.data(), sig.data(), 0, poly_flags,
+                                               vec(L.poly), L.poly_bytes, st);
+                if (s_ != MPK_OK) return s_;
             } else {
                 mpk_status s_ = sstep_basis(lo, sb, lam.data(), sig.data(), Q(c), V0(), L.ld, poly_flags, nullptr, 0,
                                             st);
@@ -463,7 +467,13 @@ struct Solver {
                 } else if (c > 0) {
                     s_ = lincomb(nullptr, 0.0, Q(0), c, y, 1, vec(L.z), 2);
                     if (s_ != MPK_OK) return s_;
-                    if (precond == MPK_PRECOND_JACOBI) {
+                    if (precond == MPK_PRECOND_GS2) {  // t = P^{-1} z, x += t
+                        s_ = mpk::gs2_chain(lo, degree, vec(L.z), vec(L.t), L.ld, 1, nullptr, nullptr, 1, poly_flags,
+                                            vec(L.poly), L.poly_bytes, st);
+                        if (s_ != MPK_OK) return s_;
+                        s_ = lincomb(x, 1.0, vec(L.t), 1, std::vector<double>{1.0}, 1, x, 3);
+                        if (s_ != MPK_OK) return s_;
+                    } else if (precond == MPK_PRECOND_JACOBI) {
                         hipLaunchKernelGGL(add_div_kernel, dim3(grid_rows(n)), dim3(kThreads), 0, st, x,
                                            (const double*)vec(L.z), (const double*)vec(L.diag), n);
                         s_ = hip(hipGetLastError(), "update launch");
@@ -483,7 +493,24 @@ struct Solver {
 };
 
 bool params_ok(int32_t s, int32_t m, int32_t degree) {
-    return s >= 1 && s <= kMaxS && m >= s && m <= kMaxM && degree >= 1 && degree <= 4096;
+    return s >= 1 && s <= kMaxS && m >= s && m <= kMaxM && degree >= 0 && degree <= 4096;
+}
+
+// Bytes of the polynomial ring: the Chebyshev ring of poly_apply, or for a plan with
+// lower-triangle masks (the GS2 preconditioner, degree = gamma) the GS2 ring.
+mpk_status ring_bytes(mpk_plan_t lo, int32_t degree, size_t* bytes) {
+    size_t pb = 0;
+    mpk_status st = mpk_work_bytes(lo, MPK_CALL_POLY, std::max(degree, 1), MPK_IO_PERMUTED, &pb);
+    if (st != MPK_OK) return st;
+    if (mpk::plan_split_lower(lo)) {
+        int64_t n = 0;
+        st = mpk_plan_info(lo, &n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
+        if (st != MPK_OK) return st;
+        const size_t gs2 = (size_t)(mpk::plan_p_block(lo) + std::min(degree, 16) + 2) * ((n + 31) / 32 * 32) * 8;
+        pb = std::max(pb, gs2);
+    }
+    *bytes = pb;
+    return MPK_OK;
 }
 
 }  // namespace
@@ -497,7 +524,7 @@ MPK_API mpk_status mpk_sstep_gmres_work_bytes(mpk_plan_t lo, int32_t s, int32_t 
     mpk_status st = mpk_plan_info(lo, &n, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     if (st != MPK_OK) return st;
     size_t pb = 0;
-    st = mpk_work_bytes(lo, MPK_CALL_POLY, degree, MPK_IO_PERMUTED, &pb);
+    st = ring_bytes(lo, degree, &pb);
     if (st != MPK_OK) return st;
     *bytes = layout(n, s, m, pb, flags & MPK_IO_PERMUTED).total;
     return MPK_OK;
@@ -511,7 +538,7 @@ MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t prec
     if (cycles_out) *cycles_out = 0;
     if (relres_out) *relres_out = 0.0;
     if (!hi || !lo) return mpk::set_error(MPK_ERR_ARG, "null plan");
-    if (precond < MPK_PRECOND_CHEBYSHEV || precond > MPK_PRECOND_JACOBI)
+    if (precond < MPK_PRECOND_CHEBYSHEV || precond > MPK_PRECOND_GS2)
         return mpk::set_error(MPK_ERR_ARG, "unknown preconditioner %d", precond);
     if (!mpk::plan_is_f64(hi) || mpk::plan_column_scaling(hi) != MPK_SCALE_NONE)
         return mpk::set_error(MPK_ERR_ARG, "hi must store the FP64 values of A");
@@ -521,8 +548,12 @@ MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t prec
         return mpk::set_error(MPK_ERR_ARG, precond == MPK_PRECOND_JACOBI
                                                ? "lo must hold A D^{-1} (column_scaling = MPK_SCALE_JACOBI)"
                                                : "lo must hold A (column_scaling = MPK_SCALE_NONE)");
-    if (!params_ok(s, m, degree))
-        return mpk::set_error(MPK_ERR_ARG, "need 1 <= s <= %d, s <= m <= %d, 1 <= degree <= 4096", kMaxS, kMaxM);
+    if (!params_ok(s, m, degree) || (precond == MPK_PRECOND_CHEBYSHEV && degree < 1) ||
+        (precond == MPK_PRECOND_GS2 && degree > 16))
+        return mpk::set_error(MPK_ERR_ARG, "need 1 <= s <= %d, s <= m <= %d, 1 <= degree <= 4096 (0 <= gamma <= 16 "
+                                           "for GS2)", kMaxS, kMaxM);
+    if (precond == MPK_PRECOND_GS2 && !mpk::plan_split_lower(lo))
+        return mpk::set_error(MPK_ERR_ARG, "lo must be built with split_lower for the GS2 preconditioner");
     if (precond == MPK_PRECOND_CHEBYSHEV && !(lmin > 0.0))
         return mpk::set_error(MPK_ERR_ARG, "need 0 < lmin < lmax");
     if (!(lmax > lmin)) return mpk::set_error(MPK_ERR_ARG, "need lmin < lmax");
@@ -553,19 +584,19 @@ MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t prec
         S.degree = degree;
         S.theta = 0.5 * (lmax + lmin);
         S.delta = 0.5 * (lmax - lmin);
-        S.tcheb = std::cosh(degree * std::acosh(S.theta / S.delta));
+        S.tcheb = precond == MPK_PRECOND_CHEBYSHEV ? std::cosh(degree * std::acosh(S.theta / S.delta)) : 1.0;
         S.poly_flags = MPK_IO_PERMUTED | (flags & (MPK_PLAIN | MPK_STAGED));
         S.precond = precond;
         size_t pb = 0;
-        mpk_work_bytes(lo, MPK_CALL_POLY, degree, MPK_IO_PERMUTED, &pb);
+        ring_bytes(lo, degree, &pb);
         const bool permuted = flags & MPK_IO_PERMUTED;
         S.L = layout(n64, s, m, pb, permuted);
         S.base = (double*)work;
         S.st = (hipStream_t)stream;
         // s: the Chebyshev interpolant of 1/lambda at the zeros of T_d (its residual
         // polynomial is T_d((theta - lambda)/delta) / T_d(theta/delta))
-        S.coef.assign(degree, 0.0);
-        for (int j = 0; j < degree; ++j) {
+        S.coef.assign(std::max(degree, 1), 0.0);
+        for (int j = 0; precond == MPK_PRECOND_CHEBYSHEV && j < degree; ++j) {
             const double ang = 3.14159265358979323846 * (j + 0.5) / degree;
             const double inv = 1.0 / (S.theta + S.delta * std::cos(ang));
             for (int k = 0; k < degree; ++k) S.coef[k] += std::cos(k * ang) * inv;

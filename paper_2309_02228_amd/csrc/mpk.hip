@@ -88,15 +88,19 @@ struct Coefs {
     double theta, delta;
     int jk;             // KIND_JCHAIN: sub-powers per link; KIND_GS2: sub-powers per power
     double jc;          // KIND_JCHAIN: coefficient of (B - I)^k at the end of a link
+    int pinv;           // KIND_GS2: 1 = the chain applies P^{-1} only (a power closes with g_gamma)
 };
 
 // GS2 sub-power r of a power from the row's full sum sA = (A g)_i, its strictly lower
-// part sL = (L g)_i, its own previous value, g_0 and the diagonal entry d.
-__device__ __forceinline__ double gs2_value(double sA, double sL, double prev, double g0, double d, int r,
-                                            int gl) {
+// part sL = (L g)_i, its own previous value, g_0, the diagonal entry d and the power's
+// input w0.  A power closes with (A g_gamma - lam w0) / sig (lam = 0, sig = 1: A g_gamma;
+// Newton shifts of an s-step basis otherwise), or with g_gamma itself when pinv is set.
+__device__ __forceinline__ double gs2_value(double sA, double sL, double prev, double g0, double d, double w0, int r,
+                                            int gl, int pinv, double lam, double sig) {
     if (r == 0) return prev / d;
-    if (r < gl - 1) return g0 - sL / d;
-    return sA;
+    if (r < gl - 1 || pinv) return g0 - sL / d;
+    if (lam == 0.0 && sig == 1.0) return sA;
+    return fma(-lam, w0, sA) / sig;
 }
 
 __device__ __forceinline__ double load_coherent(const double* p) {
@@ -135,6 +139,7 @@ struct SpmvArgs {
     double c0;
     int gk;               // global power index of this launch
     const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link
+    const double* pow_in;   // KIND_GS2: the input w0 of the power
     double* link_out;       // KIND_JCHAIN: output column j - 1 receives w_j
     int64_t link_ld;
     Coefs C;              // entry 0 describes this power
@@ -236,7 +241,8 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
                 row_sums_gs2<VT>(a.P, a.in, off, width, lane, row, sA, sL, d);
             }
             if (row < a.P.n) {
-                const double y = gs2_value(sA, sL, a.in[row], a.link_in[row], d, r, a.C.jk);
+                const double y = gs2_value(sA, sL, a.in[row], a.link_in[row], d, a.pow_in[row], r, a.C.jk, a.C.pinv,
+                                           a.C.lam[0], a.C.sig[0]);
                 a.out[row] = y;
                 if (r == a.C.jk - 1) a.link_out[(int64_t)((a.gk - 1) / a.C.jk) * a.link_ld + row] = y;
             }
@@ -279,6 +285,7 @@ struct BlockArgs {
     int plain_gather;     // 1: powers written in this launch may be read with plain loads
     uint32_t epoch;
     const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link of y_{base+1}
+    const double* pow_in;   // KIND_GS2: the input w0 of the power of y_{base+1}
     double* link_out;       // KIND_JCHAIN: output column j - 1 receives w_j
     int64_t link_ld;
     Coefs C;
@@ -404,7 +411,7 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
         // the row's own previous value is needed by the shifted kinds, the
         // polynomial accumulator and the basis copy only
         const bool need_prev = KIND != KIND_MONO || POLY || a.copy0 != nullptr;
-        double prev[G], prev2[G], acc[G], link0[G];
+        double prev[G], prev2[G], acc[G], link0[G], w0[G];
         uint32_t lm[G];  // KIND_GS2: strictly lower slots of the row
         double dg[G];    // KIND_GS2: the row's diagonal entry
 #pragma unroll
@@ -412,6 +419,7 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
             const bool act = c[g] >= 0 && row[g] < a.P.n;
             prev[g] = (act && need_prev) ? a.in[row[g]] : 0.0;
             link0[g] = ((KIND == KIND_JCHAIN || KIND == KIND_GS2) && act) ? a.link_in[row[g]] : 0.0;
+            w0[g] = (KIND == KIND_GS2 && act) ? a.pow_in[row[g]] : 0.0;
             lm[g] = 0u;
             dg[g] = 1.0;
             if (KIND == KIND_GS2 && act) {
@@ -488,7 +496,9 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                 double y;
                 if constexpr (KIND == KIND_GS2) {
                     const int r = (a.base + kl) % a.C.jk;
-                    y = gs2_value(s[g], sl[g], prev[g], link0[g], dg[g], r, a.C.jk);
+                    if (r == 0) w0[g] = prev[g];  // the power's input
+                    y = gs2_value(s[g], sl[g], prev[g], link0[g], dg[g], w0[g], r, a.C.jk, a.C.pinv, a.C.lam[kl],
+                                  a.C.sig[kl]);
                     if (r == 0) link0[g] = y;  // g_0 of this power
                     if (r == a.C.jk - 1 && c[g] >= 0 && row[g] < a.P.n)
                         a.link_out[(int64_t)((a.base + kl) / a.C.jk) * a.link_ld + row[g]] = y;
@@ -534,6 +544,7 @@ struct StageTaskDev {
     const double* in;     // y_{gk-1}
     const double* prev2;  // y_{gk-2} (Chebyshev), null for gk < 2
     const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link
+    const double* pow_in;   // KIND_GS2: the input w0 of the power
     double* out;          // y_gk
     int c0, nchunks;      // chunks covering rows [r0, r1)
     int r0, r1;
@@ -576,7 +587,8 @@ __global__ __launch_bounds__(kBlockThreads) void stage_kernel(StageArgs a) {
                 row_sums_gs2<VT>(a.P, T.in, off, width, lane, row, sA, sL, d);
             }
             if (row >= T.r0 && row < T.r1) {
-                const double y = gs2_value(sA, sL, T.in[row], T.link_in[row], d, r, a.C.jk);
+                const double y = gs2_value(sA, sL, T.in[row], T.link_in[row], d, T.pow_in[row], r, a.C.jk, a.C.pinv,
+                                           a.C.lam[T.kl], a.C.sig[T.kl]);
                 T.out[row] = y;
                 if (r == a.C.jk - 1) a.link_out[(int64_t)((T.gk - 1) / a.C.jk) * a.link_ld + row] = y;
             }
@@ -943,7 +955,8 @@ struct PowerJob {
     double* acc = nullptr;
     std::vector<double> lam, sig, c;  // per global power k (index k-1); c[0] = c_0
     double theta = 0, delta = 1;
-    int jk = 1;                 // KIND_JCHAIN: sub-powers per link
+    int jk = 1;                 // KIND_JCHAIN: sub-powers per link; KIND_GS2: per power
+    int pinv = 0;               // KIND_GS2: apply P^{-1} only
     double jc = 0;              // KIND_JCHAIN: coefficient of (B - I)^k closing a link
     double* link_out = nullptr; // KIND_JCHAIN: w_j (j = 1..p / jk) at link_out + (j-1) * link_ld
     int64_t link_ld = 0;
@@ -959,9 +972,13 @@ const double* link_start(const PowerJob& j, int k) {
     if (j.kind == KIND_GS2) return t + 1 < k ? job_dest(j, t + 1) : job_vec(j, t);
     return t == 0 ? j.x : j.link_out + (int64_t)(t / j.jk - 1) * j.link_ld;
 }
+// KIND_GS2: the input of the power that holds sub-power k (x, or the ring slot of the
+// previous power's closing sub-power)
+const double* power_start(const PowerJob& j, int k) { return job_vec(j, (k - 1) / j.jk * j.jk); }
 void set_chain(const PowerJob& j, Coefs& C) {
     C.jk = j.jk;
     C.jc = j.jc;
+    C.pinv = j.pinv;
 }
 
 const std::vector<mpk::StageTask>& schedule(mpk_plan_t p, int q) {
@@ -997,6 +1014,7 @@ mpk_status run_staged(mpk_plan_t p, hipStream_t st, const PowerJob& j) {
                 d.in = job_vec(j, gk - 1);
                 d.prev2 = (j.kind == KIND_CHEB && gk >= 2) ? job_vec(j, gk - 2) : nullptr;
                 d.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, gk) : nullptr;
+                d.pow_in = j.kind == KIND_GS2 ? power_start(j, gk) : nullptr;
                 d.out = job_dest(j, gk);
                 d.r0 = T.row_begin;
                 d.r1 = T.row_end;
@@ -1035,6 +1053,7 @@ mpk_status plain_power(mpk_plan_t p, hipStream_t st, const PowerJob& j, int k) {
     a.C.delta = j.delta;
     set_chain(j, a.C);
     a.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, k) : nullptr;
+    a.pow_in = j.kind == KIND_GS2 ? power_start(j, k) : nullptr;
     a.link_out = j.link_out;
     a.link_ld = j.link_ld;
     if (k == 1 && j.copy0) {
@@ -1098,6 +1117,7 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
         a.C.delta = j.delta;
         set_chain(j, a.C);
         a.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, base + 1) : nullptr;
+        a.pow_in = j.kind == KIND_GS2 ? power_start(j, base + 1) : nullptr;
         a.link_out = j.link_out;
         a.link_ld = j.link_ld;
         mpk_status s = launch_block(p, st, j.kind, j.poly, a);
@@ -1122,6 +1142,10 @@ mpk_status mpk::set_error(mpk_status s, const char* fmt, ...) {
 mpk_status mpk::plan_uploaded(mpk_plan_t p) { return check_uploaded(p); }
 
 int mpk::plan_column_scaling(mpk_plan_t p) { return p ? p->column_scaling : MPK_SCALE_NONE; }
+
+bool mpk::plan_split_lower(mpk_plan_t p) { return p && p->H.split_lower; }
+
+int mpk::plan_p_block(mpk_plan_t p) { return p ? p->H.p_block : 0; }
 
 mpk_status mpk::plan_diagonal(mpk_plan_t p, double* out, void* stream) {
     mpk_status s = check_uploaded(p);
@@ -1803,20 +1827,42 @@ MPK_API mpk_status mpk_gs2_apply(mpk_plan_t p, int32_t gamma, const double* x, d
         yout = xp + ld;
         yld = ld;
     }
-    PowerJob j;
-    j.kind = KIND_GS2;
-    j.p = pw * (gamma + 2);
-    j.x = xin;
-    j.out0 = w;
-    j.ld = ld;
-    j.mod = ring;
-    j.jk = gamma + 2;
-    j.link_out = yout;
-    j.link_ld = yld;
-    s = run_powers(p, st, j, flags & MPK_PLAIN, flags & MPK_STAGED);
+    s = mpk::gs2_chain(p, gamma, xin, yout, yld, pw, nullptr, nullptr, 0, flags, w, work_bytes, stream);
     if (s != MPK_OK) return s;
     if (!permuted) s = permute_vecs(p, st, yout, ld, Y, ldy, pw, 1);
     return s;
+}
+
+mpk_status mpk::gs2_chain(mpk_plan_t p, int gamma, const double* x, double* Y, int64_t ldy, int pw,
+                          const double* lam, const double* sig, int pinv, uint32_t flags, void* work,
+                          size_t work_bytes, void* stream) {
+    // x and Y in level order; work holds the ring of p_block + gamma + 2 vectors
+    const int32_t n = p->H.n;
+    const int64_t ld = (n + 31) / 32 * 32;
+    const int ring = p->H.p_block + gamma + 2;
+    if (work_bytes < (size_t)ring * ld * 8) return fail(MPK_ERR_ARG, "work buffer too small for the GS2 ring");
+    if (n == 0) return MPK_OK;
+    const int gl = gamma + (pinv ? 1 : 2);
+    PowerJob j;
+    j.kind = KIND_GS2;
+    j.p = pw * gl;
+    j.x = x;
+    j.out0 = (double*)work;
+    j.ld = ld;
+    j.mod = ring;
+    j.jk = gl;
+    j.pinv = pinv;
+    j.link_out = Y;
+    j.link_ld = ldy;
+    if (lam || sig) {  // Newton shifts on the closing sub-power of each power
+        j.lam.assign((size_t)j.p, 0.0);
+        j.sig.assign((size_t)j.p, 1.0);
+        for (int q = 0; q < pw; ++q) {
+            j.lam[(size_t)(q + 1) * gl - 1] = lam ? lam[q] : 0.0;
+            j.sig[(size_t)(q + 1) * gl - 1] = sig ? sig[q] : 1.0;
+        }
+    }
+    return run_powers(p, (hipStream_t)stream, j, flags & MPK_PLAIN, flags & MPK_STAGED);
 }
 
 MPK_API mpk_status mpk_permute(mpk_plan_t p, const double* in, double* out, int32_t direction, void* stream) {

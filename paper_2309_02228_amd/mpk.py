@@ -19,7 +19,7 @@ MPK_STAGED = 4
 MPK_LAST_POWER = 8  # server applies: return y_p only
 VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}  # bf16: BF16 values with a per-row FP32 scale
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
-PRECONDS = {"chebyshev": 0, "none": 1, "jacobi": 2}  # right preconditioners of sstep_gmres
+PRECONDS = {"chebyshev": 0, "none": 1, "jacobi": 2, "gs2": 3}  # right preconditioners of sstep_gmres
 CALL_APPLY, CALL_POLY, CALL_SSTEP, CALL_SOLVE = 0, 1, 2, 3
 
 STATUS = {0: "MPK_OK", -1: "MPK_ERR_ARG", -2: "MPK_ERR_CSR", -3: "MPK_ERR_NOMEM",

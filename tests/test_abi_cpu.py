@@ -271,7 +271,7 @@ def test_sstep_gmres_argument_errors_without_gpu():
     assert lib.mpk_sstep_gmres_work_bytes(hi._h, 17, 32, 8, 1, ctypes.byref(nb)) == -1  # s > 16
     assert lib.mpk_sstep_gmres_work_bytes(hi._h, 8, 4, 8, 1, ctypes.byref(nb)) == -1    # m < s
     assert lib.mpk_sstep_gmres_work_bytes(hi._h, 8, 257, 8, 1, ctypes.byref(nb)) == -1  # m > 256
-    assert lib.mpk_sstep_gmres_work_bytes(hi._h, 8, 32, 0, 1, ctypes.byref(nb)) == -1   # d < 1
+    assert lib.mpk_sstep_gmres_work_bytes(hi._h, 8, 32, -1, 1, ctypes.byref(nb)) == -1  # d < 0 (0 is gamma = 0 of GS2)
     need = nb.value
     fake = ctypes.c_void_p(1 << 20)  # never dereferenced: every call below fails first
 

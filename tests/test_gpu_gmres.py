@@ -262,3 +262,60 @@ def test_preconditioner_plan_forms_are_checked():
     # a nonpositive lmin is allowed without the Chebyshev preconditioner
     x, it, cy, rel = hi.sstep_gmres(hi, b, 4, 8, 1, -1.0, lmax, tol=1e-10, max_cycles=40, precond="none")
     assert rel <= 1e-10
+
+
+# ------------------------------------------------------------ GS2 preconditioner (R21, R22)
+def dominant_nonsym(n, seed):
+    A = S.random_pattern(n, 6, seed, symmetric=False)
+    rp, c, v = A.rowptr, A.col, A.val.copy()
+    for i in range(n):
+        seg = slice(rp[i], rp[i + 1])
+        d = np.nonzero(c[seg] == i)[0]
+        v[rp[i] + d[0]] = 1.0 + np.abs(v[seg]).sum()
+    return S.CSR(n, rp, c, v)
+
+
+@pytest.mark.parametrize("gamma", [0, 1, 2])
+@pytest.mark.parametrize("values", ["f64", "f32"])
+@pytest.mark.parametrize("s,m", [(1, 8), (4, 8), (8, 8)])
+def test_gs2_fixed_cycle_matches_oracle(gamma, values, s, m):
+    # diagonally dominant, so A P^{-1} has its spectrum near 1 and the blocks are well
+    # conditioned; each block's basis is one GS2 chain of s powers
+    A = dominant_nonsym(3000, 8)
+    b = S.uniform_vector(A.n, 3)
+    hi = Plan.from_csr(A, p_block=8).upload(DEV)
+    lo = Plan.from_csr(A, p_block=8, values=values, split_lower=True).upload(DEV)
+    x, it, cy, rel = solve(hi, lo, b, s, m, gamma, 0.3, 1.7, 0.0, 1, precond="gs2")
+    xo, hist, ito = O.sstep_gmres_precond(A, b, np.zeros(A.n), s, m, "gs2", 0.3, 1.7, 0.0, 1,
+                                          values=None if values == "f64" else np.float32, gamma=gamma)
+    assert it == ito == m and cy == 1
+    assert np.linalg.norm(x - xo) <= BLOCK_BASIS_RTOL * np.linalg.norm(xo)
+
+
+@pytest.mark.parametrize("gamma", [1, 2])
+def test_gs2_gmres_solves_laplacian_like_oracle(gamma):
+    dims = (37, 29)
+    A = S.laplacian_2d(*dims)
+    b = S.uniform_vector(A.n, 3)
+    hi = Plan.from_csr(A, p_block=8).upload(DEV)
+    lo = Plan.from_csr(A, p_block=8, split_lower=True).upload(DEV)
+    x, it, cy, rel = solve(hi, lo, b, 8, 64, gamma, 0.002, 2.0, 1e-10, 40, precond="gs2")
+    xo, hist, ito = O.sstep_gmres_precond(A, b, np.zeros(A.n), 8, 64, "gs2", 0.002, 2.0, 1e-10, 40, gamma=gamma)
+    lmin, lmax = lap_bounds(dims)
+    assert rel <= 1e-10 and abs(cy - (len(hist) - 1)) <= 1
+    assert np.linalg.norm(b - O.spmv(A, x)) <= 1.0000001e-10 * np.linalg.norm(b)
+    assert np.linalg.norm(x - xo) <= 2e-10 * (lmax / lmin) * np.linalg.norm(xo)
+    xp, ip, cp, rp = solve(hi, lo, b, 8, 64, gamma, 0.002, 2.0, 1e-10, 40, precond="gs2", plain=True)
+    xs, is_, cs, rs = solve(hi, lo, b, 8, 64, gamma, 0.002, 2.0, 1e-10, 40, precond="gs2", staged=True)
+    assert np.array_equal(x, xp) and np.array_equal(x, xs) and it == ip == is_
+
+
+def test_gs2_gmres_needs_a_split_plan():
+    A = S.laplacian_2d(9, 7)
+    b = torch.tensor(S.uniform_vector(A.n, 2), device=DEV)
+    hi = Plan.from_csr(A).upload(DEV)
+    with pytest.raises(MPKError, match="MPK_ERR_ARG"):
+        hi.sstep_gmres(hi, b, 4, 8, 1, 0.01, 2.0, precond="gs2")
+    split = Plan.from_csr(A, split_lower=True).upload(DEV)
+    with pytest.raises(MPKError, match="MPK_ERR_ARG"):
+        hi.sstep_gmres(split, b, 4, 8, 17, 0.01, 2.0, precond="gs2")  # gamma > 16
