@@ -677,16 +677,20 @@ def main():
         # blocked against plain launches; time per 1000 basis vectors
         fixed = {}
         jac8 = Plan.from_csr(A, p_block=8, column_scaling="jacobi").upload(dev)
-        for name, lo_, lmin_, lmax_ in (("none", hi8, lmin, lmax), ("jacobi", jac8, lmin / 6, lmax / 6)):
+        gs8 = Plan.from_csr(A, p_block=8, split_lower=True).upload(dev)
+        gwork = torch.empty(gs8.gmres_work_bytes(8, 64, 1) // 8 + 64, dtype=torch.float64, device=dev)
+        for name, lo_, lmin_, lmax_, deg_, wk_ in (("none", hi8, lmin, lmax, 1, work),
+                                                    ("jacobi", jac8, lmin / 6, lmax / 6, 1, work),
+                                                    ("gs2", gs8, 0.002, 2.0, 1, gwork)):
             t = {}
             for plain_ in (False, True):
-                hi8.sstep_gmres(lo_, bvec, 8, 64, 1, lmin_, lmax_, tol=0.0, max_cycles=2, plain=plain_, work=work,
+                hi8.sstep_gmres(lo_, bvec, 8, 64, deg_, lmin_, lmax_, tol=0.0, max_cycles=2, plain=plain_, work=wk_,
                                 precond=name)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
                 for _ in range(3):
-                    res = hi8.sstep_gmres(lo_, bvec, 8, 64, 1, lmin_, lmax_, tol=0.0, max_cycles=2, plain=plain_,
-                                          work=work, precond=name)
+                    res = hi8.sstep_gmres(lo_, bvec, 8, 64, deg_, lmin_, lmax_, tol=0.0, max_cycles=2, plain=plain_,
+                                          work=wk_, precond=name)
                 torch.cuda.synchronize()
                 t[plain_] = (time.perf_counter() - t0) / 3 / res[1] * 1e3 * 1e3  # ms per 1000 vectors
             fixed[name] = {"blocked_ms_per_1000_vectors": round(t[False], 2),
@@ -694,11 +698,12 @@ def main():
         jac8.check()
         out["sstep_gmres_fixed_work"] = {
             "workload": f"s-step GMRES on the 3D 7-point Laplacian {g}^3, s = 8, m = 64, two cycles (128 basis "
-                        "vectors), FP64; without a preconditioner and with the fused Jacobi A D^-1; each block's "
-                        "basis is one MPK of 8 powers (blocked) or 8 SpMV launches (plain)", **fixed}
+                        "vectors), FP64; without a preconditioner, with the fused Jacobi A D^-1, and with GS2 "
+                        "(gamma = 1: 3 sub-powers per basis vector); each block's basis is one blocked chain of "
+                        "8 powers or one launch per (sub-)power (plain)", **fixed}
         log("s-step gmres: " + ", ".join(f"{k2}: {v['blocked_ms_per_1000_vectors']} ms/1000 vectors blocked, "
                                            f"{v['speedup']}x" for k2, v in fixed.items()))
-        del hi8, lo8, work, jac8
+        del hi8, lo8, work, jac8, gs8, gwork
     if not args.no_serve and args.only == "both":
         out["serving"] = serving_bench(args, A, plan, dev)
         sv = out["serving"]["by_kind"]["solve"]
