@@ -256,7 +256,6 @@ struct Solver {
     hipStream_t st;
     std::vector<double> coef;            // s(A) in T_k((A - theta I)/delta), k < degree
     std::vector<double> lam, sig;        // Newton shifts, Leja order, and scalings
-    std::vector<double> host_small;      // results of Gram products
     std::vector<double> host_c[4];       // coefficient staging (rewritten only after a sync)
 
     double* vec(size_t off) const { return base + off; }
