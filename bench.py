@@ -493,6 +493,12 @@ def main():
                               "speedup": round(tpl[0] / tb[0], 3)}
         out["p_sweep"] = sweep
         log("p sweep: " + ", ".join(f"p={k}: {v['speedup']}x" for k, v in sweep.items()))
+        # p_opt (Sec. 3): the tuner times every admissible block size for 8 powers
+        q_opt, t_opt = plan8.tune_block(x8, 8, Y=Y8)
+        plan8.set_block(0)
+        out["p_opt"] = {"p": 8, "q_opt": q_opt, "us_per_call": round(t_opt * 1e6, 1),
+                        "note": "mpk_tune_block over q = 1..min(8, deadlock bound) on the same plan"}
+        log(f"p_opt: q = {q_opt} for 8 powers ({t_opt * 1e6:.1f} us per call)")
         del plan8, Y8
     if args.only == "both" and not args.no_sweep:
         # Jacobi-preconditioned MPK (A P^{-1})^j x, j = 1..p, with k Jacobi sweeps: the plan

@@ -480,6 +480,24 @@ mpk_status mpk_gs2_apply(mpk_plan_t plan, int32_t gamma, const double* x, double
 mpk_status mpk_gs2_work_bytes(mpk_plan_t plan, int32_t gamma, int32_t p, uint32_t flags, size_t* bytes);
 
 /*
+ * p_opt of Sec. 3 (the powers per blocked launch, which the paper tunes over
+ * 1..8 per matrix and machine).  mpk_set_block caps the powers per blocked
+ * launch of every later call on the plan at q (1..15; 0 removes the cap; the
+ * deadlock bound of the plan still applies).  mpk_tune_block times
+ * mpk_apply(x, Y, ldy, p, MPK_IO_PERMUTED) on `stream` for each admissible
+ * q = 1..min(p, bound) (one warm-up and three timed calls each, HIP events),
+ * keeps the fastest as the plan's cap and returns it in *q_out and its time
+ * per call in *seconds_out (may be NULL).  x and Y (device, perm space, Y of
+ * p*ldy) are the caller's buffers; Y is overwritten.  Every q gives bitwise
+ * identical powers, so tuning changes time only.  Synchronises `stream`.
+ * Errors: MPK_ERR_ARG (q or p out of range, ldy < n, null pointers),
+ * MPK_ERR_STATE, MPK_ERR_HIP, MPK_ERR_DEVICE.
+ */
+mpk_status mpk_set_block(mpk_plan_t plan, int32_t q);
+mpk_status mpk_tune_block(mpk_plan_t plan, int32_t p, const double* x, double* Y, int64_t ldy, void* stream,
+                          int32_t* q_out, double* seconds_out);
+
+/*
  * Permutes a device vector into the plan's level order, x_perm[i] = x[perm[i]]
  * (direction 0), or back, x[perm[i]] = x_perm[i] (direction 1).  in and out
  * must not alias.

@@ -791,6 +791,7 @@ struct mpk_plan_s {
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
     int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
+    int q_cap = 0;                                   // powers per blocked launch at most (0: none)
     std::vector<std::vector<mpk::StageTask>> sched;  // wavefront schedule per q (lazy, under mu)
     std::mutex mu;
 };
@@ -1070,14 +1071,14 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
     // admits only one power per launch (levels too wide for the resident waves)
     // every block is such a block: the plain kernel is faster there, and both
     // give bitwise-equal results.
-    if (plain || p->q_eff[j.kind][j.poly] <= 1) {
+    const int qe = p->q_cap > 0 ? std::min(p->q_eff[j.kind][j.poly], p->q_cap) : p->q_eff[j.kind][j.poly];
+    if (plain || qe <= 1) {
         for (int k = 1; k <= j.p; ++k) {
             mpk_status s = plain_power(p, st, j, k);
             if (s != MPK_OK) return s;
         }
         return MPK_OK;
     }
-    const int qe = p->q_eff[j.kind][j.poly];
     for (int base = 0; base < j.p; base += qe) {
         const int q = std::min(qe, j.p - base);
         if (q == 1) {  // a one-power block (p = 1, or the remainder)
@@ -1863,6 +1864,58 @@ mpk_status mpk::gs2_chain(mpk_plan_t p, int gamma, const double* x, double* Y, i
         }
     }
     return run_powers(p, (hipStream_t)stream, j, flags & MPK_PLAIN, flags & MPK_STAGED);
+}
+
+MPK_API mpk_status mpk_set_block(mpk_plan_t p, int32_t q) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (q < 0 || q > mpk::kMaxBlock) return fail(MPK_ERR_ARG, "q must be in 0..%d", mpk::kMaxBlock);
+    p->q_cap = q;
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_tune_block(mpk_plan_t p, int32_t pw, const double* x, double* Y, int64_t ldy, void* stream,
+                                  int32_t* q_out, double* seconds_out) {
+    if (!p || !q_out) return fail(MPK_ERR_ARG, "null argument");
+    if (pw < 1) return fail(MPK_ERR_ARG, "p must be >= 1 (got %d)", pw);
+    if (ldy < p->H.n) return fail(MPK_ERR_ARG, "ldy must be >= n");
+    if (p->H.n > 0 && (!x || !Y)) return fail(MPK_ERR_ARG, "x or Y is null");
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const int qmax = std::min<int>(pw, p->q_eff[KIND_MONO][0]);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIP_TRY(hipEventCreate(&e0));
+    hipError_t he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        hipEventDestroy(e0);
+        return fail(MPK_ERR_HIP, "event: %s", hipGetErrorString(he));
+    }
+    int best = 1;
+    double best_t = 0.0;
+    const int saved = p->q_cap;
+    for (int q = 1; q <= std::max(qmax, 1) && s == MPK_OK; ++q) {
+        p->q_cap = q;
+        s = mpk_apply(p, x, Y, ldy, pw, MPK_IO_PERMUTED, nullptr, 0, st);  // warm-up
+        if (s == MPK_OK && (he = hipEventRecord(e0, st)) != hipSuccess) s = MPK_ERR_HIP;
+        for (int r = 0; r < 3 && s == MPK_OK; ++r) s = mpk_apply(p, x, Y, ldy, pw, MPK_IO_PERMUTED, nullptr, 0, st);
+        if (s == MPK_OK && (he = hipEventRecord(e1, st)) != hipSuccess) s = MPK_ERR_HIP;
+        if (s == MPK_OK && (he = hipEventSynchronize(e1)) != hipSuccess) s = MPK_ERR_HIP;
+        float ms = 0.0f;
+        if (s == MPK_OK && (he = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) s = MPK_ERR_HIP;
+        if (s == MPK_OK && (q == 1 || ms / 3.0 * 1e-3 < best_t)) {
+            best = q;
+            best_t = ms / 3.0 * 1e-3;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (s == MPK_ERR_HIP && he != hipSuccess) fail(MPK_ERR_HIP, "timing: %s", hipGetErrorString(he));
+    if (s == MPK_OK) s = mpk_check_device(p, stream);
+    p->q_cap = s == MPK_OK ? best : saved;
+    if (s != MPK_OK) return s;
+    *q_out = best;
+    if (seconds_out) *seconds_out = best_t;
+    return MPK_OK;
 }
 
 MPK_API mpk_status mpk_permute(mpk_plan_t p, const double* in, double* out, int32_t direction, void* stream) {

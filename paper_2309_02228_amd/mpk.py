@@ -35,7 +35,8 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_server_create", "mpk_server_submit_apply", "mpk_server_submit_solve",
            "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes",
            "mpk_server_submit_gmres", "mpk_jacobi_apply", "mpk_jacobi_work_bytes",
-           "mpk_gs2_apply", "mpk_gs2_work_bytes", "mpk_sstep_gmres_ex"]
+           "mpk_gs2_apply", "mpk_gs2_work_bytes", "mpk_sstep_gmres_ex",
+           "mpk_set_block", "mpk_tune_block"]
 
 
 class MPKError(RuntimeError):
@@ -106,6 +107,8 @@ def _load():
         "mpk_jacobi_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_gs2_apply": (I32, [P, I32, P, P, I64, I32, U32, P, SZ, P]),
         "mpk_gs2_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
+        "mpk_set_block": (I32, [P, I32]),
+        "mpk_tune_block": (I32, [P, I32, P, P, I64, P, pI32, ctypes.POINTER(ctypes.c_double)]),
         "mpk_server_submit_gmres": (I32, [P, P, P, P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double,
                                           ctypes.c_double, I32, U32, pI64]),
     }
@@ -384,6 +387,21 @@ class Plan:
                                        _dptr(work), work.numel() * work.element_size(), ctypes.byref(it),
                                        ctypes.byref(cy), ctypes.byref(rel), _stream(stream)))
         return x, it.value, cy.value, rel.value
+
+    def set_block(self, q):
+        """Caps the powers per blocked launch at q (0 removes the cap)."""
+        _check(_lib.mpk_set_block(self._h, int(q)))
+
+    def tune_block(self, x, p, Y=None, stream=None):
+        """Times the blocked MPK of p powers for each admissible block size on x (level
+        order), keeps the fastest as the plan's cap; returns (q, seconds per call)."""
+        import torch
+        if Y is None:
+            Y = torch.empty((p, self.n), dtype=torch.float64, device=x.device)
+        q, t = ctypes.c_int32(), ctypes.c_double()
+        _check(_lib.mpk_tune_block(self._h, int(p), _dptr(x), _dptr(Y), Y.stride(0), _stream(stream),
+                                   ctypes.byref(q), ctypes.byref(t)))
+        return q.value, t.value
 
     def permute(self, x, direction=0, out=None, stream=None):
         import torch

@@ -358,3 +358,18 @@ def test_gs2_split_plan_and_apply_argument_errors_without_gpu():
     assert lib.mpk_gs2_apply(split._h, 2, fake, fake, 64, 4, 1, ctypes.c_void_p((1 << 20) + 8), need,
                              None) == -1                                                  # misaligned
     assert lib.mpk_gs2_apply(split._h, 2, fake, fake, 64, 4, 1, fake, need, None) == -6    # not uploaded
+
+
+def test_block_cap_and_tuner_argument_errors_without_gpu():
+    lib = M.lib()
+    plan = M.Plan.from_csr(S.laplacian_2d(8))
+    assert lib.mpk_set_block(plan._h, 4) == 0 and lib.mpk_set_block(plan._h, 0) == 0
+    assert lib.mpk_set_block(plan._h, -1) == -1 and lib.mpk_set_block(plan._h, 16) == -1
+    assert lib.mpk_set_block(None, 2) == -1
+    q, t = ctypes.c_int32(), ctypes.c_double()
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.mpk_tune_block(plan._h, 0, fake, fake, 64, None, ctypes.byref(q), None) == -1   # p < 1
+    assert lib.mpk_tune_block(plan._h, 4, fake, fake, 63, None, ctypes.byref(q), None) == -1   # ldy < n
+    assert lib.mpk_tune_block(plan._h, 4, None, fake, 64, None, ctypes.byref(q), None) == -1   # null x
+    assert lib.mpk_tune_block(plan._h, 4, fake, fake, 64, None, None, None) == -1              # null q_out
+    assert lib.mpk_tune_block(plan._h, 4, fake, fake, 64, None, ctypes.byref(q), ctypes.byref(t)) == -6
