@@ -490,6 +490,8 @@ mpk_status mpk_gs2_work_bytes(mpk_plan_t plan, int32_t gamma, int32_t p, uint32_
  * per call in *seconds_out (may be NULL).  x and Y (device, perm space, Y of
  * p*ldy) are the caller's buffers; Y is overwritten.  Every q gives bitwise
  * identical powers, so tuning changes time only.  Synchronises `stream`.
+ * Both change the plan's state: they must not overlap other calls on the
+ * same plan (unlike the compute calls, which may overlap on several streams).
  * Errors: MPK_ERR_ARG (q or p out of range, ldy < n, null pointers),
  * MPK_ERR_STATE, MPK_ERR_HIP, MPK_ERR_DEVICE.
  */
