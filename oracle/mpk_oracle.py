@@ -463,11 +463,14 @@ def interval_shifts(s, lo, hi):
     return leja_order(c + h * np.cos(np.pi * (2 * i + 1) / (2 * s))), np.full(s, 0.5 * h)
 
 
-def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, values=None, gamma=1):
+def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, values=None, gamma=1, ksweeps=1):
     """Reading R22: s-step GMRES (Alg. 3a/3c) without a preconditioner (M = A, x = x0 + Q y),
     with the diagonal (one-sweep Jacobi) preconditioner from the right (M = A D^{-1},
     x = x0 + D^{-1} Q y, Sec. 5.1), or with the GS2 preconditioner of gs2_precondition
-    (M = A P^{-1}, x = x0 + P^{-1} Q y, ``gamma`` inner sweeps); [lmin, lmax] holds the
+    (M = A P^{-1}, x = x0 + P^{-1} Q y, ``gamma`` inner sweeps); with ``ksweeps`` > 1 the
+    Jacobi preconditioner is k sweeps (R20), applied through B = A D^{-1} whose diagonal is
+    one: M = jacobi_mpk(B) = I - (I - B)^k and x = x0 + D^{-1} jacobi_precondition(B, Q y).
+    [lmin, lmax] holds the
     spectrum of M, the shifts are those of interval_shifts, and the cycle is sstep_cycle.
     With ``values`` the basis and the preconditioner use the rounded matrix.
     Returns (x, history, iters)."""
@@ -483,6 +486,9 @@ def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, va
     if precond == "gs2":
         def apply_M(w):
             return spmv(Mlo, gs2_precondition(Mlo, w, gamma))
+    elif precond == "jacobi" and ksweeps > 1:
+        def apply_M(w):
+            return jacobi_mpk(Mlo, w, 1, ksweeps)[0]
     else:
         def apply_M(w):
             return spmv(Mlo, w)
@@ -504,6 +510,8 @@ def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, va
             z = z + y[j] * Q[j]
         if precond == "gs2":
             z = gs2_precondition(Mlo, z, gamma)
+        elif precond == "jacobi" and ksweeps > 1:
+            z = jacobi_precondition(Mlo, z, ksweeps)
         x = x + (z / d if d is not None else z)
     return x, hist, iters
 

@@ -339,3 +339,25 @@ def test_gs2_cycle_equals_textbook_gmres(gamma, s, m):
     x_ref = P @ textbook_gmres_cycle(M, b, m)
     assert iters == m
     np.testing.assert_allclose(x1, x_ref, rtol=0, atol=1e-9 * np.abs(x_ref).max())
+
+
+@pytest.mark.parametrize("k", [2, 3])
+@pytest.mark.parametrize("s,m", [(1, 9), (4, 12)])
+def test_jacobi_k_sweeps_cycle_equals_textbook_gmres(k, s, m):
+    # P^{-1} = sum_{i<k} (I - D^{-1} A)^i D^{-1} built densely (the paper's Jacobi iteration
+    # from zero); one cycle equals textbook GMRES on M = A P^{-1}, mapped back by P^{-1}
+    A = S.random_pattern(50, 5, 23, symmetric=False)
+    Ad = dense(A)
+    Ad[np.arange(50), np.arange(50)] = 1.0 + np.abs(Ad).sum(axis=1)
+    A = S.from_dense(Ad)
+    Dinv = np.diag(1.0 / np.diag(Ad))
+    N = np.eye(50) - Dinv @ Ad
+    P = sum(np.linalg.matrix_power(N, i) for i in range(k)) @ Dinv
+    M = Ad @ P
+    b = S.uniform_vector(50, 6)
+    ev = np.linalg.eigvals(M)
+    lo, hi = float(ev.real.min()) * 0.9, float(ev.real.max()) * 1.1
+    x1, hist, iters = O.sstep_gmres_precond(A, b, np.zeros(50), s, m, "jacobi", lo, hi, 0.0, 1, ksweeps=k)
+    x_ref = P @ textbook_gmres_cycle(M, b, m)
+    assert iters == m
+    np.testing.assert_allclose(x1, x_ref, rtol=0, atol=1e-9 * np.abs(x_ref).max())
