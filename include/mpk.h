@@ -390,7 +390,8 @@ mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, i
 /* preconditioners of mpk_sstep_gmres_ex */
 #define MPK_PRECOND_CHEBYSHEV 0 /* P^{-1} = s(A) of degree d - 1 (as mpk_sstep_gmres)     */
 #define MPK_PRECOND_NONE 1      /* M = A, x = x0 + Q y                                     */
-#define MPK_PRECOND_JACOBI 2    /* M = A D^{-1}, x = x0 + D^{-1} Q y (Sec. 5.1, fused)     */
+#define MPK_PRECOND_JACOBI 2    /* k = degree Jacobi sweeps: M = A P^{-1} (k = 1: A D^{-1},
+                                   fused), x = x0 + P^{-1} Q y (Sec. 5.1)                 */
 #define MPK_PRECOND_GS2 3       /* M = A P^{-1}, P^{-1} one GS2 iteration from zero with
                                    gamma = degree inner sweeps, x = x0 + P^{-1} Q y        */
 
@@ -409,8 +410,12 @@ mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, i
  * GS2 chain of s powers (s (gamma + 2) sub-powers blocked together, the Newton
  * shift applied as each power closes; see mpk_gs2_apply), [lmin, lmax] holds
  * the spectrum of A P^{-1}, and x = x0 + P^{-1} Q y with P^{-1} as a chain of
- * gamma + 1 sub-powers.  `degree` is unused by MPK_PRECOND_NONE and
- * MPK_PRECOND_JACOBI (pass 1); lmin may be <= 0 for all but Chebyshev.  Errors as mpk_sstep_gmres, plus MPK_ERR_ARG for an unknown
+ * gamma + 1 sub-powers.  With MPK_PRECOND_JACOBI, `degree` is the number k
+ * of Jacobi sweeps (1..64): k = 1 builds each block with sstep_basis on
+ * A D^{-1}; k > 1 with one Jacobi chain of s k sub-powers (mpk_jacobi_apply)
+ * with the shifts applied as each link closes, and x = x0 + D^{-1}
+ * sum_{i<k} (I - A D^{-1})^i Q y.  `degree` is unused by MPK_PRECOND_NONE
+ * (pass 1); lmin may be <= 0 for all but Chebyshev.  Errors as mpk_sstep_gmres, plus MPK_ERR_ARG for an unknown
  * preconditioner or a `lo` plan of the wrong form.
  */
 mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t precond, int32_t s, int32_t m, int32_t degree,

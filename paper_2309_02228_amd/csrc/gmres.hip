@@ -368,6 +368,10 @@ struct Solver {
                 mpk_status s_ = mpk::gs2_chain(lo, degree, Q(c), W(0), L.ld, sb, lam.data(), sig.data(), 0, poly_flags,
                                                vec(L.poly), L.poly_bytes, st);
                 if (s_ != MPK_OK) return s_;
+            } else if (precond == MPK_PRECOND_JACOBI && degree > 1) {  // one Jacobi chain of sb powers
+                mpk_status s_ = mpk::jacobi_chain(lo, degree, Q(c), W(0), L.ld, sb, lam.data(), sig.data(), poly_flags,
+                                                  vec(L.poly), L.poly_bytes, st);
+                if (s_ != MPK_OK) return s_;
             } else {
                 mpk_status s_ = sstep_basis(lo, sb, lam.data(), sig.data(), Q(c), V0(), L.ld, poly_flags, nullptr, 0,
                                             st);
@@ -473,8 +477,19 @@ struct Solver {
                         s_ = lincomb(x, 1.0, vec(L.t), 1, std::vector<double>{1.0}, 1, x, 3);
                         if (s_ != MPK_OK) return s_;
                     } else if (precond == MPK_PRECOND_JACOBI) {
-                        hipLaunchKernelGGL(add_div_kernel, dim3(grid_rows(n)), dim3(kThreads), 0, st, x,
-                                           (const double*)vec(L.z), (const double*)vec(L.diag), n);
+                        // P^{-1} z = D^{-1} sum_{i<k} (I - B)^i z: a Newton polynomial in B with all
+                        // shifts 1 and coefficients (-1)^i, then the diagonal
+                        const double* zk = vec(L.z);
+                        if (degree > 1) {
+                            std::vector<double> c(degree), ones(degree - 1, 1.0);
+                            for (int i = 0; i < degree; ++i) c[i] = (i % 2) ? -1.0 : 1.0;
+                            s_ = poly_apply(lo, MPK_POLY_NEWTON, degree - 1, c.data(), ones.data(), vec(L.z),
+                                            vec(L.t), poly_flags, vec(L.poly), L.poly_bytes, st);
+                            if (s_ != MPK_OK) return s_;
+                            zk = vec(L.t);
+                        }
+                        hipLaunchKernelGGL(add_div_kernel, dim3(grid_rows(n)), dim3(kThreads), 0, st, x, zk,
+                                           (const double*)vec(L.diag), n);
                         s_ = hip(hipGetLastError(), "update launch");
                         if (s_ != MPK_OK) return s_;
                     } else {
@@ -548,9 +563,10 @@ MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t prec
                                                ? "lo must hold A D^{-1} (column_scaling = MPK_SCALE_JACOBI)"
                                                : "lo must hold A (column_scaling = MPK_SCALE_NONE)");
     if (!params_ok(s, m, degree) || (precond == MPK_PRECOND_CHEBYSHEV && degree < 1) ||
-        (precond == MPK_PRECOND_GS2 && degree > 16))
+        (precond == MPK_PRECOND_GS2 && degree > 16) ||
+        (precond == MPK_PRECOND_JACOBI && (degree < 1 || degree > 64)))
         return mpk::set_error(MPK_ERR_ARG, "need 1 <= s <= %d, s <= m <= %d, 1 <= degree <= 4096 (0 <= gamma <= 16 "
-                                           "for GS2)", kMaxS, kMaxM);
+                                           "for GS2, 1 <= k <= 64 for Jacobi)", kMaxS, kMaxM);
     if (precond == MPK_PRECOND_GS2 && !mpk::plan_split_lower(lo))
         return mpk::set_error(MPK_ERR_ARG, "lo must be built with split_lower for the GS2 preconditioner");
     if (precond == MPK_PRECOND_CHEBYSHEV && !(lmin > 0.0))

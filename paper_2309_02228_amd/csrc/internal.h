@@ -20,6 +20,12 @@ int plan_p_block(mpk_plan_t p);
 int plan_column_scaling(mpk_plan_t p);
 // out (device, n, level order) = the stored diagonal of the plan's matrix, on `stream`.
 mpk_status plan_diagonal(mpk_plan_t p, double* out, void* stream);
+// The Jacobi chain in level order (plan holding A D^{-1}): Y[(q-1) ldy + i] receives power
+// q = 1..p of x under A P^{-1} = I - (I - B)^k, each link closing with (A P^{-1} w - lam_q w)
+// / sig_q (lam, sig: host arrays of p, or NULL for 0 and 1).  work: the ring of p_block + 2
+// vectors of n doubles.
+mpk_status jacobi_chain(mpk_plan_t p, int k, const double* x, double* Y, int64_t ldy, int pw, const double* lam,
+                        const double* sig, uint32_t flags, void* work, size_t work_bytes, void* stream);
 // The GS2 chain in level order (plan built with split_lower): Y[(q-1) ldy + i] receives
 // power q = 1..p of x, each power gamma + 2 sub-powers closing with (A g_gamma - lam_q w)
 // / sig_q (lam, sig: host arrays of p, or NULL for 0 and 1), or, with pinv, gamma + 1

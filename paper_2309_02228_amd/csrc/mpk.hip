@@ -122,7 +122,10 @@ __device__ __forceinline__ double finish(double s, double prev, double prev2, do
     if (KIND == KIND_NEWTON) return fma(-C.lam[kl], prev, s) / C.sig[kl];
     if (KIND == KIND_JCHAIN) {
         const double u = s - prev;
-        return gk % C.jk == 0 ? fma(C.jc, u, link0) : u;
+        if (gk % C.jk != 0) return u;
+        const double w = fma(C.jc, u, link0);  // w_j = A P^{-1} w_{j-1}
+        // a Newton shift of an s-step basis: (A P^{-1} - lam) w_{j-1} / sig
+        return (C.lam[kl] == 0.0 && C.sig[kl] == 1.0) ? w : fma(-C.lam[kl], link0, w) / C.sig[kl];
     }
     const double t = fma(-C.theta, prev, s);
     return gk == 1 ? t / C.delta : (2.0 * t) / C.delta - prev2;
@@ -1756,19 +1759,7 @@ MPK_API mpk_status mpk_jacobi_apply(mpk_plan_t p, int32_t k, const double* x, do
     if (flags & MPK_IO_PERMUTED) {
         mpk_status s = check_uploaded(p);
         if (s != MPK_OK) return s;
-        if (p->H.n == 0) return MPK_OK;
-        PowerJob j;
-        j.kind = KIND_JCHAIN;
-        j.p = pw * k;
-        j.x = x;
-        j.out0 = (double*)work;  // ring of sub-powers
-        j.ld = p->H.n;
-        j.mod = poly_ring(p);
-        j.jk = k;
-        j.jc = cjk;
-        j.link_out = Y;
-        j.link_ld = ldy;
-        return run_powers(p, (hipStream_t)stream, j, flags & MPK_PLAIN, flags & MPK_STAGED);
+        return mpk::jacobi_chain(p, k, x, Y, ldy, pw, nullptr, nullptr, flags, work, work_bytes, stream);
     }
     // original row order: one Newton polynomial per power (all shifts 1, c_0 = 1,
     // c_k = -(-1)^k) through poly_apply, which permutes; the same arithmetic
@@ -1832,6 +1823,33 @@ MPK_API mpk_status mpk_gs2_apply(mpk_plan_t p, int32_t gamma, const double* x, d
     if (s != MPK_OK) return s;
     if (!permuted) s = permute_vecs(p, st, yout, ld, Y, ldy, pw, 1);
     return s;
+}
+
+mpk_status mpk::jacobi_chain(mpk_plan_t p, int k, const double* x, double* Y, int64_t ldy, int pw, const double* lam,
+                             const double* sig, uint32_t flags, void* work, size_t work_bytes, void* stream) {
+    const int32_t n = p->H.n;
+    if (work_bytes < (size_t)poly_ring(p) * n * 8) return fail(MPK_ERR_ARG, "work buffer too small for the ring");
+    if (n == 0) return MPK_OK;
+    PowerJob j;
+    j.kind = KIND_JCHAIN;
+    j.p = pw * k;
+    j.x = x;
+    j.out0 = (double*)work;  // ring of sub-powers
+    j.ld = n;
+    j.mod = poly_ring(p);
+    j.jk = k;
+    j.jc = (k % 2) ? 1.0 : -1.0;  // -(-1)^k
+    j.link_out = Y;
+    j.link_ld = ldy;
+    if (lam || sig) {  // Newton shifts where each link closes
+        j.lam.assign((size_t)j.p, 0.0);
+        j.sig.assign((size_t)j.p, 1.0);
+        for (int q = 0; q < pw; ++q) {
+            j.lam[(size_t)(q + 1) * k - 1] = lam ? lam[q] : 0.0;
+            j.sig[(size_t)(q + 1) * k - 1] = sig ? sig[q] : 1.0;
+        }
+    }
+    return run_powers(p, (hipStream_t)stream, j, flags & MPK_PLAIN, flags & MPK_STAGED);
 }
 
 mpk_status mpk::gs2_chain(mpk_plan_t p, int gamma, const double* x, double* Y, int64_t ldy, int pw,
