@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cstdio>
 #include <numeric>
+#include <thread>
 
 namespace mpk {
 
@@ -33,6 +34,28 @@ std::string validate_csr(int32_t n, const int32_t* rowptr, const int32_t* col) {
 
 namespace {
 
+// Threads for building host tables: the machine's hardware threads, at most 16.
+int host_threads() {
+    const unsigned h = std::thread::hardware_concurrency();
+    return (int)std::max(1u, std::min(h, 16u));
+}
+
+// Runs fn(i0, i1) over [0, n) cut into contiguous ranges whose bounds are
+// multiples of `align`, one per thread (one thread below 2^16 items).  The
+// ranges must write disjoint memory; results do not depend on the thread count.
+template <typename Fn>
+void parallel_ranges(int64_t n, int64_t align, Fn fn) {
+    const int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, n >> 16));
+    const int64_t per = ((n + nt - 1) / nt + align - 1) / align * align;
+    std::vector<std::thread> pool;
+    for (int t = 1; t < nt; ++t) {
+        const int64_t i0 = std::min(n, t * per), i1 = std::min(n, (t + 1) * per);
+        if (i0 < i1) pool.emplace_back(fn, i0, i1);
+    }
+    fn((int64_t)0, std::min(n, per));
+    for (auto& th : pool) th.join();
+}
+
 // Undirected graph of pattern(A) + pattern(A^T), self-loops dropped, each
 // neighbour list sorted and free of duplicates.
 void symmetric_pattern(int32_t n, const int32_t* rowptr, const int32_t* col,
@@ -53,16 +76,21 @@ void symmetric_pattern(int32_t n, const int32_t* rowptr, const int32_t* col,
                 tmp[fill[i]++] = col[e];
                 tmp[fill[col[e]]++] = i;
             }
+    // each row's neighbours sorted and without repeats, then packed
     ptr.assign(n + 1, 0);
-    adj.clear();
-    adj.reserve(tmp.size());
-    for (int32_t i = 0; i < n; ++i) {
-        auto b = tmp.begin() + cnt[i], e = tmp.begin() + cnt[i + 1];
-        std::sort(b, e);
-        auto u = std::unique(b, e);
-        adj.insert(adj.end(), b, u);
-        ptr[i + 1] = (int64_t)adj.size();
-    }
+    parallel_ranges(n, 1, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i) {
+            auto b = tmp.begin() + cnt[i], e = tmp.begin() + cnt[i + 1];
+            std::sort(b, e);
+            ptr[i + 1] = std::unique(b, e) - b;
+        }
+    });
+    for (int32_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
+    adj.resize(ptr[n]);
+    parallel_ranges(n, 1, [&](int64_t i0, int64_t i1) {
+        for (int64_t i = i0; i < i1; ++i)
+            std::copy(tmp.begin() + cnt[i], tmp.begin() + cnt[i] + (ptr[i + 1] - ptr[i]), adj.begin() + ptr[i]);
+    });
 }
 
 // Breadth-first search from `root`.  Fills dist for every reached vertex
@@ -105,12 +133,12 @@ void reset(std::vector<int32_t>& dist, const Bfs& b) {
 }
 
 // George-Liu pseudo-peripheral node of the component containing `start`.
+// `br` holds the search from `start` on entry and the search from the
+// returned node on exit.
 int32_t pseudo_peripheral(const std::vector<int64_t>& ptr, const std::vector<int32_t>& adj,
-                          int32_t start, std::vector<int32_t>& dist) {
-    Bfs br, bx;
+                          int32_t start, std::vector<int32_t>& dist, Bfs& br) {
+    Bfs bx;
     int32_t r = start;
-    bfs(ptr, adj, r, dist, br);
-    reset(dist, br);
     for (;;) {
         const int32_t lb = br.layer_ptr[br.layer_ptr.size() - 2];
         const int32_t le = br.layer_ptr.back();
@@ -157,13 +185,19 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
         bfs(ptr, adj, v, dist, comp);  // the component of the lowest unvisited row
         bool has_root = P.root_mode == 1 && dist[P.root] >= 0;
         reset(dist, comp);
-        int32_t r = has_root ? P.root : pseudo_peripheral(ptr, adj, v, dist);
-        bfs(ptr, adj, r, dist, lv);
+        int32_t r;
+        if (has_root) {
+            r = P.root;
+            bfs(ptr, adj, r, dist, lv);
+            reset(dist, lv);
+        } else {  // the component's search is the first step of the root search
+            std::swap(lv, comp);
+            r = pseudo_peripheral(ptr, adj, v, dist, lv);
+        }
         for (size_t d = 0; d + 1 < lv.layer_ptr.size(); ++d)
             for (int32_t t = lv.layer_ptr[d]; t < lv.layer_ptr[d + 1]; ++t)
                 P.level_of_row[lv.order[t]] = base + (int32_t)d;
-        reset(dist, lv);
-        for (int32_t u : comp.order) seen[u] = 1;
+        for (int32_t u : lv.order) seen[u] = 1;
         base += (int32_t)lv.layer_ptr.size() - 1;
         P.roots.push_back(r);
     }
@@ -206,9 +240,10 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
         P.lmask.assign((size_t)P.nchunks * kChunkRows, 0u);
         P.dslot.assign((size_t)P.nchunks * kChunkRows, 0);
     }
-    {
+    // rows write disjoint slots: threads take contiguous ranges of chunks
+    parallel_ranges(n, kChunkRows, [&](int64_t i0, int64_t i1) {
         std::vector<std::pair<int32_t, double>> row;
-        for (int32_t i = 0; i < n; ++i) {
+        for (int32_t i = (int32_t)i0; i < (int32_t)i1; ++i) {
             int32_t o = P.perm[i];
             row.clear();
             for (int32_t e = rowptr[o]; e < rowptr[o + 1]; ++e)
@@ -228,7 +263,7 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
                 }
             }
         }
-    }
+    });
     // register slots: the smallest supported width covering every chunk, capped
     P.reg_slots = P.max_width <= 4 ? 4 : P.max_width <= 7 ? 7 : P.max_width <= 8 ? 8
                 : P.max_width <= 16 ? 16 : 32;

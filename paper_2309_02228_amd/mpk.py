@@ -197,7 +197,8 @@ class Plan:
         return cls(A[0], A[1], A[2], A[3], **kw)
 
     def __del__(self):
-        if getattr(self, "_h", None):
+        # at interpreter exit the module's globals may already be gone
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.mpk_destroy(self._h)
             self._h = None
 
@@ -427,7 +428,8 @@ class Server:
         self._keep = {}  # ticket -> host arrays and plans the request uses
 
     def __del__(self):
-        self.close()
+        if _lib is not None:  # at interpreter exit the module's globals may already be gone
+            self.close()
 
     def close(self):
         if getattr(self, "_h", None):

@@ -84,6 +84,26 @@ def test_planner_bit_exact_to_oracle(name):
         assert plan.min_workers(q) == O.min_workers(ref["owner"], ref["deps"], G, q), q
 
 
+@pytest.mark.parametrize("name", ["lap3d_52", "rand_nonsym_300k"])
+def test_planner_threaded_sizes_bit_exact_to_oracle(name):
+    # large enough that the planner splits its table building over threads
+    # (2 and 4 ranges): the tables must not depend on that split
+    A = {"lap3d_52": lambda: S.laplacian_3d(52),
+         "rand_nonsym_300k": lambda: S.random_pattern(300000, 2.5, 5)}[name]()
+    assert A.n >= 2 << 16
+    plan = M.Plan.from_csr(A, p_block=4)
+    got = plan.levels()
+    ref = oracle_plan(A)
+    assert got["nlevels"] == ref["nl"]
+    assert np.array_equal(got["level_of_row"], ref["level"])
+    assert np.array_equal(got["perm"], ref["perm"])
+    assert np.array_equal(got["level_ptr"], ref["level_ptr"])
+    assert np.array_equal(plan.partition()["owner"], ref["owner"])
+    ptr, idx = plan.deps()
+    assert ptr.size == len(ref["deps"]) + 1
+    assert np.array_equal(idx, np.concatenate([np.asarray(d, dtype=idx.dtype) for d in ref["deps"]]))
+
+
 @pytest.mark.parametrize("G", [1, 2, 4])
 def test_planner_unit_bound_by_group(G):
     A = S.laplacian_3d(14, 12, 10)
