@@ -35,17 +35,19 @@ std::string validate_csr(int32_t n, const int32_t* rowptr, const int32_t* col) {
 namespace {
 
 // Threads for building host tables: the machine's hardware threads, at most 16.
+constexpr int64_t kRowGrain = 1 << 16;  // rows per thread at least
+
 int host_threads() {
     const unsigned h = std::thread::hardware_concurrency();
     return (int)std::max(1u, std::min(h, 16u));
 }
 
 // Runs fn(i0, i1) over [0, n) cut into contiguous ranges whose bounds are
-// multiples of `align`, one per thread (one thread below 2^16 items).  The
+// multiples of `align`, one per thread and at least `grain` items each.  The
 // ranges must write disjoint memory; results do not depend on the thread count.
 template <typename Fn>
-void parallel_ranges(int64_t n, int64_t align, Fn fn) {
-    const int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, n >> 16));
+void parallel_ranges(int64_t n, int64_t align, int64_t grain, Fn fn) {
+    const int nt = (int)std::min<int64_t>(host_threads(), std::max<int64_t>(1, n / grain));
     const int64_t per = ((n + nt - 1) / nt + align - 1) / align * align;
     std::vector<std::thread> pool;
     for (int t = 1; t < nt; ++t) {
@@ -78,7 +80,7 @@ void symmetric_pattern(int32_t n, const int32_t* rowptr, const int32_t* col,
             }
     // each row's neighbours sorted and without repeats, then packed
     ptr.assign(n + 1, 0);
-    parallel_ranges(n, 1, [&](int64_t i0, int64_t i1) {
+    parallel_ranges(n, 1, kRowGrain, [&](int64_t i0, int64_t i1) {
         for (int64_t i = i0; i < i1; ++i) {
             auto b = tmp.begin() + cnt[i], e = tmp.begin() + cnt[i + 1];
             std::sort(b, e);
@@ -87,7 +89,7 @@ void symmetric_pattern(int32_t n, const int32_t* rowptr, const int32_t* col,
     });
     for (int32_t i = 0; i < n; ++i) ptr[i + 1] += ptr[i];
     adj.resize(ptr[n]);
-    parallel_ranges(n, 1, [&](int64_t i0, int64_t i1) {
+    parallel_ranges(n, 1, kRowGrain, [&](int64_t i0, int64_t i1) {
         for (int64_t i = i0; i < i1; ++i)
             std::copy(tmp.begin() + cnt[i], tmp.begin() + cnt[i] + (ptr[i + 1] - ptr[i]), adj.begin() + ptr[i]);
     });
@@ -241,7 +243,7 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
         P.dslot.assign((size_t)P.nchunks * kChunkRows, 0);
     }
     // rows write disjoint slots: threads take contiguous ranges of chunks
-    parallel_ranges(n, kChunkRows, [&](int64_t i0, int64_t i1) {
+    parallel_ranges(n, kChunkRows, kRowGrain, [&](int64_t i0, int64_t i1) {
         std::vector<std::pair<int32_t, double>> row;
         for (int32_t i = (int32_t)i0; i < (int32_t)i1; ++i) {
             int32_t o = P.perm[i];
@@ -292,11 +294,12 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
     }
 
     // ---- dependency lists (R7) -----------------------------------------------
+    // two passes over ranges of chunks (lengths, then the sorted lists), each
+    // range with its own marks
     P.dep_ptr.assign(P.nchunks + 1, 0);
     P.dep_idx.clear();
     {
-        std::vector<int32_t> stamp(P.nchunks, -1), list;
-        for (int32_t c = 0; c < P.nchunks; ++c) {
+        auto chunk_list = [&](int32_t c, std::vector<int32_t>& stamp, std::vector<int32_t>& list) {
             list.clear();
             stamp[c] = c;  // never list the chunk itself
             for (int32_t i = c * kChunkRows; i < std::min(n, (c + 1) * kChunkRows); ++i) {
@@ -309,10 +312,24 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
                     }
                 }
             }
-            std::sort(list.begin(), list.end());
-            P.dep_idx.insert(P.dep_idx.end(), list.begin(), list.end());
-            P.dep_ptr[c + 1] = (int32_t)P.dep_idx.size();
-        }
+        };
+        parallel_ranges(P.nchunks, 1, kRowGrain / kChunkRows, [&](int64_t c0, int64_t c1) {
+            std::vector<int32_t> stamp(P.nchunks, -1), list;
+            for (int64_t c = c0; c < c1; ++c) {
+                chunk_list((int32_t)c, stamp, list);
+                P.dep_ptr[c + 1] = (int32_t)list.size();
+            }
+        });
+        for (int32_t c = 0; c < P.nchunks; ++c) P.dep_ptr[c + 1] += P.dep_ptr[c];
+        P.dep_idx.resize(P.dep_ptr[P.nchunks]);
+        parallel_ranges(P.nchunks, 1, kRowGrain / kChunkRows, [&](int64_t c0, int64_t c1) {
+            std::vector<int32_t> stamp(P.nchunks, -1), list;
+            for (int64_t c = c0; c < c1; ++c) {
+                chunk_list((int32_t)c, stamp, list);
+                std::sort(list.begin(), list.end());
+                std::copy(list.begin(), list.end(), P.dep_idx.begin() + P.dep_ptr[c]);
+            }
+        });
     }
 
     // ---- smallest deadlock-free worker count per block size q (R7) ----------
