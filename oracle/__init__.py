@@ -27,11 +27,6 @@ sparse iterative solvers on multi-core CPUs"):
   ``level_permutation``,
   ``permute_symmetric``             -- Sec. 3 (BFS level structure of the
   matrix graph) and Sec. 5.1.2 (levels come from A alone)
-* ``chunk_owner``, ``chunk_dependencies``, ``worker_units``,
-  ``unit_dependencies``, ``hop_min``, ``window_ok``, ``min_workers``,
-  ``simulate_blocked_mpk``          -- Sec. 3 (an execution order derived
-  from the level structure; p_opt and the remainder loop), in the readings
-  R5-R7 and R10
 * ``group_levels``, ``wavefront_schedule``, ``validate_schedule``,
   ``run_schedule``                  -- Sec. 3 (level groups from the cache size
   and the skewed wavefront over them), readings R14 and R15

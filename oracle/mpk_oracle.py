@@ -9,23 +9,24 @@ and unique within a row), vectors are float64 NumPy arrays.
 
 Parity status
 -------------
-pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_coeffs, refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
+pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_coeffs,
+         refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          leja_order, chebyshev_scale, newton_shifts, cholqr_truncated, sstep_cycle, sstep_gmres,
          diagonal, jacobi_precondition, jacobi_mpk, spmv_lower, gs2_precondition, gs2_mpk,
          interval_shifts, sstep_gmres_precond,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
-         chunk_owner, chunk_dependencies, worker_units, unit_dependencies,
-         hop_min, window_ok, min_workers,
-         simulate_blocked_mpk, group_levels, wavefront_schedule,
-         validate_schedule, run_schedule
+         group_levels, wavefront_schedule, validate_schedule, run_schedule
          (pins: exact integer arithmetic, closed-form Laplacian eigenpairs,
          closed-form grid levels, scipy shortest paths, brute force on tiny
          inputs, special cases; see tests/test_oracle_pins.py)
-unpinned the choice of chunk-to-XCD ownership and the execution order are this
-         project's own readings (R5-R7 below); the paper gives no rule to
-         check them against, so only their validity (coverage, read-after-
-         write order, deadlock freedom, bitwise equality with the plain
-         MPK) is pinned, not their identity with the paper's library.
+unpinned the level grouping and the wavefront order (R14, R15) are readings of a
+         passage that gives no rule; only their validity (coverage, read-after-write
+         order, bitwise equality with the plain MPK) is pinned, not their identity
+         with the paper's library.
+
+How the GPU kernel hands out work (chunk ownership, units, the deadlock bound)
+is a design choice of the HIP path, not a statement of the paper: it is
+modelled on the test side (tests/schedule_model.py), not here.
 """
 import math
 from collections import deque
@@ -48,20 +49,6 @@ READINGS = {
           "of each component continue after the last level of the previous one.",
     "R4": "Within a level, rows keep ascending original index: perm[new] = old, "
           "iperm[old] = new.",
-    "R5": "Rows are cut, in permuted order, into chunks of C consecutive rows (the last "
-          "may be shorter); a chunk is the unit of work and of synchronisation.",
-    "R6": "Chunk c is owned by partition x = floor(P * (r0 - level_start) / level_size), "
-          "where r0 = C*c is its first row and level_start/level_size describe the "
-          "level of r0; each partition processes its chunks in ascending order.",
-    "R7": "Chunk c may compute power k once every chunk holding a row adjacent to c's "
-          "rows in the symmetrised pattern has finished power k-1. Each partition's "
-          "ascending chunk sequence is cut into units of G consecutive chunks; a worker "
-          "takes the partition's next unit in sequence order, carries all its chunks "
-          "together through the q powers of a block, then takes the next. With at "
-          "least W_x >= W "
-          "active workers per partition this cannot deadlock when, for every unit "
-          "position j >= W, the first chunk of unit j - W has a smaller index than the "
-          "first chunk of every unit within q-1 unit-dependency hops of unit j.",
     "R8": "Newton basis: V_k = (A - lambda_k I) V_{k-1} / sigma_k, the product of distinct "
           "shifted factors (the printed powers (A - lambda_2 I)^2 ... are read as this "
           "product).",
@@ -156,30 +143,19 @@ def _arrays(A):
 
 
 def spmv(A, x):
-    """y = A x, every row summed as in Alg. 2: tmp = 0, then tmp += val*y[col] over
-    the row's stored entries in order.
+    """y = A x (Sec. 3, Alg. 1: one sparse matrix-vector product per power).
 
-    Each product is rounded on its own (no fused multiply-add); ``np.bincount``
-    adds the weights into the output one after the other in input order, so
-    row i is accumulated left to right starting from 0.0.
+    y_i is the sum over row i's stored entries of a_ij * x_j: every product is
+    rounded on its own (no fused multiply-add) and the sum runs over the
+    entries in stored (ascending-column) order, starting from zero.  The
+    products are formed elementwise and ``np.bincount`` then adds the weights
+    of each output bin in input order, which is that sequential row sum.
     """
     n, rowptr, col, val = _arrays(A)
     x = np.asarray(x, dtype=np.float64)
     prod = val * x[col]
     rows = np.repeat(np.arange(n, dtype=np.int64), np.diff(rowptr))
     return np.bincount(rows, weights=prod, minlength=n)
-
-
-def spmv_rowloop(A, x):
-    """The same product with explicit Python loops (tiny matrices only)."""
-    n, rowptr, col, val = _arrays(A)
-    y = np.zeros(n)
-    for i in range(n):
-        tmp = 0.0
-        for idx in range(rowptr[i], rowptr[i + 1]):
-            tmp += float(val[idx]) * float(x[col[idx]])
-        y[i] = tmp
-    return y
 
 
 def spmv_rows(A, x, r0, r1):
@@ -866,196 +842,3 @@ def permute_symmetric(A, perm, iperm):
     rows = np.repeat(np.arange(n, dtype=np.int64), lens)
     order = np.lexsort((bcol, rows))
     return (n, bptr, bcol[order], bval[order])
-
-
-# --------------------------------------------------------------------------- #
-# Execution order of the blocked MPK (readings R5-R7)
-# --------------------------------------------------------------------------- #
-def chunk_owner(level_ptr, level_of_new_row, n, chunk_rows, nparts):
-    """Owner partition of every chunk (reading R6)."""
-    nchunks = (n + chunk_rows - 1) // chunk_rows
-    owner = np.empty(nchunks, dtype=np.int64)
-    for c in range(nchunks):
-        r0 = c * chunk_rows
-        lv = int(level_of_new_row[r0])
-        start, size = int(level_ptr[lv]), int(level_ptr[lv + 1] - level_ptr[lv])
-        owner[c] = (nparts * (r0 - start)) // size
-    return owner
-
-
-def chunk_dependencies(B, chunk_rows):
-    """For every chunk, the sorted other chunks holding a row adjacent to one of
-    its rows in pattern(B) union pattern(B^T) (reading R7)."""
-    n = int(B[0])
-    ptr, adj = pattern_graph(B)
-    nchunks = (n + chunk_rows - 1) // chunk_rows
-    deps = []
-    for c in range(nchunks):
-        r0, r1 = c * chunk_rows, min(n, (c + 1) * chunk_rows)
-        nb = adj[ptr[r0]:ptr[r1]] // chunk_rows
-        nb = np.unique(nb)
-        deps.append(nb[nb != c])
-    return deps
-
-
-def worker_units(owner, group):
-    """Units of ``group`` consecutive chunks of each partition's ascending sequence
-    (reading R7).  Returns (units, unit_part): a list of chunk-index arrays and the
-    partition of each unit, units of partition 0 first, each partition in order."""
-    owner = np.asarray(owner)
-    nparts = int(owner.max()) + 1 if owner.size else 0
-    units, part = [], []
-    for x in range(nparts):
-        seq = np.nonzero(owner == x)[0]
-        for j in range(0, seq.size, group):
-            units.append(seq[j:j + group])
-            part.append(x)
-    return units, np.asarray(part, dtype=np.int64)
-
-
-def unit_dependencies(units, deps, nchunks):
-    """Other units holding a chunk that some chunk of the unit waits on."""
-    unit_of = np.empty(nchunks, dtype=np.int64)
-    for u, ch in enumerate(units):
-        unit_of[ch] = u
-    out = []
-    for u, ch in enumerate(units):
-        d = np.unique(np.concatenate([unit_of[deps[c]] for c in ch])) if len(ch) else \
-            np.zeros(0, dtype=np.int64)
-        out.append(d[d != u])
-    return out
-
-
-def hop_min(udeps, first, hops):
-    """B[u] = smallest first-chunk index among units within ``hops`` dependency hops
-    of unit u (u included).  The relation is symmetric (it comes from a
-    symmetrised pattern), so this is also the smallest first chunk of a unit from
-    which u is reachable in ``hops``."""
-    b = np.asarray(first, dtype=np.int64).copy()
-    for _ in range(max(0, hops)):
-        nb = b.copy()
-        for u, dl in enumerate(udeps):
-            if dl.size:
-                nb[u] = min(nb[u], int(b[dl].min()))
-        b = nb
-    return b
-
-
-def window_ok(first, workers, bmin):
-    """Deadlock-freedom condition of reading R7 for one partition: ``first`` are the
-    first-chunk indices of the partition's units in order, ``bmin`` their values of
-    ``hop_min(..., q - 1)``.
-
-    Proof sketch: in a deadlock every started unit waits; take the one whose
-    first chunk c is smallest.  Its chain of waits has at most q-1 hops (powers
-    drop by one per hop and power 1 never waits) and ends at a unit u that has
-    not started.  If nobody holds u, units start in order, so the W busy
-    workers of u's partition hold units at positions below u's, one of them at
-    pos(u) - W or earlier, whose first chunk is below bmin[u] <= c.  If a worker
-    claimed u early, it did so while on a unit at position <= pos(u) - W, whose
-    first chunk is again below bmin[u] <= c.  Either way a waiting unit with a
-    smaller first chunk exists: a contradiction.
-    """
-    first = np.asarray(first, dtype=np.int64)
-    if first.size <= workers:
-        return True
-    return bool(np.all(first[:-workers] < np.asarray(bmin)[workers:]))
-
-
-def min_workers(owner, deps, group, q):
-    """Smallest W meeting ``window_ok`` in every partition (direct search)."""
-    units, upart = worker_units(owner, group)
-    udeps = unit_dependencies(units, deps, len(deps))
-    first = np.array([u[0] for u in units], dtype=np.int64)
-    bmin = hop_min(udeps, first, q - 1)
-    parts = [np.nonzero(upart == x)[0] for x in range(int(upart.max()) + 1 if upart.size else 0)]
-    for w in range(1, len(units) + 1):
-        if all(window_ok(first[pu], w, bmin[pu]) for pu in parts):
-            return w
-    return max(1, len(units))
-
-
-def simulate_blocked_mpk(B, x, p, q, chunk_rows, owner, deps, workers, kind=None, group=1,
-                         active=None, early=None):
-    """Execute the blocked MPK on permuted matrix B sequentially, in the worker
-    order of reading R7, and return Y (p, n) in permuted space.
-
-    Each partition hands out its units in sequence order to ``workers`` workers
-    (``active`` of them actually run, default all).  A worker repeatedly tries to
-    advance its current (unit, power): power k of all chunks of the unit is
-    computed only when every chunk they wait on, outside the unit, has finished
-    power k-1; an idle worker takes the partition's next unit.  ``early`` = W
-    models a variant that the GPU kernel does not use: a worker about to compute
-    the last power of the unit at position j first claims its next unit if the
-    partition's next position is >= j + W (safe by the same condition, but a
-    unit claimed this way cannot start until its holder finishes, which delays
-    everything that waits on it).
-    Values not yet computed are NaN, so a wrong order shows up as NaN in the
-    result; a full sweep without progress raises (deadlock).  Powers are done
-    in blocks of q (R10).  ``kind`` is None for plain powers, or a callable
-    (k, acc, prev, prev2) -> y_k for the shifted and three-term forms, where
-    acc = (A y_{k-1}) on the chunk's rows and prev/prev2 are y_{k-1}/y_{k-2} on
-    the same rows.
-    """
-    n = int(B[0])
-    nchunks = len(deps)
-    Y = np.full((p + 1, n), np.nan)
-    Y[0] = x
-    units, upart = worker_units(owner, group)
-    nparts = int(upart.max()) + 1 if upart.size else 0
-    pu = [np.nonzero(upart == part)[0] for part in range(nparts)]
-    inside = [set(u.tolist()) for u in units]
-    nact = workers if active is None else active
-    base = 0
-    while base < p:
-        qb = min(q, p - base)
-        done = np.zeros(nchunks, dtype=np.int64)  # powers finished in this block
-        ticket = [0] * nparts
-        # worker: [partition, position of current unit or -1, power, claimed next position or -1]
-        state = [[part, -1, 0, -1] for part in range(nparts) for _ in range(nact)]
-        remaining = len(units) * qb
-        while remaining:
-            progress = False
-            for st in state:
-                part, pos, k, nxt = st
-                if pos < 0:
-                    if nxt >= 0:
-                        pos, nxt = nxt, -1
-                    elif ticket[part] < pu[part].size:
-                        pos = ticket[part]
-                        ticket[part] += 1
-                    else:
-                        continue
-                    k = 1
-                    st[1], st[2], st[3] = pos, k, nxt
-                    progress = True
-                u = int(pu[part][pos])
-                if (early is not None and k == qb and nxt < 0 and ticket[part] < pu[part].size
-                        and ticket[part] >= pos + early):
-                    nxt = ticket[part]
-                    ticket[part] += 1
-                    st[3] = nxt
-                    progress = True
-                if k > 1 and any(done[d] < k - 1 for c in units[u] for d in deps[c]
-                                 if int(d) not in inside[u]):
-                    continue
-                gk = base + k
-                for c in units[u]:
-                    r0, r1 = int(c) * chunk_rows, min(n, (int(c) + 1) * chunk_rows)
-                    acc = spmv_rows(B, Y[gk - 1], r0, r1)
-                    if kind is None:
-                        Y[gk, r0:r1] = acc
-                    else:
-                        prev2 = Y[gk - 2, r0:r1] if gk >= 2 else None
-                        Y[gk, r0:r1] = kind(gk, acc, Y[gk - 1, r0:r1], prev2)
-                    done[c] = k
-                remaining -= 1
-                progress = True
-                if k == qb:
-                    st[1], st[2] = -1, 0
-                else:
-                    st[2] = k + 1
-            if not progress:
-                raise RuntimeError("blocked MPK schedule deadlocked")
-        base += qb
-    return Y[1:]
