@@ -28,8 +28,9 @@
  *   - Calls on one plan may overlap on several streams and host threads:
  *     blocked (persistent) launches on one device are chained one after the
  *     other by the library, whatever stream or plan issues them, and all
- *     other launches use only caller buffers.  A device error raised by one
- *     call may be reported by mpk_check_device on another call of the plan.
+ *     other launches use only caller buffers.  A device error raised by a
+ *     call is reported by mpk_check_device for the stream that call ran on
+ *     (each stream has its own status on each plan, see mpk_check_device).
  *   - Indices are 0-based int32; n and nnz must be below 2^31.
  */
 #ifndef MPK_H
@@ -223,6 +224,28 @@ mpk_status mpk_get_deps(mpk_plan_t plan, int64_t* ndeps, int32_t* dep_ptr, int32
  * most half of the waves it launches.  1 <= q <= p_block.
  */
 mpk_status mpk_min_workers(mpk_plan_t plan, int32_t q, int32_t* workers_per_xcd);
+
+/* Operator kinds of mpk_block_powers. */
+#define MPK_OP_POWERS 0           /* mpk_apply (and mpk_jacobi_apply with k = 1)  */
+#define MPK_OP_POLY_MONOMIAL 1    /* poly_apply, MPK_POLY_MONOMIAL                */
+#define MPK_OP_POLY_NEWTON 2      /* poly_apply, MPK_POLY_NEWTON                  */
+#define MPK_OP_POLY_CHEBYSHEV 3   /* poly_apply, MPK_POLY_CHEBYSHEV (and the      */
+                                  /* Chebyshev preconditioner of the solvers)     */
+#define MPK_OP_NEWTON_BASIS 4     /* sstep_basis                                  */
+#define MPK_OP_JACOBI_CHAIN 5     /* mpk_jacobi_apply with k > 1                  */
+#define MPK_OP_GS2_CHAIN 6        /* mpk_gs2_apply                                */
+
+/*
+ * Powers (or sub-powers of a chain) per blocked launch that calls of operator
+ * kind `op` use on this uploaded plan: p_block lowered to the deadlock bound of
+ * the resident waves (Sec. 3 temporal blocking needs the matrix rows of a
+ * block of levels to stay on chip while q powers advance) and to the cap of
+ * mpk_set_block.  1 means those calls run one plain SpMV launch per power (no
+ * blocking engages).  A call also never uses more than the powers it asks for.
+ * Errors: MPK_ERR_ARG (null pointers, unknown op), MPK_ERR_STATE (not
+ * uploaded).
+ */
+mpk_status mpk_block_powers(mpk_plan_t plan, int32_t op, int32_t* q);
 
 /*
  * Binds caller-owned device memory (at least device_bytes from
@@ -513,13 +536,27 @@ mpk_status mpk_permute(mpk_plan_t plan, const double* in, double* out, int32_t d
                        void* stream);
 
 /*
- * Waits for `stream`, then reads the plan's device status word.  MPK_OK if
- * every blocked launch so far finished normally; MPK_ERR_DEVICE if a wave of
- * the blocked kernel gave up waiting (watchdog: a dependency not satisfied
- * within about a second, e.g. because the GPU could not keep every worker
- * resident); the message names the chunk and power.  Clears the word.
+ * Waits for `stream`, then reads the plan's device status for that stream:
+ * every stream that launches the blocked kernel on a plan gets its own status
+ * slot (64 per plan; beyond that the least recently used stream's slot is
+ * reused).  MPK_OK if every blocked launch of the plan on `stream` since the
+ * last check finished normally; MPK_ERR_DEVICE if a wave gave up waiting
+ * (watchdog: an entry it reads not written within the poll limit, about a
+ * second by default, e.g. because the GPU could not keep every worker
+ * resident); the message names the chunk and power.  After such a failure the
+ * launch's outputs are undefined, and later blocked launches of the plan on
+ * the same stream stop early until the check clears the status.
  */
 mpk_status mpk_check_device(mpk_plan_t plan, void* stream);
+
+/*
+ * Sets the watchdog of the plan's blocked launches: polls of a pending entry
+ * before a wave gives up (0: the default of about 10^6; negative: give up at
+ * the first wait, which tests of the failure path use).  Applies to launches
+ * enqueued after the call; must not overlap other calls on the plan.
+ * Errors: MPK_ERR_ARG (null plan).
+ */
+mpk_status mpk_set_watchdog(mpk_plan_t plan, int32_t polls);
 
 /*
  * Plan facts: n, nnz, number of levels, chunk count, SELL slots (padded

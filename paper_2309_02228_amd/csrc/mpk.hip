@@ -48,6 +48,7 @@ constexpr uint32_t kEpochLimit = 1u << 27; // done words hold epoch * 16 + power
 // different waves (and XCDs); sharing a line makes every write-through
 // invalidate the line under the other chunks' pollers.
 constexpr int kFlagStride = 32;
+constexpr int kStatusSlots = 64;  // per plan: one per calling stream (least recently used reused)
 
 // KIND_JCHAIN: the Jacobi-preconditioned chain w_j = w_{j-1} + c (B - I)^k w_{j-1}
 // (c = -(-1)^k) as one sequence of sub-powers u = (B - I) u_prev; every k-th
@@ -74,7 +75,6 @@ struct DevPlan {
     const int32_t* dep_idx;
     uint32_t* done;
     uint32_t* tickets;  // [4 launch slots][kParts], one per 128-byte line
-    int32_t* status;    // [0] code, [1] chunk, [2] power
     const uint32_t* lmask;  // per permuted row: slots of the strictly lower triangle (split plans)
     const int32_t* dslot;   // per permuted row: slot of the diagonal entry (split plans)
     int32_t n;
@@ -287,6 +287,7 @@ struct BlockArgs {
     int spin_limit;       // watchdog polls; negative: give up at once
     int plain_gather;     // 1: powers written in this launch may be read with plain loads
     uint32_t epoch;
+    int32_t* status;      // the calling stream's status slot: [0] code, [1] chunk, [2] power
     const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link of y_{base+1}
     const double* pow_in;   // KIND_GS2: the input w0 of the power of y_{base+1}
     double* link_out;       // KIND_JCHAIN: output column j - 1 receives w_j
@@ -300,9 +301,9 @@ __device__ __forceinline__ double* dest(const BlockArgs& a, int kl) {
 
 // Raises the device status (first failure wins) and returns false.
 __device__ bool give_up(const BlockArgs& a, int c, int kl) {
-    if ((threadIdx.x & 63) == 0 && atomicCAS(a.P.status, 0, (int)MPK_ERR_DEVICE) == 0) {
-        __hip_atomic_store(a.P.status + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(a.P.status + 2, a.base + kl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((threadIdx.x & 63) == 0 && atomicCAS(a.status, 0, (int)MPK_ERR_DEVICE) == 0) {
+        __hip_atomic_store(a.status + 1, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(a.status + 2, a.base + kl + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     return false;
 }
@@ -329,7 +330,7 @@ __device__ bool poll_until(const BlockArgs& a, __amdgpu_buffer_rsrc_t dr, const 
         for (int g = 0; g < G; ++g) all = all && ok[g];
         if (__all(all)) return true;
         if ((spin & 255) == 255 || a.spin_limit < 0) {
-            if (__hip_atomic_load(a.P.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            if (__hip_atomic_load(a.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
                 return false;
             if (spin >= a.spin_limit) return give_up(a, c_report, kl);
         }
@@ -771,7 +772,7 @@ Layout make_layout(const mpk::HostPlan& H) {
     L.dep_idx = take(std::max<size_t>(1, H.dep_idx.size()) * 4);
     L.done = take(std::max<size_t>(1, H.nchunks) * 4 * kFlagStride);
     L.tickets = take(4 * kParts * 4 * kFlagStride);
-    L.status = take(16);
+    L.status = take(kStatusSlots * 4 * kFlagStride);
     L.lmask = take(H.lmask.size() * 4);
     L.dslot = take(H.dslot.size() * 4);
     L.total = o;
@@ -796,6 +797,10 @@ struct mpk_plan_s {
     int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
     int q_cap = 0;                                   // powers per blocked launch at most (0: none)
     std::vector<std::vector<mpk::StageTask>> sched;  // wavefront schedule per q (lazy, under mu)
+    // status slot of each calling stream (device failures are reported to the
+    // stream whose launch failed), with a use stamp for reuse
+    std::vector<std::pair<void*, uint64_t>> status_owner = std::vector<std::pair<void*, uint64_t>>(kStatusSlots);
+    uint64_t status_clock = 0;
     std::mutex mu;
 };
 
@@ -899,6 +904,25 @@ struct BlockedChain {
 };
 BlockedChain g_chain[16];
 
+// Status slot of `stream` on plan p: assigned on the stream's first blocked
+// launch, the least recently used slot reused once all are taken.  Returns
+// null for a stream that has none when `assign` is false.
+int32_t* status_slot(mpk_plan_t p, void* stream, bool assign) {
+    std::lock_guard<std::mutex> lk(p->mu);
+    int pick = -1;
+    for (int i = 0; i < kStatusSlots; ++i)
+        if (p->status_owner[i].second != 0 && p->status_owner[i].first == stream) pick = i;
+    if (pick < 0) {
+        if (!assign) return nullptr;
+        pick = 0;
+        for (int i = 1; i < kStatusSlots; ++i)
+            if (p->status_owner[i].second < p->status_owner[pick].second) pick = i;
+        p->status_owner[pick].first = stream;
+    }
+    p->status_owner[pick].second = ++p->status_clock;
+    return (int32_t*)(p->dev + p->L.status) + (size_t)pick * kFlagStride;
+}
+
 // Launches the blocked kernel for powers base+1 .. base+q.
 mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, BlockArgs a) {
     int dev = 0;
@@ -918,6 +942,7 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
     a.P = p->D;
     a.epoch = ++p->epoch;
     a.workers = p->workers[kind][poly];
+    a.status = status_slot(p, st, true);
     a.spin_limit = p->H.watchdog == 0 ? kSpinLimit : p->H.watchdog;
     const BlockFn fn = pick_block(p->H, kind, poly);
     if (!fn) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this row width and group");
@@ -1306,6 +1331,18 @@ MPK_API mpk_status mpk_min_workers(mpk_plan_t p, int32_t q, int32_t* w) {
     return MPK_OK;
 }
 
+MPK_API mpk_status mpk_block_powers(mpk_plan_t p, int32_t op, int32_t* q) {
+    if (!p || !q) return fail(MPK_ERR_ARG, "null argument");
+    static const int kind_of[7] = {KIND_MONO, KIND_MONO, KIND_NEWTON, KIND_CHEB, KIND_NEWTON, KIND_JCHAIN, KIND_GS2};
+    static const int poly_of[7] = {0, 1, 1, 1, 0, 0, 0};
+    if (op < 0 || op > 6) return fail(MPK_ERR_ARG, "unknown operator kind %d", op);
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    const int qe = p->q_eff[kind_of[op]][poly_of[op]];
+    *q = p->q_cap > 0 ? std::min(qe, p->q_cap) : qe;
+    return MPK_OK;
+}
+
 MPK_API mpk_status mpk_plan_info(mpk_plan_t p, int64_t* n, int64_t* nnz, int32_t* nlevels,
                                  int32_t* nchunks, int64_t* sell_slots, int32_t* reg_slots,
                                  int32_t* workers_per_xcd, int32_t* p_block) {
@@ -1384,7 +1421,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     const int64_t nd = (int64_t)std::max<int32_t>(1, H.nchunks) * kFlagStride;
     fill_u32_kernel<<<grid_1d(nd), 256, 0, st>>>((uint32_t*)(d + L.done), nd, 0u);
     HIP_TRY(hipGetLastError());
-    fill_u32_kernel<<<1, 64, 0, st>>>((uint32_t*)(d + L.status), 4, 0u);
+    fill_u32_kernel<<<8, 256, 0, st>>>((uint32_t*)(d + L.status), kStatusSlots * kFlagStride, 0u);
     HIP_TRY(hipGetLastError());
     fill_u32_kernel<<<8, 256, 0, st>>>((uint32_t*)(d + L.tickets), 4 * kParts * kFlagStride, 0u);
     HIP_TRY(hipGetLastError());
@@ -1407,11 +1444,15 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     D.lmask = (const uint32_t*)(d + L.lmask);
     D.dslot = (const int32_t*)(d + L.dslot);
     D.tickets = (uint32_t*)(d + L.tickets);
-    D.status = (int32_t*)(d + L.status);
     D.n = H.n;
     p->D = D;
     p->dev = d;
     p->epoch = 0;
+    {
+        std::lock_guard<std::mutex> lk(p->mu);
+        for (auto& o : p->status_owner) o = {nullptr, 0};
+        p->status_clock = 0;
+    }
 
     // launch shapes: every workgroup of the blocked kernel must be resident at
     // once (waves wait on each other), so its grid is the occupancy limit
@@ -1428,16 +1469,19 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
             HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
                 &occ, (const void*)pick_block(H, kind, poly), kBlockThreads, 0));
             int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
-            wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
             if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));
+            const int resident = wg_per_part * kWaves;  // waves per partition the GPU holds at once
+            // no more waves than units
+            wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
             p->grid_block[kind][poly] = wg_per_part * kParts;
             p->workers[kind][poly] = wg_per_part * kWaves;
-            // units come from in-order tickets, so the deadlock bound counts resident
-            // waves only; keep it within half of the launched waves as a margin
-            // against workgroups that the GPU does not make resident
+            // units come from in-order tickets, so only running waves hold work: a
+            // block of q powers needs the deadlock bound within the launched waves,
+            // and within half of the resident capacity as a margin for workgroups
+            // that start late (other kernels still holding compute units)
             p->q_eff[kind][poly] = 1;
             for (int q = H.p_block; q >= 1; --q)
-                if (2 * H.min_workers[q] <= p->workers[kind][poly]) {
+                if (H.min_workers[q] <= p->workers[kind][poly] && 2 * H.min_workers[q] <= resident) {
                     p->q_eff[kind][poly] = q;
                     break;
                 }
@@ -1884,6 +1928,12 @@ mpk_status mpk::gs2_chain(mpk_plan_t p, int gamma, const double* x, double* Y, i
     return run_powers(p, (hipStream_t)stream, j, flags & MPK_PLAIN, flags & MPK_STAGED);
 }
 
+MPK_API mpk_status mpk_set_watchdog(mpk_plan_t p, int32_t polls) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    p->H.watchdog = polls;
+    return MPK_OK;
+}
+
 MPK_API mpk_status mpk_set_block(mpk_plan_t p, int32_t q) {
     if (!p) return fail(MPK_ERR_ARG, "null plan");
     if (q < 0 || q > mpk::kMaxBlock) return fail(MPK_ERR_ARG, "q must be in 0..%d", mpk::kMaxBlock);
@@ -1948,13 +1998,17 @@ MPK_API mpk_status mpk_permute(mpk_plan_t p, const double* in, double* out, int3
 MPK_API mpk_status mpk_check_device(mpk_plan_t p, void* stream) {
     mpk_status s = check_uploaded(p);
     if (s != MPK_OK) return s;
-    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    hipStream_t st = (hipStream_t)stream;
+    HIP_TRY(hipStreamSynchronize(st));
+    int32_t* slot = status_slot(p, stream, false);
+    if (!slot) return MPK_OK;  // no blocked launch on this stream
     int32_t h[4] = {0, 0, 0, 0};
-    HIP_TRY(hipMemcpy(h, p->D.status, sizeof h, hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpyAsync(h, slot, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
     if (h[0] == 0) return MPK_OK;
-    fill_u32_kernel<<<1, 64, 0, (hipStream_t)stream>>>((uint32_t*)p->D.status, 4, 0u);
+    fill_u32_kernel<<<1, 64, 0, st>>>((uint32_t*)slot, 4, 0u);
     HIP_TRY(hipGetLastError());
-    HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+    HIP_TRY(hipStreamSynchronize(st));
     return fail(MPK_ERR_DEVICE,
                 "blocked kernel watchdog: chunk %d waited too long before power %d "
                 "(not every worker was resident, or a dependency never completed)",

@@ -19,6 +19,9 @@ MPK_STAGED = 4
 MPK_LAST_POWER = 8  # server applies: return y_p only
 VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}  # bf16: BF16 values with a per-row FP32 scale
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
+# operator kinds of mpk_block_powers
+OPS = {"powers": 0, "poly_monomial": 1, "poly_newton": 2, "poly_chebyshev": 3, "newton_basis": 4,
+       "jacobi_chain": 5, "gs2_chain": 6}
 PRECONDS = {"chebyshev": 0, "none": 1, "jacobi": 2, "gs2": 3}  # right preconditioners of sstep_gmres
 CALL_APPLY, CALL_POLY, CALL_SSTEP, CALL_SOLVE = 0, 1, 2, 3
 
@@ -36,7 +39,7 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes",
            "mpk_server_submit_gmres", "mpk_jacobi_apply", "mpk_jacobi_work_bytes",
            "mpk_gs2_apply", "mpk_gs2_work_bytes", "mpk_sstep_gmres_ex",
-           "mpk_set_block", "mpk_tune_block"]
+           "mpk_set_block", "mpk_tune_block", "mpk_block_powers", "mpk_set_watchdog"]
 
 
 class MPKError(RuntimeError):
@@ -79,6 +82,8 @@ def _load():
         "mpk_get_partition": (I32, [P, pI32, pI32, pI32, P]),
         "mpk_get_deps": (I32, [P, pI64, P, P]),
         "mpk_min_workers": (I32, [P, I32, pI32]),
+        "mpk_block_powers": (I32, [P, I32, pI32]),
+        "mpk_set_watchdog": (I32, [P, I32]),
         "mpk_upload": (I32, [P, P, SZ, P]),
         "mpk_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_apply": (I32, [P, D, D, I64, I32, U32, P, SZ, P]),
@@ -240,6 +245,13 @@ class Plan:
         w = ctypes.c_int32()
         _check(_lib.mpk_min_workers(self._h, int(q), ctypes.byref(w)))
         return w.value
+
+    def block_powers(self, op="powers"):
+        """Powers per blocked launch for calls of operator kind ``op`` (see OPS); 1 means
+        those calls run the plain kernel."""
+        q = ctypes.c_int32()
+        _check(_lib.mpk_block_powers(self._h, OPS[op], ctypes.byref(q)))
+        return q.value
 
     def info(self):
         n, nnz, slots = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
@@ -411,8 +423,14 @@ class Plan:
         _check(_lib.mpk_permute(self._h, _dptr(x), _dptr(out), int(direction), _stream(stream)))
         return out
 
+    def set_watchdog(self, polls):
+        """Polls of a pending entry before a blocked-kernel wave gives up (0: default,
+        negative: at once)."""
+        _check(_lib.mpk_set_watchdog(self._h, int(polls)))
+
     def check(self, stream=None):
-        """Synchronises and raises MPKError if a blocked launch reported a failure."""
+        """Synchronises ``stream`` and raises MPKError if a blocked launch on it reported a
+        failure."""
         _check(_lib.mpk_check_device(self._h, _stream(stream)))
 
 

@@ -18,6 +18,8 @@ more than 100 MB in CRS form), which is not available here:
   unstructured SPD matrix in the middle of Table 2's nonzeros-per-row range.
 * ``random_pattern``: seeded random (possibly nonsymmetric, possibly
   disconnected) patterns for property tests.
+* ``banded_random``: seeded random patterns inside a band, nonsymmetric
+  unless asked otherwise, with long level structures.
 """
 from .matrices import (  # noqa: F401
     CSR,
@@ -26,6 +28,7 @@ from .matrices import (  # noqa: F401
     laplacian_3d,
     knn_graph_laplacian,
     random_pattern,
+    banded_random,
     block_diagonal,
     from_dense,
     identity,

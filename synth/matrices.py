@@ -170,6 +170,39 @@ def random_pattern(n, avg_nnz, seed, symmetric=False, diag=True, integer=False, 
     return _from_coo(n, r, c, v)
 
 
+def banded_random(n, avg_nnz, half_band, seed, symmetric=False, integer=False):
+    """Seeded random pattern confined to a band |i - j| <= half_band, diagonal
+    always present.  Off-diagonal entries are drawn independently per (row,
+    column) with probability (avg_nnz - 1) / (2 half_band), so unless
+    ``symmetric`` the pattern is nonsymmetric; the band keeps the graph's
+    diameter near n / half_band (long BFS level structures), unlike
+    ``random_pattern``.  Values uniform in [-1, 1] (integers in [-3, 3] with
+    ``integer``), the diagonal 1 + |row sum| of the off-diagonal magnitudes.
+    """
+    rng = np.random.default_rng(seed)
+    w = 2 * half_band + 1
+    i = np.arange(n, dtype=np.int64)[:, None]
+    cols = i + np.arange(-half_band, half_band + 1, dtype=np.int64)[None, :]
+    prob = min(1.0, (avg_nnz - 1.0) / (2.0 * half_band))
+    keep = rng.random((n, w)) < prob
+    if integer:
+        vals = rng.integers(-3, 4, size=(n, w)).astype(np.float64)
+    else:
+        vals = rng.uniform(-1.0, 1.0, size=(n, w))
+    if symmetric:  # mirror the strictly upper half onto the lower half
+        for d in range(1, half_band + 1):
+            up_k, up_v = keep[:, half_band + d], vals[:, half_band + d]
+            keep[d:, half_band - d] = up_k[:-d]
+            vals[d:, half_band - d] = up_v[:-d]
+    mask = keep & (cols >= 0) & (cols < n)
+    mask[:, half_band] = False
+    off = np.where(mask, np.abs(vals), 0.0).sum(axis=1)
+    vals = vals.copy()
+    vals[:, half_band] = 1.0 + (np.ceil(off) if integer else off)
+    mask[:, half_band] = True
+    return _from_rows(n, cols, vals, mask)
+
+
 def block_diagonal(*mats):
     """Block-diagonal matrix from CSR blocks (a graph with several components)."""
     rows, cols, vals = [], [], []

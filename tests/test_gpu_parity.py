@@ -62,7 +62,13 @@ CASES = {
     "blocks": lambda: S.block_diagonal(S.laplacian_2d(30, 20), S.identity(100), S.laplacian_1d(700)),
     "knn_20k": lambda: S.knn_graph_laplacian(20000, k=26, seed=0),
     "wide_rows": lambda: S.random_pattern(3000, 40, 5),
+    "band_nonsym": lambda: S.banded_random(20000, 6, 40, 1),
+    "band_wide": lambda: S.banded_random(20000, 40, 60, 2),
 }
+# plans whose levels are narrow enough that the blocked kernel must run (not the
+# plain fallback); the random patterns have a small diameter and wide levels
+ENGAGED = {"lap2d_64x64", "lap2d_ragged_37x29", "lap3d_24", "lap3d_ragged", "band_nonsym", "band_wide",
+           "knn_20k"}
 
 
 @pytest.mark.parametrize("name", sorted(CASES))
@@ -70,6 +76,8 @@ CASES = {
 def test_mpk_apply_matches_oracle(name, p):
     A = CASES[name]()
     plan, perm = make_plan(A, p_block=4)
+    if name in ENGAGED:
+        assert plan.block_powers() >= 2
     x = S.uniform_vector(A.n, 0)
     ref = O.mpk(A, x, p)
     got = run_apply(plan, perm, x, p)
@@ -214,23 +222,46 @@ def test_permute_roundtrip():
     assert np.array_equal(plan.permute(xp, 1).cpu().numpy(), x)
 
 
-def test_repeated_calls_and_epochs():
-    # the per-chunk completion words are never reset between launches
+def test_repeated_calls_alternate_inputs_into_one_buffer():
+    # two inputs alternate into the same Y buffer: a value left from the previous
+    # launch must never be taken for this launch's
     A = S.laplacian_3d(20)
     plan, perm = make_plan(A, p_block=3)
-    x = S.uniform_vector(A.n, 9)
-    ref = O.mpk(A, x, 7)
-    xd = torch.tensor(x[perm], device=DEV)
-    for _ in range(20):
-        Y = plan.apply(xd, 7)
-    plan.check()
-    assert np.all(rel_err(to_orig(Y.cpu().numpy(), perm), ref) <= TOL)
+    assert plan.block_powers() == 3
+    xs = [S.uniform_vector(A.n, 9), S.uniform_vector(A.n, 10)]
+    refs = [O.mpk(A, x, 7) for x in xs]
+    xds = [torch.tensor(x[perm], device=DEV) for x in xs]
+    Y = torch.empty((7, A.n), dtype=torch.float64, device=DEV)
+    for i in range(12):
+        plan.apply(xds[i % 2], 7, Y=Y)
+        plan.check()
+        assert np.all(rel_err(to_orig(Y.cpu().numpy(), perm), refs[i % 2]) <= TOL), i
+
+
+def test_non_finite_inputs_and_the_pending_pattern():
+    # NaN, infinities and the bit pattern the blocked kernel uses for entries not
+    # yet written (a signalling NaN) in x: arithmetic quiets NaNs, so the launch
+    # must finish and give bitwise the plain kernel's results
+    A = S.laplacian_3d(18, 17, 16)
+    plan, perm = make_plan(A, p_block=4)
+    assert plan.block_powers() == 4
+    x = S.uniform_vector(A.n, 4)
+    pend = np.array([0x7FF05E471A3E0001], dtype=np.uint64).view(np.float64)[0]
+    x[[5, 700, 2900]] = [np.nan, np.inf, -np.inf]
+    x[[17, 1800, A.n - 1]] = pend
+    blocked = run_apply(plan, perm, x, 4).view(np.int64)
+    plain = run_apply(plan, perm, x, 4, plain=True).view(np.int64)
+    assert np.array_equal(blocked, plain)
+    assert not np.any(blocked == np.int64(0x7FF05E471A3E0001))
+    fin = np.isfinite(O.mpk(A, np.nan_to_num(x, nan=0.0, posinf=0.0, neginf=0.0), 4))
+    assert fin.all()
 
 
 def test_watchdog_reports_and_recovers():
     # forced from the host: every dependency wait gives up at once; all waves exit
     A = S.laplacian_2d(64)
     plan, perm = make_plan(A, watchdog_polls=-1)
+    assert plan.block_powers() >= 2
     x = torch.tensor(S.uniform_vector(A.n, 0)[perm], device=DEV)
     plan.apply(x, 4)
     with pytest.raises(MPKError) as e:
@@ -241,6 +272,27 @@ def test_watchdog_reports_and_recovers():
     Y = ok.apply(x, 4)
     ok.check()
     assert np.all(rel_err(to_orig(Y.cpu().numpy(), perm2), O.mpk(A, S.uniform_vector(A.n, 0), 4)) <= TOL)
+
+
+def test_device_status_belongs_to_the_stream_that_failed():
+    # one plan, two streams: a launch forced to give up on stream a reports on a
+    # only; the later good launch on stream b reports success
+    A = S.laplacian_2d(64)
+    plan, perm = make_plan(A)
+    x0 = S.uniform_vector(A.n, 0)
+    x = torch.tensor(x0[perm], device=DEV)
+    sa, sb = torch.cuda.Stream(), torch.cuda.Stream()
+    plan.set_watchdog(-1)
+    plan.apply(x, 4, stream=sa)
+    sa.synchronize()
+    plan.set_watchdog(0)
+    Y = plan.apply(x, 4, stream=sb)
+    plan.check(stream=sb)
+    assert np.all(rel_err(to_orig(Y.cpu().numpy(), perm), O.mpk(A, x0, 4)) <= TOL)
+    with pytest.raises(MPKError) as e:
+        plan.check(stream=sa)
+    assert e.value.code == -7
+    plan.check(stream=sa)  # cleared by the report
 
 
 @pytest.mark.slow
