@@ -307,6 +307,27 @@ mpk_status poly_apply(mpk_plan_t plan, int32_t kind, int32_t d, const double* c,
                       void* work, size_t work_bytes, void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): poly_apply
+ * without a work argument.  The intermediate vectors live in a scratch array
+ * the library holds on each GPU it runs on, MPK_STATIC_SCRATCH_BYTES (64 MiB)
+ * per device, kept until the process ends; its address is looked up once per
+ * device on the first call there.  The call itself allocates nothing.
+ * The result equals poly_apply's with the same arguments.  It needs
+ * mpk_work_bytes(plan, MPK_CALL_POLY, d, flags) bytes of that scratch, i.e.
+ * 8 n (p_block + 2) bytes (plus 16 n without MPK_IO_PERMUTED); larger
+ * requests fail with MPK_ERR_ARG.  Every call on one GPU shares that GPU's
+ * scratch, and it keeps the last call's contents: calls that overlap on one
+ * GPU (from several streams or host threads) race and must be serialised by
+ * the caller.  Errors: as poly_apply, plus MPK_ERR_ARG when the scratch is too
+ * small, MPK_ERR_HIP if the scratch address cannot be obtained.
+ */
+#define MPK_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+mpk_status poly_apply_static(mpk_plan_t plan, int32_t kind, int32_t d, const double* c,
+                             const double* params, const double* x, double* out, uint32_t flags,
+                             void* stream);
+
+/*
  * s-step Krylov basis with constant real shifts (Sec. 4):
  *   V[:,0] = v, V[:,k] = (A - lambda[k-1] I) V[:,k-1] / sigma[k-1], k = 1..s,
  * with column k at V + k*ldv (device, ldv >= n).  lambda (host, s entries) are

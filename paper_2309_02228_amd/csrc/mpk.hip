@@ -1601,6 +1601,50 @@ MPK_API mpk_status poly_apply(mpk_plan_t p, int32_t kind, int32_t d, const doubl
     return s;
 }
 
+// Scratch of poly_apply_static, one copy per GPU (the array's name is a host
+// stand-in: host code uses only the device address looked up per device).
+static __device__ __align__(256) unsigned char scratch[MPK_STATIC_SCRATCH_BYTES];
+
+namespace {
+struct StaticScratch {
+    std::mutex mu;
+    void* ptr[64] = {};  // device address of `scratch` per device id
+};
+StaticScratch g_static;
+
+// Device address of the current device's scratch, looked up on the first call
+// on that device.
+mpk_status static_scratch(void** out) {
+    int dev = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(MPK_ERR_UNSUPPORTED, "device id %d beyond the 64 supported", dev);
+    std::lock_guard<std::mutex> lk(g_static.mu);
+    if (!g_static.ptr[dev]) {
+        void* a = nullptr;
+        HIP_TRY(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+        g_static.ptr[dev] = a;
+    }
+    *out = g_static.ptr[dev];
+    return MPK_OK;
+}
+}  // namespace
+
+MPK_API mpk_status poly_apply_static(mpk_plan_t p, int32_t kind, int32_t d, const double* c,
+                                     const double* params, const double* x, double* out, uint32_t flags,
+                                     void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    size_t need = 0;
+    mpk_status s = mpk_work_bytes(p, MPK_CALL_POLY, std::max(d, 0), flags, &need);
+    if (s != MPK_OK) return s;
+    if (need > MPK_STATIC_SCRATCH_BYTES)
+        return fail(MPK_ERR_ARG, "poly_apply_static needs %zu scratch bytes; the static scratch holds %zu",
+                    need, (size_t)MPK_STATIC_SCRATCH_BYTES);
+    void* w = nullptr;
+    s = static_scratch(&w);
+    if (s != MPK_OK) return s;
+    return poly_apply(p, kind, d, c, params, x, out, flags, w, MPK_STATIC_SCRATCH_BYTES, stream);
+}
+
 MPK_API mpk_status mpk_get_schedule(mpk_plan_t p, int32_t q, int32_t* ntasks, int32_t* ngroups, int32_t* tasks) {
     if (!p || !ntasks || !ngroups) return fail(MPK_ERR_ARG, "null argument");
     if (q < 1 || q > mpk::kMaxBlock) return fail(MPK_ERR_ARG, "q must be in 1..%d", mpk::kMaxBlock);

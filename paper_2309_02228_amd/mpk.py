@@ -39,7 +39,8 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_server_wait", "mpk_server_destroy", "mpk_sstep_gmres", "mpk_sstep_gmres_work_bytes",
            "mpk_server_submit_gmres", "mpk_jacobi_apply", "mpk_jacobi_work_bytes",
            "mpk_gs2_apply", "mpk_gs2_work_bytes", "mpk_sstep_gmres_ex",
-           "mpk_set_block", "mpk_tune_block", "mpk_block_powers", "mpk_set_watchdog"]
+           "mpk_set_block", "mpk_tune_block", "mpk_block_powers", "mpk_set_watchdog",
+           "poly_apply_static"]
 
 
 class MPKError(RuntimeError):
@@ -84,6 +85,7 @@ def _load():
         "mpk_min_workers": (I32, [P, I32, pI32]),
         "mpk_block_powers": (I32, [P, I32, pI32]),
         "mpk_set_watchdog": (I32, [P, I32]),
+        "poly_apply_static": (I32, [P, I32, I32, P, P, D, D, U32, P]),
         "mpk_upload": (I32, [P, P, SZ, P]),
         "mpk_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_apply": (I32, [P, D, D, I64, I32, U32, P, SZ, P]),
@@ -311,6 +313,19 @@ class Plan:
         w, nb = self._work(CALL_POLY, d, flags, x.device)
         _check(_lib.poly_apply(self._h, POLY_KINDS[kind], d, _ptr(c), _ptr(pr), _dptr(x), _dptr(out),
                                flags, _dptr(w), nb, _stream(stream)))
+        return out
+
+    def poly_static(self, kind, c, x, params=None, out=None, permuted=True, plain=False, stream=None):
+        """``poly`` through poly_apply_static: no work buffer, the library's per-device
+        static scratch holds the intermediate vectors."""
+        import torch
+        c = np.ascontiguousarray(c, dtype=np.float64)
+        pr = None if params is None else np.ascontiguousarray(params, dtype=np.float64)
+        if out is None:
+            out = torch.empty(self.n, dtype=torch.float64, device=x.device)
+        flags = self._flags(permuted, plain)
+        _check(_lib.poly_apply_static(self._h, POLY_KINDS[kind], c.size - 1, _ptr(c), _ptr(pr), _dptr(x), _dptr(out),
+                                      flags, _stream(stream)))
         return out
 
     def sstep(self, v, lambdas, sigmas=None, V=None, permuted=True, plain=False, stream=None, staged=False):
