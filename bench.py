@@ -54,20 +54,160 @@ def load_traffic(sha):
     return t.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(A, x, p, budget_s):
+def cpu_child(grid, p, reps):
+    """Runs in a child process (no GPU): times the plain C reference of the oracle on
+    the 3D 7-point Laplacian, pinned to one core, then with OpenMP on every host core
+    this process may use, then the NumPy oracle; prints one JSON line."""
     import numpy as np
     import oracle
-    reps, t0 = 0, time.perf_counter()
-    while True:
-        oracle.mpk(A, x, p)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s or reps >= 20:
-            break
-    gf = 2.0 * A.col.size * p * reps / el / 1e9
-    return {"value": round(gf, 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
-            "sample": f"full 160^3 matrix, p={p}, {reps} complete MPK calls "
-                      f"({el:.1f} s, single-threaded NumPy)"}
+    import synth
+    from oracle import ref_c
+    if not os.path.exists(ref_c.LIB):
+        ref_c.build()
+    A = synth.laplacian_3d(grid)
+    x = synth.uniform_vector(A.n, 0)
+    flops = 2.0 * A.col.size * p
+    allowed = sorted(os.sched_getaffinity(0))
+
+    def median_time(fn):
+        fn()  # warm-up
+        ts = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            fn()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts))
+
+    os.sched_setaffinity(0, {allowed[0]})
+    t1 = median_time(lambda: ref_c.mpk(A, x, p))
+    os.sched_setaffinity(0, set(allowed))
+    used = [0]
+
+    def par():
+        used[0] = ref_c.mpk_omp(A, x, p, len(allowed))[1]
+    tp = median_time(par)
+    os.sched_setaffinity(0, {allowed[0]})
+    tn = median_time(lambda: oracle.mpk(A, x, p))
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    print(json.dumps({"c_1core_s": t1, "c_omp_s": tp, "omp_threads": used[0], "numpy_1core_s": tn,
+                      "gflop": flops / 1e9, "allowed_cpus": len(allowed), "nproc": os.cpu_count(),
+                      "cpu_model": model}), flush=True)
+
+
+def cpu_baseline(grid, p):
+    """The oracle on the host: the plain C reference on one core (the baseline), and the
+    same loops with OpenMP on every core the process may use, both timed in a child
+    process that never touches the GPU."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-child", "--grid", str(grid), "--p", str(p)],
+                       capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"value": None, "unit": "GFLOP/s", "cores": 1, "kind": "oracle", "error": r.stderr[-500:]}
+    c = json.loads(r.stdout.strip().splitlines()[-1])
+    sample = (f"full {grid}^3 matrix, p={p}: median of 5 complete MPK calls after one warm-up")
+    return {
+        "value": round(c["gflop"] / c["c_1core_s"], 3), "unit": "GFLOP/s", "cores": 1, "kind": "oracle",
+        "sample": sample + " (oracle/mpk_ref.c, gcc -O2 -ffp-contract=off, pinned to one core)",
+        "ms_per_mpk": round(c["c_1core_s"] * 1e3, 2),
+        "all_cores": {"value": round(c["gflop"] / c["c_omp_s"], 3), "unit": "GFLOP/s",
+                      "threads": c["omp_threads"], "ms_per_mpk": round(c["c_omp_s"] * 1e3, 2),
+                      "note": "the same loops with OpenMP over rows, every CPU this process may use"},
+        "numpy_oracle_1core": {"value": round(c["gflop"] / c["numpy_1core_s"], 3), "unit": "GFLOP/s"},
+        "host": {"nproc": c["nproc"], "cpus_allowed": c["allowed_cpus"], "cpu_model": c["cpu_model"]},
+    }
+
+
+def knn_bench(args, dev, stream):
+    """The unstructured workload: the shifted graph Laplacian of the symmetrised
+    26-NN graph of uniform points in the unit cube (Morton order), FP64.  Blocked
+    against plain powers, the tuned block size, the degree-8 Chebyshev polynomial
+    and s-step GMRES (s = 8) with that polynomial as right preconditioner."""
+    import numpy as np
+    import torch
+    import oracle
+    import synth
+    from paper_2309_02228_amd import Plan
+    t0 = time.perf_counter()
+    A = synth.knn_graph_laplacian(args.knn_points, k=26, seed=0)
+    t_gen = time.perf_counter() - t0
+    n, nnz = A.n, int(A.col.size)
+    t0 = time.perf_counter()
+    plan = Plan.from_csr(A, p_block=8)
+    t_plan = time.perf_counter() - t0
+    plan.upload(dev)
+    info = plan.info()
+    log(f"knn: {n} rows, {nnz} nonzeros ({t_gen:.1f} s to generate), plan {t_plan:.2f} s, {info}")
+    x = plan.permute(torch.tensor(synth.uniform_vector(n, 0), device=dev), 0)
+
+    def tm(fn, reps=10):
+        for _ in range(2):
+            fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        plan.check()
+        return e0.elapsed_time(e1) / reps * 1e-3
+    powers = {}
+    Y = torch.empty((8, n), dtype=torch.float64, device=dev)
+    for pp in (1, 2, 4, 8):
+        tb = tm(lambda: plan.apply(x, pp, Y=Y[:pp]))
+        tp = tm(lambda: plan.apply(x, pp, Y=Y[:pp], plain=True))
+        f = 2.0 * nnz * pp
+        powers[str(pp)] = {"blocked_us": round(tb * 1e6, 1), "plain_us": round(tp * 1e6, 1),
+                           "blocked_gflops": round(f / tb / 1e9, 1), "plain_gflops": round(f / tp / 1e9, 1),
+                           "speedup": round(tp / tb, 3)}
+    q_opt, t_opt = plan.tune_block(x, 8, Y=Y)
+    plan.set_block(0)
+    lmax = 2.0 * float(np.max(np.diff(A.rowptr))) + 0.1
+    c, th, de = oracle.chebyshev_inverse_coeffs(8, 0.1, lmax)
+    prm = np.array([th, de])
+    tb = tm(lambda: plan.poly("chebyshev", c, x, params=prm))
+    tp = tm(lambda: plan.poly("chebyshev", c, x, params=prm, plain=True))
+    cheb = {"blocked_us": round(tb * 1e6, 1), "plain_us": round(tp * 1e6, 1), "speedup": round(tp / tb, 3)}
+    bvec = plan.permute(torch.tensor(synth.uniform_vector(n, 1), device=dev), 0)
+    work = torch.empty(plan.gmres_work_bytes(8, 64, 8) // 8 + 64, dtype=torch.float64, device=dev)
+    lat, res = [], None
+    for r in range(6):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = plan.sstep_gmres(plan, bvec, 8, 64, 8, 0.1, lmax, tol=1e-8, max_cycles=50, work=work)
+        torch.cuda.synchronize()
+        if r > 0:
+            lat.append(time.perf_counter() - t0)
+    plan.check()
+    true = float(torch.linalg.norm(bvec - plan.apply(res[0], 1)[0]) / torch.linalg.norm(bvec))
+    lat = np.array(lat) * 1e3
+    gm = {"p50_ms": round(float(np.percentile(lat, 50)), 2), "p99_ms": round(float(np.percentile(lat, 99)), 2),
+          "basis_vectors": res[1], "cycles": res[2], "final_rel_residual": res[3], "true_rel_residual": true}
+    out = {
+        "workload": f"shifted graph Laplacian (+0.1 I) of the symmetrised 26-NN graph of {n} uniform points in "
+                    f"[0,1)^3, Morton order, FP64; {nnz} nonzeros ({nnz / n:.2f} per row), {info['nlevels']} BFS levels",
+        "plan_build_s": round(t_plan, 2),
+        "powers_per_blocked_launch": {"mpk": plan.block_powers("powers"),
+                                      "chebyshev": plan.block_powers("poly_chebyshev")},
+        "register_slots": info["reg_slots"],
+        "mpk": powers,
+        "p_opt": {"p": 8, "q_opt": q_opt, "us_per_call": round(t_opt * 1e6, 1),
+                  "note": "mpk_tune_block over q = 1..min(8, deadlock bound); q = 1 is the plain kernel"},
+        "chebyshev_degree8": cheb,
+        "sstep_gmres": {**gm, "setup": "s = 8, m = 64, degree-8 Chebyshev right preconditioner on "
+                                        f"[0.1, {lmax:g}], tol 1e-8, FP64, 5 solves after one warm-up"},
+    }
+    log("knn: " + ", ".join(f"p={k}: {v['speedup']}x" for k, v in powers.items())
+        + f"; q_opt {q_opt}; chebyshev {cheb['speedup']}x; gmres p50 {gm['p50_ms']} ms ({gm['basis_vectors']} "
+          f"vectors, true residual {true:.1e})")
+    del plan, Y, work
+    return out
 
 
 def natural_order_library_spmv(A, x, p, steps, warmup, dev, y_ref, to_level):
@@ -295,7 +435,9 @@ def main():
     ap.add_argument("--grid", type=int, default=160)
     ap.add_argument("--p-block", type=int, default=0)
     ap.add_argument("--chunks-per-worker", type=int, default=0)
-    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-knn", action="store_true", help="skip the unstructured 8M-point kNN workload")
+    ap.add_argument("--knn-points", type=int, default=8_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-f32", action="store_true", help="skip the FP32 and BF16 matrix-value measurements")
     ap.add_argument("--no-solve", action="store_true", help="skip the refinement-solve latency measurement")
@@ -321,6 +463,9 @@ def main():
                     help="only run 5 device-to-device copies of MIB MiB (scales the HBM byte "
                          "counters of a profiler run) and exit")
     args = ap.parse_args()
+    if args.cpu_child:
+        cpu_child(args.grid, args.p, 5)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU matrix power "
               "kernel; no multi-GPU path exists (use --gpus 1).", file=sys.stderr)
@@ -446,6 +591,10 @@ def main():
             "workload": f"3D 7-point Laplacian {g}^3 (N={n}, nnz={nnz}), FP64, SELL-64 in BFS level "
                         f"order, x uniform[-1,1] seed 0, p={p} powers stored, I/O in level order",
             "p": p, "p_block": info["p_block"], "kernel": key,
+            "timing": "warm: the calls run back to back with x, Y and the plan resident in HBM (part of the "
+                      "matrix may still sit in the 256 MB Infinity Cache from the previous call); HIP events "
+                      "on the launch stream; cold_cache_timing gives each call timed alone after writing "
+                      "2 GiB",
             "chunks_per_worker": args.chunks_per_worker or None,
             "workers_per_xcd": info["workers_per_xcd"],
         },
@@ -763,6 +912,8 @@ def main():
         log("s-step gmres: " + ", ".join(f"{k2}: {v['blocked_ms_per_1000_vectors']} ms/1000 vectors blocked, "
                                            f"{v['speedup']}x" for k2, v in fixed.items()))
         del hi8, lo8, work, jac8, gs8, gwork
+    if not args.no_knn and args.only == "both":
+        out["knn_8m"] = knn_bench(args, dev, stream)
     if not args.no_serve and args.only == "both":
         out["serving"] = serving_bench(args, A, plan, dev)
         sv = out["serving"]["by_kind"]["solve"]
@@ -771,7 +922,8 @@ def main():
                                            "(serving.workload), PCIe copies included"}
     if not args.no_cpu_baseline and args.only == "both":
         log("cpu baseline: FP64 oracle on the host ...")
-        out["cpu_baseline"] = cpu_baseline(A, x, p, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(g, p)
+        log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
 
 

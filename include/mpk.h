@@ -328,16 +328,6 @@ mpk_status poly_apply_static(mpk_plan_t plan, int32_t kind, int32_t d, const dou
                              void* stream);
 
 /*
- * s-step Krylov basis with constant real shifts (Sec. 4):
- *   V[:,0] = v, V[:,k] = (A - lambda[k-1] I) V[:,k-1] / sigma[k-1], k = 1..s,
- * with column k at V + k*ldv (device, ldv >= n).  lambda (host, s entries) are
- * the Newton shifts (all zero gives the monomial basis); sigma (host, s
- * entries) are column scalings, NULL meaning all ones.  v (device, n) may
- * alias V's column 0.  Perm space with MPK_IO_PERMUTED; otherwise through
- * `work`.  Errors: MPK_ERR_ARG (s < 1, ldv < n, zero sigma, null pointers,
- * work too small), MPK_ERR_STATE, MPK_ERR_HIP.
- */
-/*
  * Level groups and wavefront schedule of one block of q powers (Sec. 3: an
  * execution order from the level structure and the cache size):
  *   levels are grouped greedily and contiguously: a group is closed before
@@ -473,6 +463,16 @@ mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t precond, int
 mpk_status mpk_sstep_gmres_work_bytes(mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, uint32_t flags,
                                       size_t* bytes);
 
+/*
+ * s-step Krylov basis with constant real shifts (Sec. 4):
+ *   V[:,0] = v, V[:,k] = (A - lambda[k-1] I) V[:,k-1] / sigma[k-1], k = 1..s,
+ * with column k at V + k*ldv (device, ldv >= n).  lambda (host, s entries) are
+ * the Newton shifts (all zero gives the monomial basis); sigma (host, s
+ * entries) are column scalings, NULL meaning all ones.  v (device, n) may
+ * alias V's column 0.  Perm space with MPK_IO_PERMUTED; otherwise through
+ * `work`.  Errors: MPK_ERR_ARG (s < 1, ldv < n, zero sigma, null pointers,
+ * work too small), MPK_ERR_STATE, MPK_ERR_HIP.
+ */
 mpk_status sstep_basis(mpk_plan_t plan, int32_t s, const double* lambda, const double* sigma,
                        const double* v, double* V, int64_t ldv, uint32_t flags, void* work,
                        size_t work_bytes, void* stream);

@@ -44,6 +44,10 @@ sparse iterative solvers on multi-core CPUs"):
   preconditioner or with the diagonal (Jacobi) one, a blocked Newton MPK per
   block of s vectors, reading R22
 
+* ``ref_c`` (``mpk_ref.c``)         -- the same MPK in plain C, single-threaded
+  and with OpenMP over rows (the CPU baselines of the benchmark), equal to
+  ``mpk`` bitwise
+
 Parity status of each function is stated in its docstring.  The readings
 taken where the paper is silent are listed in ``mpk_oracle.READINGS``.
 """

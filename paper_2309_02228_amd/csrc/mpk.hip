@@ -481,17 +481,36 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                         if (KIND == KIND_GS2 && ((lm[g] >> j) & 1u)) sl[g] = fma(decode<VT>(r, rsc[g]), xv[j], sl[g]);
                     }
             }
+            // slots beyond the register cache, streamed at every power in batches
+            // (columns and values, then the gathers: two round trips per batch); the
+            // wide-row kernels, which rely on this path, take eight slots per batch,
+            // the others one (plans use them only when the caller caps the slots)
+            constexpr int kTB = REG >= 16 ? 8 : 1;
 #pragma unroll
             for (int g = 0; g < G; ++g)
-                for (int j = REG; j < (local ? 0 : width[g]); ++j) {  // slots beyond the register cache
-                    const int64_t slot = off[g] + (int64_t)j * kChunkRows + lane;
-                    const int cj = a.P.col[slot];
-                    if (cj >= 0) {
-                        const double vj = decode<VT>(val[slot], rsc[g]);
-                        const double xj = kl == 0 || a.plain_gather ? src[cj] : load_coherent(src + cj);
-                        s[g] = fma(vj, xj, s[g]);
-                        if (KIND == KIND_GS2 && j < 32 && ((lm[g] >> j) & 1u)) sl[g] = fma(vj, xj, sl[g]);
+                for (int j0 = REG; j0 < (local ? 0 : width[g]); j0 += kTB) {
+                    int cj[kTB];
+                    double vj[kTB], xj[kTB];
+#pragma unroll
+                    for (int t = 0; t < kTB; ++t) {
+                        cj[t] = -1;
+                        vj[t] = 0.0;
+                        if (j0 + t < width[g]) {
+                            const int64_t slot = off[g] + (int64_t)(j0 + t) * kChunkRows + lane;
+                            cj[t] = a.P.col[slot];
+                            vj[t] = decode<VT>(val[slot], rsc[g]);
+                        }
                     }
+#pragma unroll
+                    for (int t = 0; t < kTB; ++t)
+                        xj[t] = cj[t] < 0 ? 0.0 : (kl == 0 || a.plain_gather ? src[cj[t]] : load_coherent(src + cj[t]));
+#pragma unroll
+                    for (int t = 0; t < kTB; ++t)
+                        if (cj[t] >= 0) {
+                            s[g] = fma(vj[t], xj[t], s[g]);
+                            if (KIND == KIND_GS2 && j0 + t < 32 && ((lm[g] >> (j0 + t)) & 1u))
+                                sl[g] = fma(vj[t], xj[t], sl[g]);
+                        }
                 }
             double* dst = dest(a, kl);
             const bool last = kl + 1 == a.q;
@@ -792,6 +811,7 @@ struct mpk_plan_s {
     int workers[kKinds][2] = {};  // waves per partition
     int grid_block[kKinds][2] = {};
     int q_eff[kKinds][2] = {};    // powers per launch meeting the deadlock bound
+    int reg[kKinds][2] = {};      // register slots per row of the kernel in use
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
     int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
@@ -842,11 +862,11 @@ BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
     return pick_block_g<4, VT>(reg, kind, poly);
 }
 
-// The planner keeps one chunk per worker when rows need 32 or more slots.
-BlockFn pick_block(const mpk::HostPlan& H, int kind, bool poly) {
-    if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_vt<uint16_t>(H.reg_slots, H.group, kind, poly);
-    return H.value_type == MPK_VALUES_F32 ? pick_block_vt<float>(H.reg_slots, H.group, kind, poly)
-                                          : pick_block_vt<double>(H.reg_slots, H.group, kind, poly);
+// The planner keeps one chunk per worker when rows need more than 16 slots.
+BlockFn pick_block(const mpk::HostPlan& H, int reg, int kind, bool poly) {
+    if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_vt<uint16_t>(reg, H.group, kind, poly);
+    return H.value_type == MPK_VALUES_F32 ? pick_block_vt<float>(reg, H.group, kind, poly)
+                                          : pick_block_vt<double>(reg, H.group, kind, poly);
 }
 
 template <typename VT>
@@ -944,7 +964,7 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
     a.workers = p->workers[kind][poly];
     a.status = status_slot(p, st, true);
     a.spin_limit = p->H.watchdog == 0 ? kSpinLimit : p->H.watchdog;
-    const BlockFn fn = pick_block(p->H, kind, poly);
+    const BlockFn fn = pick_block(p->H, p->reg[kind][poly], kind, poly);
     if (!fn) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this row width and group");
     hipLaunchKernelGGL(fn, dim3(p->grid_block[kind][poly]),
                        dim3(kBlockThreads), 0, st, a);
@@ -1352,7 +1372,8 @@ MPK_API mpk_status mpk_plan_info(mpk_plan_t p, int64_t* n, int64_t* nnz, int32_t
     if (nlevels) *nlevels = p->H.nlevels;
     if (nchunks) *nchunks = p->H.nchunks;
     if (sell_slots) *sell_slots = (int64_t)p->H.sell_val.size();
-    if (reg_slots) *reg_slots = p->H.reg_slots;
+    // after upload: the register slots of the plain powers' kernel in use
+    if (reg_slots) *reg_slots = p->dev ? p->reg[KIND_MONO][0] : p->H.reg_slots;
     // reported for the plain matrix powers (mpk_apply's blocked kernel)
     if (workers_per_xcd) *workers_per_xcd = p->workers[KIND_MONO][0];
     if (p_block) *p_block = p->dev ? p->q_eff[KIND_MONO][0] : p->H.p_block;
@@ -1464,27 +1485,39 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     const int maxunits = (maxlen + H.group - 1) / H.group;
     for (int kind = 0; kind < kKinds; ++kind)
         for (int poly = 0; poly < 2; ++poly) {
-            int occ = 0;
-            if (!pick_block(H, kind, poly)) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this plan");
-            HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &occ, (const void*)pick_block(H, kind, poly), kBlockThreads, 0));
-            int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
-            if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));
-            const int resident = wg_per_part * kWaves;  // waves per partition the GPU holds at once
-            // no more waves than units
-            wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
-            p->grid_block[kind][poly] = wg_per_part * kParts;
-            p->workers[kind][poly] = wg_per_part * kWaves;
-            // units come from in-order tickets, so only running waves hold work: a
-            // block of q powers needs the deadlock bound within the launched waves,
-            // and within half of the resident capacity as a margin for workgroups
-            // that start late (other kernels still holding compute units)
-            p->q_eff[kind][poly] = 1;
-            for (int q = H.p_block; q >= 1; --q)
-                if (H.min_workers[q] <= p->workers[kind][poly] && 2 * H.min_workers[q] <= resident) {
-                    p->q_eff[kind][poly] = q;
-                    break;
+            // wide rows: the kernel holding 32 slots per row in registers and the one
+            // holding 16 (streaming the rest at each power) use the same units of
+            // one chunk; the leaner one keeps more waves resident, which deep level
+            // structures need for a block of q powers.  Take the one that admits
+            // more powers per launch, the 32-slot one on a tie.
+            const int cand[2] = {H.reg_slots, H.reg_slots >= 32 ? 16 : 0};
+            p->q_eff[kind][poly] = 0;
+            for (int ci = 0; ci < 2 && cand[ci] > 0; ++ci) {
+                const BlockFn fn = pick_block(H, cand[ci], kind, poly);
+                if (!fn) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this plan");
+                int occ = 0;
+                HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, kBlockThreads, 0));
+                int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
+                if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));
+                // no more waves than units
+                wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
+                // units come from in-order tickets, so only running waves hold work, and
+                // every launched workgroup is resident at once on an idle GPU (the grid is
+                // the occupancy limit) or starts once the kernels ahead of it finish: a
+                // block of q powers needs the deadlock bound within the launched waves
+                int qe = 1;
+                for (int q = H.p_block; q >= 1; --q)
+                    if (H.min_workers[q] <= wg_per_part * kWaves) {
+                        qe = q;
+                        break;
+                    }
+                if (qe > p->q_eff[kind][poly]) {
+                    p->q_eff[kind][poly] = qe;
+                    p->reg[kind][poly] = cand[ci];
+                    p->grid_block[kind][poly] = wg_per_part * kParts;
+                    p->workers[kind][poly] = wg_per_part * kWaves;
                 }
+            }
         }
     // plain launches: up to 32 workgroups per CU (128 waves), a few chunks per
     // wave; this measured faster than 8 per CU at the 160^3 Laplacian

@@ -43,6 +43,11 @@ def test_knn_8m_mpk_and_chebyshev_degree8():
     assert lv["nlevels"] == nl and np.array_equal(lv["level_of_row"], level)
     say(t0, f"levels bit-exact ({nl} levels)")
     plan.upload(DEV)
+    # the levels hold up to ~94k rows: the blocked kernel must still run (blocks of
+    # at least 2 powers), not the plain fallback
+    qp, qc = plan.block_powers("powers"), plan.block_powers("poly_chebyshev")
+    say(t0, f"uploaded: {plan.info()}, powers per blocked launch: MPK {qp}, Chebyshev {qc}")
+    assert qp >= 2 and qc >= 2
     perm = lv["perm"].astype(np.int64)
     x = S.uniform_vector(A.n, 0)
     xd = torch.tensor(x[perm], device=DEV)
@@ -63,9 +68,27 @@ def test_knn_8m_mpk_and_chebyshev_degree8():
     lmax = 2.0 * np.max(np.diff(A.rowptr)) + 0.1
     c, theta, delta = O.chebyshev_inverse_coeffs(8, 0.1, lmax)
     out = plan.poly("chebyshev", c, xd, params=np.array([theta, delta])).cpu().numpy()
+    outp = plan.poly("chebyshev", c, xd, params=np.array([theta, delta]), plain=True).cpu().numpy()
     plan.check()
+    assert np.array_equal(out, outp)
     got = np.empty_like(out)
     got[perm] = out
     e = rel_err(got, O.poly_chebyshev(A, x, c, theta, delta))
     say(t0, f"Chebyshev degree 8: rel err {e:.2e}")
     assert e <= TOL
+    del got, outp, out
+    # s-step GMRES (Sec. 4, Alg. 3c) with s = 8 and the degree-8 Chebyshev polynomial
+    # preconditioner on [0.1, Gershgorin bound] (R12, R17-R19), b uniform in [-1, 1]
+    b = S.uniform_vector(A.n, 1)
+    bd = torch.tensor(b[perm], device=DEV)
+    xs, nvec, cycles, rel = plan.sstep_gmres(plan, bd, 8, 64, 8, 0.1, lmax, tol=1e-8, max_cycles=50)
+    xp = plan.sstep_gmres(plan, bd, 8, 64, 8, 0.1, lmax, tol=1e-8, max_cycles=50, plain=True)[0]
+    plan.check()
+    say(t0, f"s-step GMRES: {nvec} basis vectors, {cycles} cycles, reported residual {rel:.2e}")
+    assert rel <= 1e-8
+    assert torch.equal(xs, xp)  # blocked and plain bases give the same iterates
+    xh = np.empty(A.n)
+    xh[perm] = xs.cpu().numpy()
+    true_rel = np.linalg.norm(b - O.spmv(A, xh)) / np.linalg.norm(b)
+    say(t0, f"true residual on the host (oracle SpMV): {true_rel:.2e}")
+    assert true_rel <= 1.01e-8

@@ -572,3 +572,45 @@ def test_schedule_validator_catches_planted_mistakes():
     # 3) drop a task (rows never computed)
     with pytest.raises(AssertionError):
         O.validate_schedule(B, lp, tasks[:-1], 3)
+
+
+# ------------------------------------------------- plain C reference (mpk_ref.c)
+@pytest.fixture(scope="module")
+def ref_c():
+    from oracle import ref_c as R
+    if not os.path.exists(R.LIB):
+        R.build()
+    return R
+
+
+@pytest.mark.parametrize("mk", [lambda: S.laplacian_3d(6, 5, 4), lambda: S.random_pattern(80, 5, 6, integer=True),
+                                lambda: S.block_diagonal(S.identity(7), S.laplacian_1d(20))])
+def test_c_reference_exact_against_integer_dense_powers(ref_c, mk):
+    # catches: a dropped power, a transposed operand, an off-by-one in the row loop
+    A = mk()
+    x = S.integer_vector(A.n, 3, bound=1 << 14)
+    M = int_dense(A)
+    y = x.astype(np.int64)
+    Y = ref_c.mpk(A, x, 6)
+    for k in range(6):
+        y = M @ y
+        assert np.array_equal(Y[k], y.astype(np.float64)), k
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_c_reference_equals_numpy_oracle_bitwise(ref_c, seed):
+    # both sum each row in stored order from zero without fused multiply-adds; the
+    # OpenMP split over rows leaves every row's sum to one thread
+    A = S.random_pattern(4000, 7, seed) if seed % 2 else S.knn_graph_laplacian(3000, k=12, seed=seed)
+    x = S.uniform_vector(A.n, seed + 7)
+    ref = O.mpk(A, x, 5)
+    assert np.array_equal(ref_c.mpk(A, x, 5), ref)
+    Y, used = ref_c.mpk_omp(A, x, 5, 4)
+    assert used >= 1 and np.array_equal(Y, ref)
+
+
+def test_c_reference_order_sensitive_case(ref_c):
+    # the hand-worked order case of the SpMV pin: 1e16 + 1 - 1e16 = 0 left to right
+    A = S.CSR(3, np.array([0, 3, 3, 3], dtype=np.int32), np.array([0, 1, 2], dtype=np.int32),
+              np.array([1e16, 1.0, -1e16]))
+    assert ref_c.mpk(A, np.ones(3), 1)[0, 0] == 0.0
