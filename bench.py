@@ -267,10 +267,13 @@ def serving_bench(args, A160, plan160, dev):
     import numpy as np
     import torch
     import synth
-    from paper_2309_02228_amd import Plan
+    from paper_2309_02228_amd import Plan, PlanCache
     from paper_2309_02228_amd.mpk import Server
 
     rng = np.random.default_rng(args.serve_seed)
+    # the catalogue's plans come from the library's plan cache, keyed by sparsity pattern
+    # (the 160^3 stencil reuses the plan of the headline measurement)
+    cache = PlanCache(device_bytes=12 << 30)
 
     def lap_bounds(dims):
         return (sum(2 - 2 * np.cos(np.pi / (m + 1)) for m in dims),
@@ -290,12 +293,12 @@ def serving_bench(args, A160, plan160, dev):
             lmin, lmax = lap_bounds(dims)
         else:
             lmin, lmax = 0.1, 2.0 * float(np.max(np.diff(A.rowptr))) + 0.1
-        hi = plan160 if make is None else Plan.from_csr(A, p_block=4).upload(dev)
-        lo = Plan.from_csr(A, p_block=4, values="f32").upload(dev)
+        hi = plan160 if make is None else cache.get(A, p_block=4)[0]
+        lo = cache.get(A, p_block=4, values="f32")[0]
         # preconditioner degree: about a third of sqrt(kappa), 4..32, so that GMRES
         # needs a few dozen basis vectors
         deg = int(min(32, max(4, np.ceil(np.sqrt(lmax / lmin) / 3))))
-        cat.append({"name": name, "n": A.n, "hi": hi, "lo": lo, "lmin": lmin, "lmax": lmax, "degree": deg,
+        cat.append({"name": name, "n": A.n, "A": A, "hi": hi, "lo": lo, "lmin": lmin, "lmax": lmax, "degree": deg,
                     "x": synth.uniform_vector(A.n, 10), "b": synth.uniform_vector(A.n, 11)})
     torch.cuda.synchronize()
     log(f"serving: catalogue of {len(cat)} matrices planned in {time.perf_counter() - t0:.1f} s")
@@ -348,7 +351,8 @@ def serving_bench(args, A160, plan160, dev):
     rate = args.serve_load / alone.mean()
     gaps = rng.exponential(1.0 / rate, size=nreq)
     arrive = np.cumsum(gaps) - gaps[0]
-    srv = Server(workers=args.serve_workers, device_bytes=pool)
+    srv = Server(workers=args.serve_workers, device_bytes=pool, apply_workers=args.serve_apply_workers,
+                 max_wait_s=args.serve_max_wait)
     lat, queue = np.zeros(nreq), np.zeros(nreq)
     tickets = [None] * nreq
     import threading
@@ -408,7 +412,9 @@ def serving_bench(args, A160, plan160, dev):
                     "solves to 1e-8 (s = 8, m = 64; right Chebyshev preconditioner of degree "
                     "min(32, max(4, sqrt(kappa) / 3)) through FP32-valued launches; FP64 residuals and "
                     "orthogonalisation)",
-        "workers": args.serve_workers, "pool_gib": args.serve_pool_gib,
+        "workers": args.serve_workers, "apply_workers": args.serve_apply_workers,
+        "admission": f"any waiting request that fits, oldest first; aging bound {args.serve_max_wait} s",
+        "pool_gib": args.serve_pool_gib,
         "throughput_req_s": round(nreq / makespan, 2), "makespan_s": round(makespan, 3),
         "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99), "queue_p50_ms": pct(queue, 50),
         "by_kind": by,
@@ -417,12 +423,36 @@ def serving_bench(args, A160, plan160, dev):
         "alone_service_s": round(float(alone.sum()), 3),
         "bitwise_same_as_alone": f"{len(check_idx)} sampled requests",
         "note": "host buffers in pinned memory; latency = submit to result in host memory, PCIe copies "
-                "included; plans built once before the run (the plan cache)",
+                "included; plans built once before the run through the plan cache",
     }
     log(f"serving: {nreq / makespan:.1f} req/s, p50 {out['p50_ms']} ms, p99 {out['p99_ms']} ms "
         f"(solves p50 {by['solve']['p50_ms']} / p99 {by['solve']['p99_ms']} ms)")
+    # the plan cache on one pattern with new values (a shifted 100^3 stencil): the levels
+    # and layout are kept and only the values refilled, against planning from scratch
+    for c in cat:
+        for key in ("hi", "lo"):
+            if c[key] is not plan160:
+                c[key].release()
+    A100 = next(c["A"] for c in cat if c["name"] == "lap3d_100^3")
+    diag = A100.col == np.repeat(np.arange(A100.n), np.diff(A100.rowptr))
+    shifted = synth.CSR(A100.n, A100.rowptr, A100.col, A100.val + 0.5 * diag)
+    t0 = time.perf_counter()
+    ps, how = cache.get(shifted, p_block=4)
+    torch.cuda.synchronize()
+    t_upd = time.perf_counter() - t0
+    ps.release()
+    t0 = time.perf_counter()
+    Plan.from_csr(shifted, p_block=4).upload(dev)
+    torch.cuda.synchronize()
+    t_new = time.perf_counter() - t0
+    out["plan_cache"] = {**cache.stats(), "new_values_outcome": how, "new_values_ms": round(t_upd * 1e3, 1),
+                         "plan_and_upload_ms": round(t_new * 1e3, 1),
+                         "note": "catalogue planned through the cache (FP64 and FP32 plans per pattern); then "
+                                 "new values on the 100^3 pattern, refilled in place, against a fresh plan"}
+    log(f"plan cache: {out['plan_cache']}")
     for c in cat:
         del c["lo"]
+    cache.close()
     return out
 
 
@@ -447,6 +477,10 @@ def main():
     ap.add_argument("--no-cold", action="store_true", help="skip the cold-cache timing (profiler runs)")
     ap.add_argument("--serve-requests", type=int, default=512)
     ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-apply-workers", type=int, default=4,
+                    help="server workers that take matrix power requests only")
+    ap.add_argument("--serve-max-wait", type=float, default=0.1,
+                    help="aging bound (s) of the server's any-fit admission")
     ap.add_argument("--serve-load", type=float, default=0.8,
                     help="arrival rate as a fraction of the one-at-a-time service rate")
     ap.add_argument("--serve-pool-gib", type=int, default=8)

@@ -45,6 +45,7 @@ extern "C" {
 
 typedef struct mpk_plan_s* mpk_plan_t;     /* opaque; owned by the library */
 typedef struct mpk_server_s* mpk_server_t; /* opaque; owned by the library */
+typedef struct mpk_plan_cache_s* mpk_plan_cache_t; /* opaque; owned by the library */
 
 typedef enum {
     MPK_OK = 0,
@@ -256,6 +257,48 @@ mpk_status mpk_block_powers(mpk_plan_t plan, int32_t op, int32_t* q);
  * is allowed once earlier work on the plan has finished.
  */
 mpk_status mpk_upload(mpk_plan_t plan, void* dev_buf, size_t bytes, void* stream);
+
+/*
+ * New values for the matrix of a plan, with the sparsity pattern the plan was
+ * built from (n, rowptr, col identical; checked through a 128-bit hash of the
+ * pattern): the BFS levels, permutation, layout and schedule are kept (the
+ * preprocessing of Sec. 3 is amortised over calls on one pattern, Sec. 6) and
+ * only the values are refilled (column scaling and value storage type as at
+ * build) and, if the plan is uploaded, copied to its device buffer on
+ * `stream`, which is then synchronised.  Must not overlap other calls on the
+ * plan; earlier device work on the plan must have finished.
+ * Errors: MPK_ERR_ARG (null pointers, n or pattern differs), MPK_ERR_CSR,
+ * MPK_ERR_NOMEM, MPK_ERR_HIP.
+ */
+mpk_status mpk_update_values(mpk_plan_t plan, int32_t n, const int32_t* rowptr, const int32_t* col,
+                             const double* val, void* stream);
+
+/*
+ * ---- Plan cache ---------------------------------------------------------
+ * Plans keyed by the sparsity pattern of their matrix (a 128-bit hash of n,
+ * rowptr and col) and by the options that shape them, on the device current
+ * at mpk_plan_cache_create, within `device_bytes` of plan buffers (the cache
+ * allocates one buffer per plan when a pattern is first planned).
+ * mpk_plan_cache_get returns the cached, uploaded plan of the pattern
+ * (*outcome 0: same values; 1: new values, refilled as by mpk_update_values,
+ * allowed only while no other user holds the plan), or plans and uploads a new
+ * pattern (*outcome 2), evicting least recently used plans that no user holds
+ * when the budget requires.  Each get must be paired with
+ * mpk_plan_cache_release once the caller's work on the plan has finished; the
+ * plan belongs to the cache (never mpk_destroy it).  Thread-safe.
+ * Errors: MPK_ERR_ARG, MPK_ERR_CSR, MPK_ERR_STATE (new values for a plan in
+ * use), MPK_ERR_NOMEM (plan larger than the budget, or every plan in use),
+ * MPK_ERR_HIP, and those of mpk_build_levels / mpk_upload.
+ */
+mpk_status mpk_plan_cache_create(size_t device_bytes, mpk_plan_cache_t* out);
+mpk_status mpk_plan_cache_get(mpk_plan_cache_t cache, int32_t n, const int32_t* rowptr, const int32_t* col,
+                              const double* val, const mpk_options* opt, void* stream, mpk_plan_t* plan,
+                              int32_t* outcome);
+mpk_status mpk_plan_cache_release(mpk_plan_cache_t cache, mpk_plan_t plan);
+/* Plans held, device bytes used, and gets served by each outcome so far. */
+mpk_status mpk_plan_cache_stats(mpk_plan_cache_t cache, int32_t* plans, size_t* bytes_used, int64_t* hits,
+                                int64_t* value_updates, int64_t* misses);
+void mpk_plan_cache_destroy(mpk_plan_cache_t cache);
 
 /*
  * Device work-buffer size (bytes) that mpk_apply (call = MPK_CALL_APPLY),
@@ -596,12 +639,21 @@ void mpk_destroy(mpk_plan_t plan);
  * ---- Request server ----------------------------------------------------
  * Serves matrix power requests (mpk_apply), refinement solves
  * (mpk_refine_solve) and s-step GMRES solves (mpk_sstep_gmres) submitted from host memory by any number of host
- * threads, on the device that is current at mpk_server_create.  Each of
- * `workers` threads owns a HIP stream and runs one request at a time: copy
- * in, compute, copy out, mpk_check_device.  Requests are admitted in arrival
- * order; the oldest waiting request starts as soon as a worker is free and
- * its device memory fits in the server's pool of `device_bytes` (one
- * allocation made here, sub-allocated first-fit with 256-byte alignment).
+ * threads, on the device that is current at mpk_server_create.  Each worker
+ * thread owns a HIP stream and runs one request at a time: copy in, compute,
+ * copy out, mpk_check_device for its stream.  mpk_server_create_ex starts
+ * `workers` workers that take any request and `apply_workers` that take
+ * matrix power requests only (so that they never wait behind long solves).
+ * A free worker starts the oldest waiting request of its kind whose device
+ * memory fits in the server's pool of `device_bytes` (one allocation made
+ * here, sub-allocated first-fit with 256-byte alignment); younger requests
+ * that fit may start before an older one that does not, but once the oldest
+ * waiting request has waited more than `max_wait_s` and does not fit, no
+ * request starts until it does.  mpk_server_create(workers, device_bytes) is
+ * mpk_server_create_ex(workers, 0, device_bytes, 0): strict arrival order.
+ * Requests on matrices of fewer than 2^19 rows run the plain kernels (unless
+ * MPK_STAGED is asked for): their blocked launches would wait for the
+ * device-wide turn of persistent kernels; the results are the same bitwise.
  * Plans must stay alive and uploaded until their requests have been waited
  * for.  Host buffers passed to a submit call belong to the caller but must
  * stay valid, and unwritten by the caller, until mpk_server_wait returns for
@@ -610,6 +662,8 @@ void mpk_destroy(mpk_plan_t plan);
  * larger than the whole pool is refused at submit), MPK_ERR_HIP.
  */
 mpk_status mpk_server_create(int32_t workers, size_t device_bytes, mpk_server_t* out);
+mpk_status mpk_server_create_ex(int32_t workers, int32_t apply_workers, size_t device_bytes, double max_wait_s,
+                                mpk_server_t* out);
 
 /*
  * Queues Y(:, k-1) = y_k, k = 1..p, for x (host, n doubles) into Y (host,

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libmpk.so")
 SOURCES = [os.path.join(HERE, "csrc", "planner.cpp"), os.path.join(HERE, "csrc", "mpk.hip"),
-           os.path.join(HERE, "csrc", "server.cpp"), os.path.join(HERE, "csrc", "gmres.hip")]
+           os.path.join(HERE, "csrc", "server.cpp"), os.path.join(HERE, "csrc", "gmres.hip"),
+           os.path.join(HERE, "csrc", "cache.cpp")]
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-fvisibility=hidden",
     "--offload-arch=gfx950",

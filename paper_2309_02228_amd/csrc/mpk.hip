@@ -1217,6 +1217,31 @@ bool mpk::plans_match(mpk_plan_t a, mpk_plan_t b) {
     return a && b && a->H.n == b->H.n && a->H.nnz == b->H.nnz && a->H.perm == b->H.perm;
 }
 
+namespace {
+// B = A D^{-1} for column_scaling = MPK_SCALE_JACOBI: every value divided by its
+// column's diagonal entry, in FP64, into `scaled`, and *val pointed there.
+mpk_status column_scaled(int scaling, int32_t n, const int32_t* rowptr, const int32_t* col, const double** val,
+                         std::vector<double>& scaled) {
+    if (scaling != MPK_SCALE_JACOBI) return MPK_OK;
+    try {
+        std::vector<double> diag(n, 0.0);
+        for (int32_t i = 0; i < n; ++i) {
+            for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
+                if (col[e] == i) diag[i] = (*val)[e];
+            if (diag[i] == 0.0)
+                return fail(MPK_ERR_CSR, "row %d has no nonzero diagonal entry (needed by column_scaling)", i);
+        }
+        const int32_t nnz = n > 0 ? rowptr[n] : 0;
+        scaled.resize(nnz);
+        for (int32_t e = 0; e < nnz; ++e) scaled[e] = (*val)[e] / diag[col[e]];
+    } catch (const std::bad_alloc&) {
+        return fail(MPK_ERR_NOMEM, "out of host memory");
+    }
+    *val = scaled.data();
+    return MPK_OK;
+}
+}  // namespace
+
 MPK_API void mpk_options_default(mpk_options* opt) {
     if (opt) memset(opt, 0, sizeof *opt);
 }
@@ -1268,25 +1293,9 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
             if (!diag) return fail(MPK_ERR_CSR, "row %d has no nonzero diagonal entry (needed by split_lower)", i);
         }
     }
-    // B = A D^{-1}: every value divided by its column's diagonal entry, in FP64
     std::vector<double> scaled;
-    if (o.column_scaling == MPK_SCALE_JACOBI) {
-        try {
-            std::vector<double> diag(n, 0.0);
-            for (int32_t i = 0; i < n; ++i) {
-                for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e)
-                    if (col[e] == i) diag[i] = val[e];
-                if (diag[i] == 0.0)
-                    return fail(MPK_ERR_CSR, "row %d has no nonzero diagonal entry (needed by column_scaling)", i);
-            }
-            const int32_t nnz = n > 0 ? rowptr[n] : 0;
-            scaled.resize(nnz);
-            for (int32_t e = 0; e < nnz; ++e) scaled[e] = val[e] / diag[col[e]];
-        } catch (const std::bad_alloc&) {
-            return fail(MPK_ERR_NOMEM, "out of host memory");
-        }
-        val = scaled.data();
-    }
+    mpk_status sc = column_scaled(o.column_scaling, n, rowptr, col, &val, scaled);
+    if (sc != MPK_OK) return sc;
     mpk_plan_s* p = new (std::nothrow) mpk_plan_s;
     if (!p) return fail(MPK_ERR_NOMEM, "out of host memory");
     try {
@@ -1311,6 +1320,39 @@ MPK_API mpk_status mpk_build_levels(int32_t n, const int32_t* rowptr, const int3
     }
     if (device_bytes_out) *device_bytes_out = p->L.total;
     *plan_out = p;
+    return MPK_OK;
+}
+
+namespace {
+mpk_status upload_values(mpk_plan_t p, char* d, hipStream_t st);
+}
+
+MPK_API mpk_status mpk_update_values(mpk_plan_t p, int32_t n, const int32_t* rowptr, const int32_t* col,
+                                     const double* val, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (n != p->H.n) return fail(MPK_ERR_ARG, "n (%d) differs from the plan's (%d)", n, p->H.n);
+    if (!rowptr || (n > 0 && rowptr[n] > 0 && (!col || !val))) return fail(MPK_ERR_ARG, "null CSR array");
+    std::string why = mpk::validate_csr(n, rowptr, col);
+    if (!why.empty()) return fail(MPK_ERR_CSR, "%s", why.c_str());
+    uint64_t key[2];
+    mpk::pattern_hash(n, rowptr, col, key);
+    if (key[0] != p->H.pattern_key[0] || key[1] != p->H.pattern_key[1])
+        return fail(MPK_ERR_ARG, "the sparsity pattern differs from the plan's");
+    if (p->H.split_lower)
+        for (int32_t i = 0; i < n; ++i) {
+            bool diag = false;
+            for (int32_t e = rowptr[i]; e < rowptr[i + 1]; ++e) diag = diag || (col[e] == i && val[e] != 0.0);
+            if (!diag) return fail(MPK_ERR_CSR, "row %d has no nonzero diagonal entry (needed by split_lower)", i);
+        }
+    std::vector<double> scaled;
+    mpk_status s = column_scaled(p->column_scaling, n, rowptr, col, &val, scaled);
+    if (s != MPK_OK) return s;
+    try {
+        mpk::refill_values(p->H, rowptr, col, val);
+    } catch (const std::bad_alloc&) {
+        return fail(MPK_ERR_NOMEM, "out of host memory");
+    }
+    if (p->dev) return upload_values(p, p->dev, (hipStream_t)stream);
     return MPK_OK;
 }
 
@@ -1380,16 +1422,12 @@ MPK_API mpk_status mpk_plan_info(mpk_plan_t p, int64_t* n, int64_t* nnz, int32_t
     return MPK_OK;
 }
 
-MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* stream) {
-    if (!p) return fail(MPK_ERR_ARG, "null plan");
-    if (!dev_buf) return fail(MPK_ERR_ARG, "dev_buf is null");
-    if (((uintptr_t)dev_buf & 255) != 0) return fail(MPK_ERR_ARG, "dev_buf must be 256-byte aligned");
-    if (bytes < p->L.total)
-        return fail(MPK_ERR_NOMEM, "device buffer too small: %zu < %zu bytes", bytes, p->L.total);
-    hipStream_t st = (hipStream_t)stream;
+namespace {
+// Converts the plan's SELL values to their storage type and copies them (with
+// the BF16 row scales) into the bound device buffer on `st`; synchronises `st`.
+mpk_status upload_values(mpk_plan_t p, char* d, hipStream_t st) {
     const auto& H = p->H;
     const auto& L = p->L;
-    char* d = (char*)dev_buf;
     auto put = [&](size_t at, const void* src, size_t nb) -> hipError_t {
         if (nb == 0) return hipSuccess;
         return hipMemcpyAsync(d + at, src, nb, hipMemcpyHostToDevice, st);
@@ -1427,6 +1465,28 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     } else {
         HIP_TRY(put(L.val, H.sell_val.data(), H.sell_val.size() * 8));
     }
+    // the host vectors must outlive the asynchronous copies
+    HIP_TRY(hipStreamSynchronize(st));
+    return MPK_OK;
+}
+}  // namespace
+
+MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (!dev_buf) return fail(MPK_ERR_ARG, "dev_buf is null");
+    if (((uintptr_t)dev_buf & 255) != 0) return fail(MPK_ERR_ARG, "dev_buf must be 256-byte aligned");
+    if (bytes < p->L.total)
+        return fail(MPK_ERR_NOMEM, "device buffer too small: %zu < %zu bytes", bytes, p->L.total);
+    hipStream_t st = (hipStream_t)stream;
+    const auto& H = p->H;
+    const auto& L = p->L;
+    char* d = (char*)dev_buf;
+    auto put = [&](size_t at, const void* src, size_t nb) -> hipError_t {
+        if (nb == 0) return hipSuccess;
+        return hipMemcpyAsync(d + at, src, nb, hipMemcpyHostToDevice, st);
+    };
+    mpk_status vs = upload_values(p, d, st);
+    if (vs != MPK_OK) return vs;
     HIP_TRY(put(L.col, H.sell_col.data(), H.sell_col.size() * 4));
     HIP_TRY(put(L.off, H.chunk_off.data(), H.chunk_off.size() * 8));
     HIP_TRY(put(L.perm, H.perm.data(), H.perm.size() * 4));

@@ -165,11 +165,65 @@ int32_t pseudo_peripheral(const std::vector<int64_t>& ptr, const std::vector<int
     }
 }
 
+// The SELL-64 slots of every permuted row: its entries sorted by permuted
+// column.  With `pattern`, the columns (and the GS2 masks) are written too;
+// otherwise only the values (a plan of the same pattern with new values).
+void fill_sell(HostPlan& P, const int32_t* rowptr, const int32_t* col, const double* val, bool pattern) {
+    // rows write disjoint slots: threads take contiguous ranges of chunks
+    parallel_ranges(P.n, kChunkRows, kRowGrain, [&](int64_t i0, int64_t i1) {
+        std::vector<std::pair<int32_t, double>> row;
+        for (int32_t i = (int32_t)i0; i < (int32_t)i1; ++i) {
+            int32_t o = P.perm[i];
+            row.clear();
+            for (int32_t e = rowptr[o]; e < rowptr[o + 1]; ++e)
+                row.emplace_back(P.iperm[col[e]], val[e]);
+            std::sort(row.begin(), row.end(),
+                      [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
+                          return a.first < b.first;
+                      });
+            const int32_t c = i / kChunkRows, lane = i % kChunkRows;
+            for (size_t j = 0; j < row.size(); ++j) {
+                int64_t s = P.chunk_off[c] + (int64_t)j * kChunkRows + lane;
+                P.sell_val[s] = row[j].second;
+                if (!pattern) continue;
+                P.sell_col[s] = row[j].first;
+                if (P.split_lower) {
+                    if (P.perm[row[j].first] < o) P.lmask[i] |= 1u << j;
+                    if (row[j].first == i) P.dslot[i] = (int32_t)j;
+                }
+            }
+        }
+    });
+}
+
 }  // namespace
+
+void refill_values(HostPlan& P, const int32_t* rowptr, const int32_t* col, const double* val) {
+    std::fill(P.sell_val.begin(), P.sell_val.end(), 0.0);
+    fill_sell(P, rowptr, col, val, false);
+}
+
+void pattern_hash(int32_t n, const int32_t* rowptr, const int32_t* col, uint64_t out[2]) {
+    // two 64-bit multiply-xorshift chains with different odd multipliers over the
+    // row pointers and the column indices (a 128-bit key of the pattern)
+    uint64_t a = 0x243F6A8885A308D3ull ^ (uint64_t)n, b = 0x13198A2E03707344ull + (uint64_t)n;
+    auto mix = [&](uint64_t w) {
+        a = (a ^ w) * 0x9E3779B97F4A7C15ull;
+        a ^= a >> 29;
+        b = (b + w) * 0xBF58476D1CE4E5B9ull;
+        b ^= b >> 31;
+    };
+    for (int32_t i = 0; i <= n; ++i) mix((uint64_t)(uint32_t)rowptr[i]);
+    const int64_t nnz = n > 0 ? rowptr[n] : 0;
+    for (int64_t e = 0; e < nnz; ++e) mix(0x5555555555555555ull ^ (uint64_t)(uint32_t)col[e]);
+    out[0] = a;
+    out[1] = b;
+}
 
 void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* col,
                 const double* val) {
     P.n = n;
+    pattern_hash(n, rowptr, col, P.pattern_key);
     P.nnz = n ? rowptr[n] : 0;
 
     // ---- levels (readings R1-R3) ------------------------------------------
@@ -242,30 +296,7 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
         P.lmask.assign((size_t)P.nchunks * kChunkRows, 0u);
         P.dslot.assign((size_t)P.nchunks * kChunkRows, 0);
     }
-    // rows write disjoint slots: threads take contiguous ranges of chunks
-    parallel_ranges(n, kChunkRows, kRowGrain, [&](int64_t i0, int64_t i1) {
-        std::vector<std::pair<int32_t, double>> row;
-        for (int32_t i = (int32_t)i0; i < (int32_t)i1; ++i) {
-            int32_t o = P.perm[i];
-            row.clear();
-            for (int32_t e = rowptr[o]; e < rowptr[o + 1]; ++e)
-                row.emplace_back(P.iperm[col[e]], val[e]);
-            std::sort(row.begin(), row.end(),
-                      [](const std::pair<int32_t, double>& a, const std::pair<int32_t, double>& b) {
-                          return a.first < b.first;
-                      });
-            const int32_t c = i / kChunkRows, lane = i % kChunkRows;
-            for (size_t j = 0; j < row.size(); ++j) {
-                int64_t s = P.chunk_off[c] + (int64_t)j * kChunkRows + lane;
-                P.sell_col[s] = row[j].first;
-                P.sell_val[s] = row[j].second;
-                if (P.split_lower) {
-                    if (P.perm[row[j].first] < o) P.lmask[i] |= 1u << j;
-                    if (row[j].first == i) P.dslot[i] = (int32_t)j;
-                }
-            }
-        }
-    });
+    fill_sell(P, rowptr, col, val, true);
     // register slots: the smallest supported width covering every chunk, capped
     P.reg_slots = P.max_width <= 4 ? 4 : P.max_width <= 7 ? 7 : P.max_width <= 8 ? 8
                 : P.max_width <= 16 ? 16 : 32;

@@ -24,6 +24,7 @@ struct HostPlan {
     int64_t cache_bytes = 256ll << 20;  // C of the level groups (R14)
     int32_t min_group_rows = 0;         // row floor of a level group (R14)
     int32_t split_lower = 0;            // also record the strictly lower slots of each row
+    uint64_t pattern_key[2] = {0, 0};   // pattern_hash of the CSR the plan was built from
 
     // Sec. 3 level structure
     int32_t nlevels = 0;
@@ -74,6 +75,13 @@ std::vector<int32_t> group_levels(const HostPlan& P, int32_t q);
 
 // The tasks of one block of q powers in stage order, then k (R15).
 std::vector<StageTask> wavefront_schedule(const HostPlan& P, int32_t q);
+
+// Rewrites the SELL values of a plan from new values of the CSR pattern it was
+// built from (columns, levels and tables unchanged).
+void refill_values(HostPlan& P, const int32_t* rowptr, const int32_t* col, const double* val);
+
+// 128-bit key of a CSR pattern (n, row pointers, column indices).
+void pattern_hash(int32_t n, const int32_t* rowptr, const int32_t* col, uint64_t out[2]);
 
 // Validates the CSR input; returns an empty string or an error message.
 std::string validate_csr(int32_t n, const int32_t* rowptr, const int32_t* col);

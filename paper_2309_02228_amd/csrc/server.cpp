@@ -1,9 +1,13 @@
 // Request server of the MPK library: MPK applications, refinement solves and
-// s-step GMRES solves submitted from the host run on a pool of worker threads, each with its own
-// HIP stream, and are admitted in arrival order as soon as their device
-// memory fits in the server's budget.  Work of different requests overlaps on
-// the GPU; blocked (persistent) launches take turns, as everywhere in the
-// library, so that each has its waves resident together.
+// s-step GMRES solves submitted from the host run on worker threads, each with
+// its own HIP stream.  A waiting request is admitted as soon as a worker of its
+// lane is free and its device memory fits in the server's pool: matrix powers
+// have workers of their own, so short applications do not queue behind long
+// solves, and any waiting request that fits may start before older ones that
+// do not, until the oldest has waited longer than the aging bound (then the
+// pool is kept for it).  Work of different requests overlaps on the GPU;
+// blocked (persistent) launches take turns, as everywhere in the library, so
+// that each has its waves resident together.
 #include <hip/hip_runtime.h>
 
 #include <chrono>
@@ -26,6 +30,18 @@ namespace {
 
 using Clock = std::chrono::steady_clock;
 constexpr size_t kAlign = 256;
+// Requests on matrices with fewer rows run the plain kernels: a blocked launch
+// waits for the device-wide turn of persistent kernels (behind the launches of
+// concurrent solves), which costs small matrices more than blocking saves; the
+// results are the same bitwise.
+constexpr int32_t kSmallRows = 1 << 19;
+
+// The executor flags of a request: the caller's, with the plain kernels for
+// small matrices unless the staged executor was asked for.
+uint32_t exec_flags(uint32_t flags, int32_t n) {
+    if (n < kSmallRows && !(flags & MPK_STAGED)) flags |= MPK_PLAIN;
+    return flags;
+}
 
 size_t round_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
 
@@ -45,6 +61,13 @@ struct Pool {
             if (rest) free_[at] = rest;
             return true;
         }
+        return false;
+    }
+
+    bool fits(size_t n) const {
+        n = round_up(n);
+        for (const auto& kv : free_)
+            if (kv.second >= n) return true;
         return false;
     }
 
@@ -89,6 +112,8 @@ struct Request {
 
 struct mpk_server_s {
     int device = 0;
+    int apply_workers = 0;            // workers that take matrix-power requests only
+    double max_wait_s = 0.25;         // aging bound of any-fit admission
     Pool pool;
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
@@ -125,7 +150,7 @@ void execute(Request* r, char* d, hipStream_t st) {
         void* w = r->work ? (void*)(d + round_up(n * 8) + round_up(n * 8 * r->p)) : nullptr;
         if (!hip(hipMemcpyAsync(x, r->in, n * 8, hipMemcpyHostToDevice, st), "copy x")) return;
         const bool last = r->flags & MPK_LAST_POWER;
-        const uint32_t fl = r->flags & ~MPK_LAST_POWER;
+        const uint32_t fl = exec_flags(r->flags & ~MPK_LAST_POWER, r->n);
         if (!lib(mpk_apply(r->plan, x, Y, (int64_t)n, r->p, fl, w, r->work, st))) return;
         const double* from = last ? Y + n * (size_t)(r->p - 1) : Y;
         if (!hip(hipMemcpyAsync(r->out, from, n * 8 * (last ? 1 : r->p), hipMemcpyDeviceToHost, st), "copy Y"))
@@ -139,12 +164,13 @@ void execute(Request* r, char* d, hipStream_t st) {
         if (!hip(hipMemcpyAsync(x, r->out, n * 8, hipMemcpyHostToDevice, st), "copy x")) return;
         if (r->type == kSolve) {
             if (!lib(mpk_refine_solve(r->plan, r->lo, r->degree, r->lmin, r->lmax, b, x, r->tol, r->max_iter,
-                                      r->flags, w, r->work, &r->iters, &r->relres, st)))
+                                      exec_flags(r->flags, r->n), w, r->work, &r->iters, &r->relres, st)))
                 return;
         } else {
             int32_t cycles = 0;
             if (!lib(mpk_sstep_gmres(r->plan, r->lo, r->s, r->m, r->degree, r->lmin, r->lmax, b, x, r->tol,
-                                     r->max_iter, r->flags, w, r->work, &r->iters, &cycles, &r->relres, st)))
+                                     r->max_iter, exec_flags(r->flags, r->n), w, r->work, &r->iters, &cycles,
+                                     &r->relres, st)))
                 return;
         }
         if (!hip(hipMemcpyAsync(r->out, x, n * 8, hipMemcpyDeviceToHost, st), "copy x back")) return;
@@ -153,7 +179,28 @@ void execute(Request* r, char* d, hipStream_t st) {
     hip(hipStreamSynchronize(st), "synchronize");
 }
 
-void worker(mpk_server_s* S) {
+// Picks the request a worker of the given lane starts now (holding S->mu), or
+// null: the oldest waiting request of the lane whose device memory fits.  While
+// the oldest waiting request overall has waited longer than the aging bound and
+// its memory does not fit, no request is admitted, so that the pool fills up for
+// it; it is taken as soon as it fits by a worker of its lane.
+Request* admit(mpk_server_s* S, bool applies_only) {
+    if (S->queue.empty()) return nullptr;
+    Request* oldest = S->queue.front();
+    const bool aged = std::chrono::duration<double>(Clock::now() - oldest->t_submit).count() > S->max_wait_s;
+    if (aged && !S->pool.fits(oldest->bytes)) return nullptr;
+    for (auto it = S->queue.begin(); it != S->queue.end(); ++it) {
+        Request* r = *it;
+        if (applies_only && r->type != kApply) continue;
+        if (S->pool.alloc(r->bytes, &r->off)) {
+            S->queue.erase(it);
+            return r;
+        }
+    }
+    return nullptr;
+}
+
+void worker(mpk_server_s* S, bool applies_only) {
     hipSetDevice(S->device);
     hipStream_t st = nullptr;
     const hipError_t se = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
@@ -161,15 +208,14 @@ void worker(mpk_server_s* S) {
         Request* r = nullptr;
         {
             std::unique_lock<std::mutex> lk(S->mu);
-            // admission in arrival order: the oldest request starts as soon as its
-            // memory fits; later ones wait behind it
-            S->cv_work.wait(lk, [&] {
-                return (S->stop && S->queue.empty()) ||
-                       (!S->queue.empty() && S->pool.alloc(S->queue.front()->bytes, &S->queue.front()->off));
-            });
-            if (S->queue.empty()) break;
-            r = S->queue.front();
-            S->queue.pop_front();
+            for (;;) {
+                r = admit(S, applies_only);
+                if (r || (S->stop && S->queue.empty())) break;
+                // wake up at least every millisecond so that the aging bound is
+                // applied while nothing completes
+                S->cv_work.wait_for(lk, std::chrono::milliseconds(1));
+            }
+            if (!r) break;
         }
         r->t_start = Clock::now();
         if (se != hipSuccess) {
@@ -209,13 +255,19 @@ mpk_status submit(mpk_server_t S, Request* r, int64_t* ticket) {
 
 }  // namespace
 
-MPK_API mpk_status mpk_server_create(int32_t workers, size_t device_bytes, mpk_server_t* out) {
+MPK_API mpk_status mpk_server_create_ex(int32_t workers, int32_t apply_workers, size_t device_bytes,
+                                        double max_wait_s, mpk_server_t* out) {
     if (!out) return mpk::set_error(MPK_ERR_ARG, "out is null");
     *out = nullptr;
     if (workers < 1 || workers > 64) return mpk::set_error(MPK_ERR_ARG, "workers must be in 1..64");
+    if (apply_workers < 0 || apply_workers > 64)
+        return mpk::set_error(MPK_ERR_ARG, "apply_workers must be in 0..64");
+    if (!(max_wait_s >= 0.0)) return mpk::set_error(MPK_ERR_ARG, "max_wait_s must be >= 0");
     if (device_bytes < kAlign) return mpk::set_error(MPK_ERR_ARG, "device_bytes must be at least %zu", kAlign);
     auto* S = new (std::nothrow) mpk_server_s;
     if (!S) return mpk::set_error(MPK_ERR_NOMEM, "out of host memory");
+    S->apply_workers = apply_workers;
+    S->max_wait_s = max_wait_s;
     hipError_t e = hipGetDevice(&S->device);
     if (e == hipSuccess) e = hipMalloc((void**)&S->pool.base, device_bytes);
     if (e != hipSuccess) {
@@ -225,13 +277,20 @@ MPK_API mpk_status mpk_server_create(int32_t workers, size_t device_bytes, mpk_s
     S->pool.size = device_bytes / kAlign * kAlign;
     S->pool.free_[0] = S->pool.size;
     try {
-        for (int i = 0; i < workers; ++i) S->threads.emplace_back(worker, S);
+        for (int i = 0; i < workers; ++i) S->threads.emplace_back(worker, S, false);
+        for (int i = 0; i < apply_workers; ++i) S->threads.emplace_back(worker, S, true);
     } catch (const std::exception& ex) {  // no exception crosses the C ABI
         mpk_server_destroy(S);
         return mpk::set_error(MPK_ERR_NOMEM, "worker threads: %s", ex.what());
     }
     *out = S;
     return MPK_OK;
+}
+
+MPK_API mpk_status mpk_server_create(int32_t workers, size_t device_bytes, mpk_server_t* out) {
+    // strict arrival order (an aging bound of zero) and no lane of its own for
+    // matrix powers
+    return mpk_server_create_ex(workers, 0, device_bytes, 0.0, out);
 }
 
 MPK_API mpk_status mpk_server_submit_apply(mpk_server_t S, mpk_plan_t plan, const double* x, int32_t p, double* Y,

@@ -40,7 +40,8 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_server_submit_gmres", "mpk_jacobi_apply", "mpk_jacobi_work_bytes",
            "mpk_gs2_apply", "mpk_gs2_work_bytes", "mpk_sstep_gmres_ex",
            "mpk_set_block", "mpk_tune_block", "mpk_block_powers", "mpk_set_watchdog",
-           "poly_apply_static"]
+           "poly_apply_static", "mpk_update_values", "mpk_plan_cache_create", "mpk_plan_cache_get",
+           "mpk_plan_cache_release", "mpk_plan_cache_stats", "mpk_plan_cache_destroy", "mpk_server_create_ex"]
 
 
 class MPKError(RuntimeError):
@@ -86,6 +87,13 @@ def _load():
         "mpk_block_powers": (I32, [P, I32, pI32]),
         "mpk_set_watchdog": (I32, [P, I32]),
         "poly_apply_static": (I32, [P, I32, I32, P, P, D, D, U32, P]),
+        "mpk_update_values": (I32, [P, I32, P, P, P, P]),
+        "mpk_plan_cache_create": (I32, [SZ, ctypes.POINTER(P)]),
+        "mpk_plan_cache_get": (I32, [P, I32, P, P, P, P, P, ctypes.POINTER(P), pI32]),
+        "mpk_plan_cache_release": (I32, [P, P]),
+        "mpk_plan_cache_stats": (I32, [P, pI32, pSZ, pI64, pI64, pI64]),
+        "mpk_plan_cache_destroy": (None, [P]),
+        "mpk_server_create_ex": (I32, [I32, I32, SZ, ctypes.c_double, ctypes.POINTER(P)]),
         "mpk_upload": (I32, [P, P, SZ, P]),
         "mpk_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_apply": (I32, [P, D, D, I64, I32, U32, P, SZ, P]),
@@ -208,6 +216,17 @@ class Plan:
         if getattr(self, "_h", None) and _lib is not None:
             _lib.mpk_destroy(self._h)
             self._h = None
+
+    def update_values(self, A, stream=None):
+        """New values of the same sparsity pattern (CSR tuple A): levels and layout are
+        kept, the values refilled and, once uploaded, copied to the device."""
+        n, rowptr, col, val = A
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        st = _stream(stream) if self.buffer is not None or stream is not None else None
+        _check(_lib.mpk_update_values(self._h, int(n), _ptr(rowptr), _ptr(col), _ptr(val), st))
+        return self
 
     # ---------------------------------------------------------- host tables
     def levels(self):
@@ -449,14 +468,85 @@ class Plan:
         _check(_lib.mpk_check_device(self._h, _stream(stream)))
 
 
+class CachedPlan(Plan):
+    """A plan held by a PlanCache (not destroyed by Python; released to the cache)."""
+
+    def __init__(self, handle, n, cache, values):
+        self._h = handle
+        self.n = int(n)
+        self.values = values
+        self.column_scaling = None
+        self.buffer = None
+        self._cache = cache
+
+    def __del__(self):
+        pass  # the cache owns the plan
+
+    def release(self):
+        if self._h is not None:
+            _check(_lib.mpk_plan_cache_release(self._cache._h, self._h))
+            self._h = None
+
+
+class PlanCache:
+    """Plans keyed by sparsity pattern (mpk_plan_cache_*), on the current device,
+    within ``device_bytes`` of plan buffers."""
+
+    OUTCOMES = {0: "hit", 1: "new values", 2: "planned"}
+
+    def __init__(self, device_bytes=8 << 30):
+        h = ctypes.c_void_p()
+        _check(_lib.mpk_plan_cache_create(int(device_bytes), ctypes.byref(h)))
+        self._h = h
+
+    def get(self, A, values="f64", p_block=0, stream=None):
+        """(plan, outcome) for the CSR tuple A; release the plan when done with it."""
+        n, rowptr, col, val = A
+        rowptr = np.ascontiguousarray(rowptr, dtype=np.int32)
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        opt = Options()
+        _lib.mpk_options_default(ctypes.byref(opt))
+        opt.p_block = int(p_block)
+        opt.value_type = VALUE_TYPES[values]
+        h = ctypes.c_void_p()
+        out = ctypes.c_int32()
+        _check(_lib.mpk_plan_cache_get(self._h, int(n), _ptr(rowptr), _ptr(col), _ptr(val), ctypes.byref(opt),
+                                       _stream(stream), ctypes.byref(h), ctypes.byref(out)))
+        return CachedPlan(h, n, self, values), self.OUTCOMES[out.value]
+
+    def stats(self):
+        pl, used = ctypes.c_int32(), ctypes.c_size_t()
+        hits, upd, miss = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.mpk_plan_cache_stats(self._h, ctypes.byref(pl), ctypes.byref(used), ctypes.byref(hits),
+                                         ctypes.byref(upd), ctypes.byref(miss)))
+        return {"plans": pl.value, "bytes_used": used.value, "hits": hits.value, "value_updates": upd.value,
+                "misses": miss.value}
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.mpk_plan_cache_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+
 class Server:
     """Request server on the current device: host-memory MPK applications and
     refinement solves, run by ``workers`` threads with a stream each and
     admitted in arrival order against a device pool of ``device_bytes``."""
 
-    def __init__(self, workers=4, device_bytes=1 << 30):
+    def __init__(self, workers=4, device_bytes=1 << 30, apply_workers=0, max_wait_s=None):
+        """``workers`` take any request, ``apply_workers`` matrix powers only; with
+        ``max_wait_s`` (seconds) any waiting request that fits may start before older
+        ones until the oldest has waited that long; None is strict arrival order."""
         h = ctypes.c_void_p()
-        _check(_lib.mpk_server_create(int(workers), int(device_bytes), ctypes.byref(h)))
+        if apply_workers == 0 and max_wait_s is None:
+            _check(_lib.mpk_server_create(int(workers), int(device_bytes), ctypes.byref(h)))
+        else:
+            _check(_lib.mpk_server_create_ex(int(workers), int(apply_workers), int(device_bytes),
+                                             float(max_wait_s or 0.0), ctypes.byref(h)))
         self._h = h
         self._keep = {}  # ticket -> host arrays and plans the request uses
 

@@ -399,3 +399,17 @@ def test_block_cap_and_tuner_argument_errors_without_gpu():
     assert lib.mpk_tune_block(plan._h, 4, None, fake, 64, None, ctypes.byref(q), None) == -1   # null x
     assert lib.mpk_tune_block(plan._h, 4, fake, fake, 64, None, None, None) == -1              # null q_out
     assert lib.mpk_tune_block(plan._h, 4, fake, fake, 64, None, ctypes.byref(q), ctypes.byref(t)) == -6
+
+
+def test_update_values_checks_the_pattern():
+    A = S.laplacian_2d(20, 17)
+    plan = M.Plan.from_csr(A)
+    plan.update_values(S.CSR(A.n, A.rowptr, A.col, A.val * 2.0))  # same pattern: accepted (host only)
+    B = S.laplacian_2d(17, 20)  # same n and nnz, other pattern
+    assert B.n == A.n and B.col.size == A.col.size
+    with pytest.raises(M.MPKError, match="MPK_ERR_ARG"):
+        plan.update_values(B)
+    with pytest.raises(M.MPKError, match="MPK_ERR_ARG"):
+        plan.update_values(S.laplacian_2d(20, 18))
+    with pytest.raises(M.MPKError, match="MPK_ERR_CSR"):
+        plan.update_values(S.CSR(A.n, A.rowptr, A.col[::-1].copy(), A.val))

@@ -208,3 +208,88 @@ def test_request_errors_stay_with_their_request(problems):
             srv.wait(good)  # a ticket is waited for once
     finally:
         srv.close()
+
+
+def test_lanes_and_any_fit_admission_equal_alone(problems):
+    # one general worker, two workers for matrix powers, any-fit admission: the mix
+    # still equals the calls made alone bitwise
+    reqs = request_mix(problems, seed=21, napply=24, nsolve=2, ngmres=3)
+    want = expected(problems, reqs)
+    srv = Server(workers=1, apply_workers=2, device_bytes=256 << 20, max_wait_s=0.05)
+    try:
+        tickets = [submit(srv, problems, r) for r in reqs]
+        for r, t, w in zip(reqs, tickets, want):
+            check(r, srv.wait(t), w)
+    finally:
+        srv.close()
+
+
+def test_applies_do_not_wait_behind_a_solve(problems):
+    # a long GMRES solve holds the only general worker; matrix powers submitted after it
+    # run on the apply lane and finish first
+    lmin, lmax = problems["bounds"]
+    A, hi = problems["A"], problems["hi"]
+    b = S.uniform_vector(A.n, 61)
+    srv = Server(workers=1, apply_workers=1, device_bytes=256 << 20, max_wait_s=0.05)
+    try:
+        solve = srv.submit_gmres(hi, problems["lo"], b, 1, 200, 32, lmin, lmax, tol=1e-13, max_cycles=3)
+        applies = [srv.submit_apply(hi, S.uniform_vector(A.n, 62 + i), 3) for i in range(4)]
+        lat = [srv.wait(t)["latency_s"] for t in applies]
+        s = srv.wait(solve)
+    finally:
+        srv.close()
+    assert s["latency_s"] > 0.0
+    assert max(lat) < s["latency_s"], (lat, s["latency_s"])
+
+
+def test_plan_cache_hits_value_updates_and_eviction():
+    from paper_2309_02228_amd import PlanCache
+    A = S.laplacian_3d(30, 28, 26)
+    B = S.knn_graph_laplacian(20000, k=26, seed=2)
+    x = S.uniform_vector(A.n, 1)
+    cache = PlanCache(device_bytes=512 << 20)
+    try:
+        p1, how = cache.get(A)
+        assert how == "planned"
+        perm = p1.levels()["perm"].astype(np.int64)
+        xd = torch.tensor(x[perm], device=DEV)
+        y1 = p1.apply(xd, 4).cpu().numpy()
+        p2, how = cache.get(A)  # same pattern, same values
+        h1 = p1._h.value
+        assert how == "hit" and p2._h.value == h1
+        p1.release()
+        p2.release()
+        # same pattern, new values (a shifted stencil): refilled, equal to a fresh plan
+        A2 = S.CSR(A.n, A.rowptr, A.col, A.val * 0.5 + (A.col == np.repeat(np.arange(A.n), np.diff(A.rowptr))) * 3.0)
+        p3, how = cache.get(A2)
+        assert how == "new values" and p3._h.value == h1
+        fresh = Plan.from_csr(A2).upload(DEV)
+        assert np.array_equal(p3.apply(xd, 4).cpu().numpy(), fresh.apply(xd, 4).cpu().numpy())
+        assert not np.array_equal(p3.apply(xd, 4).cpu().numpy(), y1)
+        # a plan in use cannot take other values
+        with pytest.raises(MPKError, match="MPK_ERR_STATE"):
+            cache.get(A)
+        p3.release()
+        assert cache.stats() == {**cache.stats(), "plans": 1, "hits": 1, "value_updates": 1, "misses": 1}
+    finally:
+        cache.close()
+    # a budget for one plan: the second pattern evicts the first once it is released
+    one = Plan.from_csr(A).device_bytes
+    cache = PlanCache(device_bytes=max(one, Plan.from_csr(B).device_bytes) + 256)
+    try:
+        pa, _ = cache.get(A)
+        with pytest.raises(MPKError, match="MPK_ERR_NOMEM"):
+            cache.get(B)  # the only plan is in use
+        pa.release()
+        pb, how = cache.get(B)
+        assert how == "planned" and cache.stats()["plans"] == 1
+        xb = S.uniform_vector(B.n, 3)
+        permb = pb.levels()["perm"].astype(np.int64)
+        got = pb.apply(torch.tensor(xb[permb], device=DEV), 3).cpu().numpy()
+        back = np.empty_like(got)
+        back[:, permb] = got
+        ref = O.mpk(B, xb, 3)
+        assert np.all(np.linalg.norm(back - ref, axis=1) <= 1e-12 * np.linalg.norm(ref, axis=1))
+        pb.release()
+    finally:
+        cache.close()
