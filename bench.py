@@ -51,7 +51,7 @@ def load_traffic(sha):
         return None
     if t.get("kernel_source_sha256") != sha:
         return None
-    return t.get("hbm_bytes_per_launch")
+    return t.get("ea_bytes_per_launch")
 
 
 def cpu_child(grid, p, reps):
@@ -639,6 +639,9 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic,
+            "traffic_counts": "L2-miss (EA) bytes of FETCH_SIZE + WRITE_SIZE per launch, copy-calibrated; "
+                              "they include Infinity Cache hits (no MALL counter on gfx950), so they bound "
+                              "the HBM bytes from above",
             "kernel": "mpk_block_kernel" if key == "blocked" else "spmv_kernel",
             "bytes_per_launch": int(bytes_per_launch),
             "avg_launch_us": round(avg_launch * 1e6, 2),
