@@ -4,10 +4,34 @@
 #pragma once
 
 #include <cstdint>
+#include <memory>
+#include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 namespace mpk {
+
+// Allocator whose value construction leaves memory uninitialised: for large
+// arrays that are written in full, in parallel, right after they are sized.
+template <typename T>
+struct NoInit : std::allocator<T> {
+    template <typename U>
+    struct rebind {
+        using other = NoInit<U>;
+    };
+    NoInit() = default;
+    template <typename U>
+    NoInit(const NoInit<U>&) noexcept {}
+    template <typename U>
+    void construct(U* p) noexcept {
+        ::new ((void*)p) U;
+    }
+    template <typename U, typename... A>
+    void construct(U* p, A&&... a) {
+        ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
 
 constexpr int kChunkRows = 64;  // rows per chunk = lanes per wavefront
 constexpr int kParts = 8;       // XCD partitions of the MI355X
@@ -37,8 +61,8 @@ struct HostPlan {
     // SELL-64 layout of P A P^T
     int32_t nchunks = 0;
     std::vector<int64_t> chunk_off;  // nchunks + 1, slot offsets (multiples of 64)
-    std::vector<double> sell_val;    // slots
-    std::vector<int32_t> sell_col;   // slots, -1 = padding
+    std::vector<double, NoInit<double>> sell_val;    // slots
+    std::vector<int32_t, NoInit<int32_t>> sell_col;  // slots, -1 = padding
     int32_t max_width = 0;
     int32_t reg_slots = 8;  // slots per row the blocked kernel keeps in registers
     // with split_lower (rows of at most 32 slots): per permuted row, bit s of lmask is

@@ -90,12 +90,15 @@ def test_planner_levels_bit_exact_and_tables_match_design(name):
         assert plan.min_workers(q) == SM.min_workers(ref["owner"], ref["deps"], G, q), q
 
 
-@pytest.mark.parametrize("name", ["lap3d_52", "rand_nonsym_300k"])
+@pytest.mark.parametrize("name", ["lap3d_52", "rand_nonsym_300k", "knn_150k"])
 def test_planner_threaded_sizes_levels_bit_exact_and_tables_match_design(name):
     # large enough that the planner splits its table building over threads
-    # (2 and 4 ranges): the tables must not depend on that split
+    # (2 and 4 ranges) and, for the random and kNN patterns, searches BFS
+    # layers of more than 4096 rows with a team of threads: the tables must
+    # not depend on either
     A = {"lap3d_52": lambda: S.laplacian_3d(52),
-         "rand_nonsym_300k": lambda: S.random_pattern(300000, 2.5, 5)}[name]()
+         "rand_nonsym_300k": lambda: S.random_pattern(300000, 2.5, 5),
+         "knn_150k": lambda: S.knn_graph_laplacian(150000, k=26, seed=3)}[name]()
     assert A.n >= 2 << 16
     plan = M.Plan.from_csr(A, p_block=4)
     got = plan.levels()
@@ -104,6 +107,8 @@ def test_planner_threaded_sizes_levels_bit_exact_and_tables_match_design(name):
     assert np.array_equal(got["level_of_row"], ref["level"])
     assert np.array_equal(got["perm"], ref["perm"])
     assert np.array_equal(got["level_ptr"], ref["level_ptr"])
+    if name != "lap3d_52":
+        assert np.bincount(ref["level"]).max() > 4096
     assert np.array_equal(plan.partition()["owner"], ref["owner"])
     ptr, idx = plan.deps()
     assert ptr.size == len(ref["deps"]) + 1
@@ -187,6 +192,25 @@ def test_malformed_csr_rejected():
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, value_type=2)[0] == 0
     assert _build(3, [0, 1, 2, 3], [0, 1, 2], [1.0] * 3, value_type=1)[0] == 0
     assert _build(0, [0], [], [])[0] == 0                                  # empty matrix
+
+
+def test_malformed_csr_reports_the_first_bad_row_at_threaded_sizes():
+    # the check runs over row ranges in threads; the message names the first
+    # offending row, as a row-by-row scan would
+    n = 300000
+    rowptr = np.arange(n + 1, dtype=np.int32)
+    col = np.arange(n, dtype=np.int32)
+    col[150000] = n          # out of range
+    col[290000] = -1         # later, in another range
+    code, msg = _build(n, rowptr, col, np.ones(n))
+    assert code == -2 and "row 150000" in msg and "out of range" in msg
+    rp = rowptr.copy()
+    rp[200001] = rp[200000] - 1  # pointer decreases at row 200000, after the bad column
+    code, msg = _build(n, rp, col, np.ones(n))
+    assert code == -2 and "row 150000" in msg
+    col[150000] = 150000
+    code, msg = _build(n, rp, col, np.ones(n))
+    assert code == -2 and "rowptr decreases at row 200000" in msg
 
 
 def test_apply_argument_errors_without_gpu():
