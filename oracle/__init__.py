@@ -40,6 +40,9 @@ sparse iterative solvers on multi-core CPUs"):
 * ``spmv_lower``, ``gs2_precondition``, ``gs2_mpk`` -- Sec. 5.1 (two-stage
   Gauss-Seidel, one outer iteration from zero, gamma inner sweeps) in the
   right-preconditioned MPK, reading R21
+* ``gs2_smooth_residual`` -- Sec. 5.3, the AMG pre-smoother (outer GS2 sweeps in the
+  non-compact form, gamma = 0: Jacobi) followed by the residual the cycle needs next,
+  reading R23
 * ``interval_shifts``, ``sstep_gmres_precond`` -- s-step GMRES without a
   preconditioner or with the diagonal (Jacobi) one, a blocked Newton MPK per
   block of s vectors, reading R22

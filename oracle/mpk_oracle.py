@@ -13,6 +13,7 @@ pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_
          refine_solve, newton_basis, poly_monomial, poly_newton, poly_chebyshev,
          leja_order, chebyshev_scale, newton_shifts, cholqr_truncated, sstep_cycle, sstep_gmres,
          diagonal, jacobi_precondition, jacobi_mpk, spmv_lower, gs2_precondition, gs2_mpk,
+         gs2_smooth_residual,
          interval_shifts, sstep_gmres_precond,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          group_levels, wavefront_schedule, validate_schedule, run_schedule
@@ -130,6 +131,15 @@ READINGS = {
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
            "matrix.",
+    "R23": "AMG pre-smoother fused with the residual (Sec. 5.3): nu outer GS2 sweeps on "
+           "A x = b from a given x^0, then r = b - A x^nu. The paper names its GS2 listing "
+           "the non-compact form of Gauss-Seidel, x^{k+1} = x^k + (D + L)^{-1}(b - A x^k), "
+           "whose update x^{k+1} = x^k + g_gamma it prints; so for sweeps after the first "
+           "g_0 is read as D^{-1}(b - A x^k) (the residual, which the printed "
+           "D^{-1}(b - U x^k) equals only when x^k = 0), then g_j = g_0 - D^{-1} L g_{j-1}, "
+           "j = 1..gamma, x^{k+1} = x^k + g_gamma. gamma = 0 is the Jacobi smoother "
+           "x^{k+1} = x^k + D^{-1}(b - A x^k). With x^0 = 0 and nu = 1, x^1 is R21's "
+           "P^{-1} b.",
 }
 
 
@@ -605,6 +615,23 @@ def gs2_mpk(A, x, p, gamma):
         w = spmv(A, gs2_precondition(A, w, gamma))
         out[j] = w
     return out
+
+
+def gs2_smooth_residual(A, b, x0, sweeps, gamma):
+    """Reading R23, the pre-smoothing step of an AMG cycle (Sec. 5.3) with the GS2 smoother
+    of Sec. 5.1 and the residual that the cycle needs next: `sweeps` outer iterations of the
+    non-compact form, each g_0 = D^{-1}(b - A x), g_j = g_0 - D^{-1} L g_{j-1} (j = 1..gamma),
+    x = x + g_gamma; then r = b - A x.  Returns (x, r)."""
+    d = diagonal(A)
+    b = np.asarray(b, dtype=np.float64)
+    x = np.array(x0, dtype=np.float64)
+    for _ in range(sweeps):
+        g0 = (b - spmv(A, x)) / d
+        g = g0
+        for _ in range(gamma):
+            g = g0 - spmv_lower(A, g) / d
+        x = x + g
+    return x, b - spmv(A, x)
 
 
 def chebyshev_basis(A, x, d, theta, delta):
