@@ -786,7 +786,35 @@ def main():
                                       f"inner sweeps, 3D 7-point Laplacian {g}^3, blocks of up to 8 sub-powers",
                           **gs2}
         log("gs2: " + ", ".join(f"{kk}: {v['blocked_us']} us blocked, {v['speedup']}x" for kk, v in gs2.items()))
-        del plang
+        # AMG pre-smoothing fused with the residual (Sec. 5.3): nu outer GS2 sweeps on
+        # A x = b, then r = b - A x, as one chain of nu (gamma + 1) + 1 sub-powers; x carries
+        # over from call to call (the work per call does not depend on its values)
+        bg = plang.permute(torch.tensor(synth.uniform_vector(n, 1), device=dev), 0)
+        xs = torch.zeros_like(bg)
+        rs = torch.empty_like(bg)
+        sm = {}
+        for nu, gam in ((2, 1), (3, 1), (2, 2)):
+            t = {}
+            for plain_ in (False, True):
+                for _ in range(3):
+                    plang.gs2_smooth(bg, xs, nu, gam, r=rs, plain=plain_)
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(10):
+                    plang.gs2_smooth(bg, xs, nu, gam, r=rs, plain=plain_)
+                e1.record(stream)
+                e1.synchronize()
+                t[plain_] = e0.elapsed_time(e1) / 10 * 1e-3
+            plang.check()
+            sm[f"sweeps={nu},gamma={gam}"] = {"blocked_us": round(t[False] * 1e6, 1), "plain_us": round(t[True] * 1e6, 1),
+                                              "speedup": round(t[True] / t[False], 3),
+                                              "sub_powers": nu * (gam + 1) + 1}
+        out["gs2_smoother_residual"] = {
+            "workload": f"AMG pre-smoother fused with the residual: sweeps outer GS2 iterations (gamma inner) on "
+                        f"A x = b, then r = b - A x, 3D 7-point Laplacian {g}^3, blocks of up to 8 sub-powers "
+                        f"(q = {plang.block_powers('gs2_smooth')})", **sm}
+        log("smoother: " + ", ".join(f"{kk}: {v['blocked_us']} us blocked, {v['speedup']}x" for kk, v in sm.items()))
+        del plang, bg, xs, rs
         out["jacobi_mpk"] = {"workload": f"(A P^-1)^j x, j = 1..{p}, P^-1 = k Jacobi sweeps from zero, "
                                          f"3D 7-point Laplacian {g}^3, plan of A D^-1 with blocks of up to 8",
                              **jac}

@@ -221,8 +221,8 @@ mpk_status mpk_get_deps(mpk_plan_t plan, int64_t* ndeps, int32_t* dep_ptr, int32
  * out in sequence order; the bound W is the smallest value such that, for
  * every partition and unit position j >= W, the first chunk of unit j - W has
  * a smaller index than the first chunk of every unit within q-1 dependency
- * hops of unit j.  mpk_upload picks the largest q <= p_block whose bound is at
- * most half of the waves it launches.  1 <= q <= p_block.
+ * hops of unit j.  mpk_upload picks, per operator kind, the largest q <= p_block
+ * whose bound fits the waves it launches (mpk_block_powers).  1 <= q <= p_block.
  */
 mpk_status mpk_min_workers(mpk_plan_t plan, int32_t q, int32_t* workers_per_xcd);
 
@@ -235,6 +235,7 @@ mpk_status mpk_min_workers(mpk_plan_t plan, int32_t q, int32_t* workers_per_xcd)
 #define MPK_OP_NEWTON_BASIS 4     /* sstep_basis                                  */
 #define MPK_OP_JACOBI_CHAIN 5     /* mpk_jacobi_apply with k > 1                  */
 #define MPK_OP_GS2_CHAIN 6        /* mpk_gs2_apply                                */
+#define MPK_OP_GS2_SMOOTH 7       /* mpk_gs2_smooth                               */
 
 /*
  * Powers (or sub-powers of a chain) per blocked launch that calls of operator
@@ -570,6 +571,35 @@ mpk_status mpk_gs2_apply(mpk_plan_t plan, int32_t gamma, const double* x, double
 
 /* Work bytes mpk_gs2_apply needs for gamma, p powers and `flags`. */
 mpk_status mpk_gs2_work_bytes(mpk_plan_t plan, int32_t gamma, int32_t p, uint32_t flags, size_t* bytes);
+
+/*
+ * AMG pre-smoothing fused with the residual (Sec. 5.3: the last sub-power of the
+ * smoother's chain computes the residual the cycle needs next, so the matrix is
+ * reused once more).  Runs `sweeps` outer GS2 iterations on A x = b from the
+ * x^0 held in x, in the non-compact (residual-correction) form that the paper
+ * names for its GS2 listing (Sec. 5.1):
+ *   g_0 = D^{-1}(b - A x^k), g_r = g_0 - D^{-1} L g_{r-1} (r = 1..gamma),
+ *   x^{k+1} = x^k + g_gamma,
+ * then r = b - A x^sweeps.  gamma = 0 is the Jacobi smoother
+ * x^{k+1} = x^k + D^{-1}(b - A x^k); L is the strictly lower triangle of A in
+ * the original numbering.  The sweeps (gamma + 1 sub-powers each) and the
+ * residual run as one chain of sweeps * (gamma + 1) + 1 sub-powers, blocked
+ * across sweeps; each row keeps its sweep's start value, g_0, b_i and its
+ * diagonal entry in registers.  The plan must be built with split_lower = 1.
+ * b (device, n) is only read; x (device, n) holds x^0 on entry and the smoothed
+ * vector on return; r (device, n) receives the residual.  Perm space with
+ * MPK_IO_PERMUTED (the fast path), otherwise permuted through `work`.  work:
+ * device, 256-byte aligned, mpk_gs2_smooth_work_bytes(plan, gamma, flags) bytes.
+ * MPK_PLAIN / MPK_STAGED select the executor; all executors give bitwise equal
+ * results.  sweeps = 0 computes only r = b - A x.  Errors: MPK_ERR_ARG (plan
+ * without split_lower, gamma outside 0..16, sweeps outside 0..65536, null
+ * pointers, work too small or misaligned), MPK_ERR_STATE, MPK_ERR_HIP.
+ */
+mpk_status mpk_gs2_smooth(mpk_plan_t plan, int32_t gamma, int32_t sweeps, const double* b, double* x, double* r,
+                          uint32_t flags, void* work, size_t work_bytes, void* stream);
+
+/* Work bytes mpk_gs2_smooth needs for gamma and `flags`. */
+mpk_status mpk_gs2_smooth_work_bytes(mpk_plan_t plan, int32_t gamma, uint32_t flags, size_t* bytes);
 
 /*
  * p_opt of Sec. 3 (the powers per blocked launch, which the paper tunes over

@@ -57,8 +57,13 @@ constexpr int kStatusSlots = 64;  // per plan: one per calling stream (least rec
 // KIND_GS2: the GS2-preconditioned chain, gl = gamma + 2 sub-powers per power: r = 0
 // gives g_0 = D^{-1} w_{j-1}, r = 1..gamma the sweeps g_r = g_0 - D^{-1} L g_{r-1}, and
 // r = gamma + 1 closes the power with w_j = A g_gamma (also stored as output column j).
-enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2, KIND_JCHAIN = 3, KIND_GS2 = 4 };
-constexpr int kKinds = 5;
+// KIND_SMOOTH: the pre-smoother of an AMG cycle followed by its residual, gamma + 1
+// sub-powers per outer GS2 sweep on A z = b and a final sub-power b - A z (see
+// smooth_value); it reads the same lower masks and diagonal slots as KIND_GS2.
+enum Kind { KIND_MONO = 0, KIND_NEWTON = 1, KIND_CHEB = 2, KIND_JCHAIN = 3, KIND_GS2 = 4, KIND_SMOOTH = 5 };
+constexpr int kKinds = 6;
+// kinds whose rows keep the diagonal entry and the strictly lower mask (split plans)
+constexpr bool split_kind(int k) { return k == KIND_GS2 || k == KIND_SMOOTH; }
 
 // ------------------------------------------------------------------ device
 struct DevPlan {
@@ -89,6 +94,7 @@ struct Coefs {
     int jk;             // KIND_JCHAIN: sub-powers per link; KIND_GS2: sub-powers per power
     double jc;          // KIND_JCHAIN: coefficient of (B - I)^k at the end of a link
     int pinv;           // KIND_GS2: 1 = the chain applies P^{-1} only (a power closes with g_gamma)
+    int chain_len;      // KIND_SMOOTH: sub-powers of the whole chain (the last is the residual)
 };
 
 // GS2 sub-power r of a power from the row's full sum sA = (A g)_i, its strictly lower
@@ -101,6 +107,21 @@ __device__ __forceinline__ double gs2_value(double sA, double sL, double prev, d
     if (r < gl - 1 || pinv) return g0 - sL / d;
     if (lam == 0.0 && sig == 1.0) return sA;
     return fma(-lam, w0, sA) / sig;
+}
+
+// Sub-power r of an outer sweep of the GS2 pre-smoother (non-compact form, gl = gamma + 1
+// sub-powers per sweep) from the row's full sum sA = (A v)_i and strictly lower part
+// sL = (L v)_i of the previous sub-power's vector v, the sweep's start value z, the
+// diagonal entry d and b_i: r = 0 gives g_0 = (b - A z)_i / d (kept in g0), r >= 1 the
+// inner sweeps g_r = g_0 - (L g_{r-1})_i / d, and the sweep's last sub-power stores
+// z + g_gamma, the start of the next sweep.  The chain's final sub-power is the residual
+// b - A z of the smoothed vector.
+__device__ __forceinline__ double smooth_value(double sA, double sL, double z, double& g0, double d, double b, int r,
+                                               int gl, bool final) {
+    if (final) return b - sA;
+    const double g = r == 0 ? (b - sA) / d : g0 - sL / d;
+    if (r == 0) g0 = g;
+    return r == gl - 1 ? z + g : g;
 }
 
 __device__ __forceinline__ double load_coherent(const double* p) {
@@ -142,9 +163,11 @@ struct SpmvArgs {
     double c0;
     int gk;               // global power index of this launch
     const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link
-    const double* pow_in;   // KIND_GS2: the input w0 of the power
+    const double* pow_in;   // KIND_GS2: the input w0 of the power (KIND_SMOOTH: b)
     double* link_out;       // KIND_JCHAIN: output column j - 1 receives w_j
     int64_t link_ld;
+    double* z_io;           // KIND_SMOOTH: the current sweep's start z, rewritten as a sweep closes
+    double* res_out;        // KIND_SMOOTH: receives the residual of the final sub-power
     Coefs C;              // entry 0 describes this power
 };
 
@@ -233,10 +256,10 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
         const int row = c * kChunkRows + lane;
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
-        if constexpr (KIND == KIND_GS2) {
+        if constexpr (split_kind(KIND)) {
             const int r = (a.gk - 1) % a.C.jk;
             double sA = 0.0, sL = 0.0, d = 1.0;
-            if (r == 0) {  // g_0 = D^{-1} w: row-local, only the diagonal entry is read
+            if (r == 0 && KIND == KIND_GS2) {  // g_0 = D^{-1} w: row-local, only the diagonal entry is read
                 if (row < a.P.n)
                     d = decode<VT>(((const VT*)a.P.val)[off + (int64_t)a.P.dslot[row] * kChunkRows + lane],
                                    row_scale<VT>(a.P, row));
@@ -244,10 +267,19 @@ __global__ __launch_bounds__(kBlockThreads) void spmv_kernel(SpmvArgs a) {
                 row_sums_gs2<VT>(a.P, a.in, off, width, lane, row, sA, sL, d);
             }
             if (row < a.P.n) {
-                const double y = gs2_value(sA, sL, a.in[row], a.link_in[row], d, a.pow_in[row], r, a.C.jk, a.C.pinv,
-                                           a.C.lam[0], a.C.sig[0]);
-                a.out[row] = y;
-                if (r == a.C.jk - 1) a.link_out[(int64_t)((a.gk - 1) / a.C.jk) * a.link_ld + row] = y;
+                if constexpr (KIND == KIND_SMOOTH) {
+                    const bool fin = a.gk == a.C.chain_len;
+                    double g0 = a.link_in[row];
+                    const double y = smooth_value(sA, sL, a.z_io[row], g0, d, a.pow_in[row], r, a.C.jk, fin);
+                    a.out[row] = y;
+                    if (fin) a.res_out[row] = y;
+                    else if (r == a.C.jk - 1) a.z_io[row] = y;
+                } else {
+                    const double y = gs2_value(sA, sL, a.in[row], a.link_in[row], d, a.pow_in[row], r, a.C.jk,
+                                               a.C.pinv, a.C.lam[0], a.C.sig[0]);
+                    a.out[row] = y;
+                    if (r == a.C.jk - 1) a.link_out[(int64_t)((a.gk - 1) / a.C.jk) * a.link_ld + row] = y;
+                }
             }
             continue;
         }
@@ -289,9 +321,11 @@ struct BlockArgs {
     uint32_t epoch;
     int32_t* status;      // the calling stream's status slot: [0] code, [1] chunk, [2] power
     const double* link_in;  // KIND_JCHAIN: the chain's value at the start of the link of y_{base+1}
-    const double* pow_in;   // KIND_GS2: the input w0 of the power of y_{base+1}
+    const double* pow_in;   // KIND_GS2: the input w0 of the power of y_{base+1} (KIND_SMOOTH: b)
     double* link_out;       // KIND_JCHAIN: output column j - 1 receives w_j
     int64_t link_ld;
+    double* z_io;           // KIND_SMOOTH: the current sweep's start z, rewritten as a sweep closes
+    double* res_out;        // KIND_SMOOTH: receives the residual of the final sub-power
     Coefs C;
 };
 
@@ -418,15 +452,17 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
         double prev[G], prev2[G], acc[G], link0[G], w0[G];
         uint32_t lm[G];  // KIND_GS2: strictly lower slots of the row
         double dg[G];    // KIND_GS2: the row's diagonal entry
+        double zr[G];    // KIND_SMOOTH: the current sweep's start value
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const bool act = c[g] >= 0 && row[g] < a.P.n;
             prev[g] = (act && need_prev) ? a.in[row[g]] : 0.0;
-            link0[g] = ((KIND == KIND_JCHAIN || KIND == KIND_GS2) && act) ? a.link_in[row[g]] : 0.0;
-            w0[g] = (KIND == KIND_GS2 && act) ? a.pow_in[row[g]] : 0.0;
+            link0[g] = ((KIND == KIND_JCHAIN || split_kind(KIND)) && act) ? a.link_in[row[g]] : 0.0;
+            w0[g] = (split_kind(KIND) && act) ? a.pow_in[row[g]] : 0.0;
             lm[g] = 0u;
             dg[g] = 1.0;
-            if (KIND == KIND_GS2 && act) {
+            zr[g] = (KIND == KIND_SMOOTH && act) ? a.z_io[row[g]] : 0.0;
+            if (split_kind(KIND) && act) {
                 lm[g] = a.P.lmask[row[g]];
                 dg[g] = decode<VT>(val[off[g] + (int64_t)a.P.dslot[row[g]] * kChunkRows + lane], rsc[g]);
             }
@@ -478,7 +514,7 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                         // instead of letting the compiler hoist a widened copy
                         if constexpr (sizeof(VT) < 8) asm volatile("" : "+v"(r));
                         s[g] = fma(decode<VT>(r, rsc[g]), xv[j], s[g]);
-                        if (KIND == KIND_GS2 && ((lm[g] >> j) & 1u)) sl[g] = fma(decode<VT>(r, rsc[g]), xv[j], sl[g]);
+                        if (split_kind(KIND) && ((lm[g] >> j) & 1u)) sl[g] = fma(decode<VT>(r, rsc[g]), xv[j], sl[g]);
                     }
             }
             // slots beyond the register cache, streamed at every power in batches
@@ -508,7 +544,7 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                     for (int t = 0; t < kTB; ++t)
                         if (cj[t] >= 0) {
                             s[g] = fma(vj[t], xj[t], s[g]);
-                            if (KIND == KIND_GS2 && j0 + t < 32 && ((lm[g] >> (j0 + t)) & 1u))
+                            if (split_kind(KIND) && j0 + t < 32 && ((lm[g] >> (j0 + t)) & 1u))
                                 sl[g] = fma(vj[t], xj[t], sl[g]);
                         }
                 }
@@ -517,7 +553,18 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
 #pragma unroll
             for (int g = 0; g < G; ++g) {
                 double y;
-                if constexpr (KIND == KIND_GS2) {
+                if constexpr (KIND == KIND_SMOOTH) {
+                    const int r = (a.base + kl) % a.C.jk;
+                    const bool act = c[g] >= 0 && row[g] < a.P.n;
+                    const bool fin = a.base + kl + 1 == a.C.chain_len;
+                    y = smooth_value(s[g], sl[g], zr[g], link0[g], dg[g], w0[g], r, a.C.jk, fin);
+                    if (fin) {
+                        if (act) a.res_out[row[g]] = y;
+                    } else if (r == a.C.jk - 1) {
+                        zr[g] = y;  // the next sweep starts here
+                        if (act) a.z_io[row[g]] = y;
+                    }
+                } else if constexpr (KIND == KIND_GS2) {
                     const int r = (a.base + kl) % a.C.jk;
                     if (r == 0) w0[g] = prev[g];  // the power's input
                     y = gs2_value(s[g], sl[g], prev[g], link0[g], dg[g], w0[g], r, a.C.jk, a.C.pinv, a.C.lam[kl],
@@ -582,6 +629,8 @@ struct StageArgs {
     double c0;
     double* link_out;  // KIND_JCHAIN: output column j - 1 receives w_j
     int64_t link_ld;
+    double* z_io;      // KIND_SMOOTH: the current sweep's start z, rewritten as a sweep closes
+    double* res_out;   // KIND_SMOOTH: receives the residual of the final sub-power
     Coefs C;
 };
 
@@ -599,10 +648,10 @@ __global__ __launch_bounds__(kBlockThreads) void stage_kernel(StageArgs a) {
         const int row = c * kChunkRows + lane;
         const int64_t off = a.P.off[c];
         const int width = (int)((a.P.off[c + 1] - off) / kChunkRows);
-        if constexpr (KIND == KIND_GS2) {
+        if constexpr (split_kind(KIND)) {
             const int r = (T.gk - 1) % a.C.jk;
             double sA = 0.0, sL = 0.0, d = 1.0;
-            if (r == 0) {  // g_0 = D^{-1} w: row-local, only the diagonal entry is read
+            if (r == 0 && KIND == KIND_GS2) {  // g_0 = D^{-1} w: row-local, only the diagonal entry is read
                 if (row < a.P.n)
                     d = decode<VT>(((const VT*)a.P.val)[off + (int64_t)a.P.dslot[row] * kChunkRows + lane],
                                    row_scale<VT>(a.P, row));
@@ -610,10 +659,19 @@ __global__ __launch_bounds__(kBlockThreads) void stage_kernel(StageArgs a) {
                 row_sums_gs2<VT>(a.P, T.in, off, width, lane, row, sA, sL, d);
             }
             if (row >= T.r0 && row < T.r1) {
-                const double y = gs2_value(sA, sL, T.in[row], T.link_in[row], d, T.pow_in[row], r, a.C.jk, a.C.pinv,
-                                           a.C.lam[T.kl], a.C.sig[T.kl]);
-                T.out[row] = y;
-                if (r == a.C.jk - 1) a.link_out[(int64_t)((T.gk - 1) / a.C.jk) * a.link_ld + row] = y;
+                if constexpr (KIND == KIND_SMOOTH) {
+                    const bool fin = T.gk == a.C.chain_len;
+                    double g0 = T.link_in[row];
+                    const double y = smooth_value(sA, sL, a.z_io[row], g0, d, T.pow_in[row], r, a.C.jk, fin);
+                    T.out[row] = y;
+                    if (fin) a.res_out[row] = y;
+                    else if (r == a.C.jk - 1) a.z_io[row] = y;
+                } else {
+                    const double y = gs2_value(sA, sL, T.in[row], T.link_in[row], d, T.pow_in[row], r, a.C.jk,
+                                               a.C.pinv, a.C.lam[T.kl], a.C.sig[T.kl]);
+                    T.out[row] = y;
+                    if (r == a.C.jk - 1) a.link_out[(int64_t)((T.gk - 1) / a.C.jk) * a.link_ld + row] = y;
+                }
             }
             continue;
         }
@@ -848,6 +906,7 @@ template <int G, typename VT>
 BlockFn pick_block_g(int reg, int kind, bool poly) {
     if (kind == KIND_JCHAIN) return block_fn<G, KIND_JCHAIN, false, VT>(reg);  // never polynomial
     if (kind == KIND_GS2) return block_fn<G, KIND_GS2, false, VT>(reg);
+    if (kind == KIND_SMOOTH) return block_fn<G, KIND_SMOOTH, false, VT>(reg);
     if (kind == KIND_MONO)
         return poly ? block_fn<G, KIND_MONO, true, VT>(reg) : block_fn<G, KIND_MONO, false, VT>(reg);
     if (kind == KIND_NEWTON)
@@ -873,6 +932,7 @@ template <typename VT>
 SpmvFn pick_spmv_vt(int kind, bool poly) {
     if (kind == KIND_JCHAIN) return spmv_kernel<KIND_JCHAIN, false, VT>;
     if (kind == KIND_GS2) return spmv_kernel<KIND_GS2, false, VT>;
+    if (kind == KIND_SMOOTH) return spmv_kernel<KIND_SMOOTH, false, VT>;
     if (kind == KIND_MONO) return poly ? spmv_kernel<KIND_MONO, true, VT> : spmv_kernel<KIND_MONO, false, VT>;
     if (kind == KIND_NEWTON) return poly ? spmv_kernel<KIND_NEWTON, true, VT> : spmv_kernel<KIND_NEWTON, false, VT>;
     return poly ? spmv_kernel<KIND_CHEB, true, VT> : spmv_kernel<KIND_CHEB, false, VT>;
@@ -883,6 +943,7 @@ template <typename VT>
 StageFn pick_stage_vt(int kind, bool poly) {
     if (kind == KIND_JCHAIN) return stage_kernel<KIND_JCHAIN, false, VT>;
     if (kind == KIND_GS2) return stage_kernel<KIND_GS2, false, VT>;
+    if (kind == KIND_SMOOTH) return stage_kernel<KIND_SMOOTH, false, VT>;
     if (kind == KIND_MONO) return poly ? stage_kernel<KIND_MONO, true, VT> : stage_kernel<KIND_MONO, false, VT>;
     if (kind == KIND_NEWTON)
         return poly ? stage_kernel<KIND_NEWTON, true, VT> : stage_kernel<KIND_NEWTON, false, VT>;
@@ -1009,6 +1070,9 @@ struct PowerJob {
     double jc = 0;              // KIND_JCHAIN: coefficient of (B - I)^k closing a link
     double* link_out = nullptr; // KIND_JCHAIN: w_j (j = 1..p / jk) at link_out + (j-1) * link_ld
     int64_t link_ld = 0;
+    const double* rhs = nullptr; // KIND_SMOOTH: b
+    double* z_io = nullptr;     // KIND_SMOOTH: z at the start of the current sweep (in/out)
+    double* res_out = nullptr;  // KIND_SMOOTH: the residual of the final sub-power
 };
 
 double* job_dest(const PowerJob& j, int k) { return j.out0 + (int64_t)((k - 1) % j.mod) * j.ld; }
@@ -1018,16 +1082,19 @@ const double* job_vec(const PowerJob& j, int k) { return k == 0 ? j.x : job_dest
 // first sub-power; any valid vector when k is itself that first sub-power).
 const double* link_start(const PowerJob& j, int k) {
     const int t = (k - 1) / j.jk * j.jk;
-    if (j.kind == KIND_GS2) return t + 1 < k ? job_dest(j, t + 1) : job_vec(j, t);
+    if (split_kind(j.kind)) return t + 1 < k ? job_dest(j, t + 1) : job_vec(j, t);
     return t == 0 ? j.x : j.link_out + (int64_t)(t / j.jk - 1) * j.link_ld;
 }
 // KIND_GS2: the input of the power that holds sub-power k (x, or the ring slot of the
-// previous power's closing sub-power)
-const double* power_start(const PowerJob& j, int k) { return job_vec(j, (k - 1) / j.jk * j.jk); }
+// previous power's closing sub-power); the smoother: b
+const double* power_start(const PowerJob& j, int k) {
+    return j.kind == KIND_SMOOTH ? j.rhs : job_vec(j, (k - 1) / j.jk * j.jk);
+}
 void set_chain(const PowerJob& j, Coefs& C) {
     C.jk = j.jk;
     C.jc = j.jc;
     C.pinv = j.pinv;
+    C.chain_len = j.p;
 }
 
 const std::vector<mpk::StageTask>& schedule(mpk_plan_t p, int q) {
@@ -1054,6 +1121,8 @@ mpk_status run_staged(mpk_plan_t p, hipStream_t st, const PowerJob& j) {
             set_chain(j, a.C);
             a.link_out = j.link_out;
             a.link_ld = j.link_ld;
+            a.z_io = j.z_io;
+            a.res_out = j.res_out;
             int total = 0;
             size_t t1 = t0;
             for (; t1 < tasks.size() && tasks[t1].stage == tasks[t0].stage; ++t1) {
@@ -1062,8 +1131,8 @@ mpk_status run_staged(mpk_plan_t p, hipStream_t st, const PowerJob& j) {
                 StageTaskDev& d = a.t[a.ntasks++];
                 d.in = job_vec(j, gk - 1);
                 d.prev2 = (j.kind == KIND_CHEB && gk >= 2) ? job_vec(j, gk - 2) : nullptr;
-                d.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, gk) : nullptr;
-                d.pow_in = j.kind == KIND_GS2 ? power_start(j, gk) : nullptr;
+                d.link_in = (j.kind == KIND_JCHAIN || split_kind(j.kind)) ? link_start(j, gk) : nullptr;
+                d.pow_in = split_kind(j.kind) ? power_start(j, gk) : nullptr;
                 d.out = job_dest(j, gk);
                 d.r0 = T.row_begin;
                 d.r1 = T.row_end;
@@ -1101,10 +1170,12 @@ mpk_status plain_power(mpk_plan_t p, hipStream_t st, const PowerJob& j, int k) {
     a.C.theta = j.theta;
     a.C.delta = j.delta;
     set_chain(j, a.C);
-    a.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, k) : nullptr;
-    a.pow_in = j.kind == KIND_GS2 ? power_start(j, k) : nullptr;
+    a.link_in = (j.kind == KIND_JCHAIN || split_kind(j.kind)) ? link_start(j, k) : nullptr;
+    a.pow_in = split_kind(j.kind) ? power_start(j, k) : nullptr;
     a.link_out = j.link_out;
     a.link_ld = j.link_ld;
+    a.z_io = j.z_io;
+    a.res_out = j.res_out;
     if (k == 1 && j.copy0) {
         HIP_TRY(hipMemcpyAsync(j.copy0, j.x, sizeof(double) * p->H.n, hipMemcpyDeviceToDevice, st));
     }
@@ -1165,10 +1236,12 @@ mpk_status run_powers(mpk_plan_t p, hipStream_t st, const PowerJob& j, bool plai
         a.C.theta = j.theta;
         a.C.delta = j.delta;
         set_chain(j, a.C);
-        a.link_in = (j.kind == KIND_JCHAIN || j.kind == KIND_GS2) ? link_start(j, base + 1) : nullptr;
-        a.pow_in = j.kind == KIND_GS2 ? power_start(j, base + 1) : nullptr;
+        a.link_in = (j.kind == KIND_JCHAIN || split_kind(j.kind)) ? link_start(j, base + 1) : nullptr;
+        a.pow_in = split_kind(j.kind) ? power_start(j, base + 1) : nullptr;
         a.link_out = j.link_out;
         a.link_ld = j.link_ld;
+        a.z_io = j.z_io;
+        a.res_out = j.res_out;
         mpk_status s = launch_block(p, st, j.kind, j.poly, a);
         if (s != MPK_OK) return s;
     }
@@ -1395,9 +1468,10 @@ MPK_API mpk_status mpk_min_workers(mpk_plan_t p, int32_t q, int32_t* w) {
 
 MPK_API mpk_status mpk_block_powers(mpk_plan_t p, int32_t op, int32_t* q) {
     if (!p || !q) return fail(MPK_ERR_ARG, "null argument");
-    static const int kind_of[7] = {KIND_MONO, KIND_MONO, KIND_NEWTON, KIND_CHEB, KIND_NEWTON, KIND_JCHAIN, KIND_GS2};
-    static const int poly_of[7] = {0, 1, 1, 1, 0, 0, 0};
-    if (op < 0 || op > 6) return fail(MPK_ERR_ARG, "unknown operator kind %d", op);
+    static const int kind_of[8] = {KIND_MONO,   KIND_MONO,  KIND_NEWTON, KIND_CHEB,
+                                   KIND_NEWTON, KIND_JCHAIN, KIND_GS2,    KIND_SMOOTH};
+    static const int poly_of[8] = {0, 1, 1, 1, 0, 0, 0, 0};
+    if (op < 0 || op > 7) return fail(MPK_ERR_ARG, "unknown operator kind %d", op);
     mpk_status s = check_uploaded(p);
     if (s != MPK_OK) return s;
     const int qe = p->q_eff[kind_of[op]][poly_of[op]];
@@ -2003,6 +2077,78 @@ MPK_API mpk_status mpk_gs2_apply(mpk_plan_t p, int32_t gamma, const double* x, d
     s = mpk::gs2_chain(p, gamma, xin, yout, yld, pw, nullptr, nullptr, 0, flags, w, work_bytes, stream);
     if (s != MPK_OK) return s;
     if (!permuted) s = permute_vecs(p, st, yout, ld, Y, ldy, pw, 1);
+    return s;
+}
+
+MPK_API mpk_status mpk_gs2_smooth_work_bytes(mpk_plan_t p, int32_t gamma, uint32_t flags, size_t* bytes) {
+    if (!p || !bytes) return fail(MPK_ERR_ARG, "null argument");
+    if (gamma < 0 || gamma > 16) return fail(MPK_ERR_ARG, "gamma must be in 0..16 (got %d)", gamma);
+    const size_t v = (size_t)(p->H.n + 31) / 32 * 32 * 8;  // one vector, 256-byte multiple
+    // the ring of the GS2 chain, the chain's own copy of x^0, and in original row
+    // order the level-order z, b and r
+    const size_t ring = (size_t)(p->H.p_block + gamma + 2);
+    *bytes = v * (ring + 1 + ((flags & MPK_IO_PERMUTED) ? 0 : 3));
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_gs2_smooth(mpk_plan_t p, int32_t gamma, int32_t sweeps, const double* b, double* x, double* r,
+                                  uint32_t flags, void* work, size_t work_bytes, void* stream) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (!p->H.split_lower) return fail(MPK_ERR_ARG, "the plan must be built with split_lower = 1");
+    if (gamma < 0 || gamma > 16) return fail(MPK_ERR_ARG, "gamma must be in 0..16 (got %d)", gamma);
+    if (sweeps < 0 || sweeps > (1 << 16)) return fail(MPK_ERR_ARG, "sweeps must be in 0..65536 (got %d)", sweeps);
+    if (p->H.n > 0 && (!b || !x || !r)) return fail(MPK_ERR_ARG, "b, x or r is null");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return fail(MPK_ERR_ARG, "unknown flag bits");
+    size_t need = 0;
+    mpk_gs2_smooth_work_bytes(p, gamma, flags, &need);
+    if (!work || work_bytes < need) return fail(MPK_ERR_ARG, "work buffer too small: %zu < %zu bytes", work_bytes, need);
+    if (((uintptr_t)work) & 255) return fail(MPK_ERR_ARG, "work must be 256-byte aligned");
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    const int32_t n = p->H.n;
+    if (n == 0) return MPK_OK;
+    hipStream_t st = (hipStream_t)stream;
+    const bool permuted = flags & MPK_IO_PERMUTED;
+    const int64_t ld = (n + 31) / 32 * 32;
+    double* w = (double*)work;
+    const int ring = p->H.p_block + gamma + 2;
+    // The chain reads x^0 from its own copy: with gamma = 0 a row closes its first
+    // sweep (writing z) while a neighbour may still be gathering x^0.
+    double* x0 = w + (int64_t)ring * ld;
+    const double* bb = b;
+    double* z = x;
+    double* rr = r;
+    if (!permuted) {
+        double* zp = x0 + ld;
+        double* bp = zp + ld;
+        double* rp = bp + ld;
+        s = permute_vecs(p, st, x, 0, x0, 0, 1, 0);
+        if (s == MPK_OK) s = permute_vecs(p, st, b, 0, bp, 0, 1, 0);
+        if (s != MPK_OK) return s;
+        HIP_TRY(hipMemcpyAsync(zp, x0, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        bb = bp;
+        z = zp;
+        rr = rp;
+    } else {
+        HIP_TRY(hipMemcpyAsync(x0, x, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    }
+    PowerJob j;
+    j.kind = KIND_SMOOTH;
+    j.p = sweeps * (gamma + 1) + 1;
+    j.x = x0;
+    j.out0 = w;
+    j.ld = ld;
+    j.mod = ring;
+    j.jk = gamma + 1;
+    j.rhs = bb;
+    j.z_io = z;
+    j.res_out = rr;
+    s = run_powers(p, st, j, flags & MPK_PLAIN, flags & MPK_STAGED);
+    if (s != MPK_OK) return s;
+    if (!permuted) {
+        s = permute_vecs(p, st, z, ld, x, n, 1, 1);
+        if (s == MPK_OK) s = permute_vecs(p, st, rr, ld, r, n, 1, 1);
+    }
     return s;
 }
 

@@ -21,7 +21,7 @@ VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}  # bf16: BF16 values with a per-ro
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
 # operator kinds of mpk_block_powers
 OPS = {"powers": 0, "poly_monomial": 1, "poly_newton": 2, "poly_chebyshev": 3, "newton_basis": 4,
-       "jacobi_chain": 5, "gs2_chain": 6}
+       "jacobi_chain": 5, "gs2_chain": 6, "gs2_smooth": 7}
 PRECONDS = {"chebyshev": 0, "none": 1, "jacobi": 2, "gs2": 3}  # right preconditioners of sstep_gmres
 CALL_APPLY, CALL_POLY, CALL_SSTEP, CALL_SOLVE = 0, 1, 2, 3
 
@@ -41,7 +41,8 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_gs2_apply", "mpk_gs2_work_bytes", "mpk_sstep_gmres_ex",
            "mpk_set_block", "mpk_tune_block", "mpk_block_powers", "mpk_set_watchdog",
            "poly_apply_static", "mpk_update_values", "mpk_plan_cache_create", "mpk_plan_cache_get",
-           "mpk_plan_cache_release", "mpk_plan_cache_stats", "mpk_plan_cache_destroy", "mpk_server_create_ex"]
+           "mpk_plan_cache_release", "mpk_plan_cache_stats", "mpk_plan_cache_destroy", "mpk_server_create_ex",
+           "mpk_gs2_smooth", "mpk_gs2_smooth_work_bytes"]
 
 
 class MPKError(RuntimeError):
@@ -122,6 +123,8 @@ def _load():
         "mpk_jacobi_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_gs2_apply": (I32, [P, I32, P, P, I64, I32, U32, P, SZ, P]),
         "mpk_gs2_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
+        "mpk_gs2_smooth": (I32, [P, I32, I32, P, P, P, U32, P, SZ, P]),
+        "mpk_gs2_smooth_work_bytes": (I32, [P, I32, U32, pSZ]),
         "mpk_set_block": (I32, [P, I32]),
         "mpk_tune_block": (I32, [P, I32, P, P, I64, P, pI32, ctypes.POINTER(ctypes.c_double)]),
         "mpk_server_submit_gmres": (I32, [P, P, P, P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double,
@@ -405,6 +408,22 @@ class Plan:
         _check(_lib.mpk_gs2_apply(self._h, int(gamma), _dptr(x), _dptr(Y), Y.stride(0), int(p), flags, _dptr(w),
                                   w.numel() * 8, _stream(stream)))
         return Y
+
+    def gs2_smooth(self, b, x, sweeps, gamma, r=None, permuted=True, plain=False, staged=False, stream=None):
+        """AMG pre-smoothing fused with the residual: ``sweeps`` outer GS2 iterations
+        (``gamma`` inner sweeps; 0 is Jacobi) on A x = b from x, which is overwritten with
+        the result, then r = b - A x.  Returns (x, r); the plan must be built with
+        split_lower=True."""
+        import torch
+        if r is None:
+            r = torch.empty_like(b)
+        flags = self._flags(permuted, plain, staged)
+        nb = ctypes.c_size_t()
+        _check(_lib.mpk_gs2_smooth_work_bytes(self._h, int(gamma), flags, ctypes.byref(nb)))
+        w = torch.empty(nb.value // 8 + 64, dtype=torch.float64, device=b.device)
+        _check(_lib.mpk_gs2_smooth(self._h, int(gamma), int(sweeps), _dptr(b), _dptr(x), _dptr(r), flags, _dptr(w),
+                                   w.numel() * 8, _stream(stream)))
+        return x, r
 
     def gmres_work_bytes(self, s, m, degree, permuted=True):
         nb = ctypes.c_size_t()

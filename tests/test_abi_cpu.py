@@ -410,6 +410,32 @@ def test_gs2_split_plan_and_apply_argument_errors_without_gpu():
     assert lib.mpk_gs2_apply(split._h, 2, fake, fake, 64, 4, 1, fake, need, None) == -6    # not uploaded
 
 
+def test_gs2_smooth_argument_errors_without_gpu():
+    lib = M.lib()
+    A = S.laplacian_2d(8)
+    plain = M.Plan.from_csr(A)
+    split = M.Plan.from_csr(A, split_lower=True)
+    nb = ctypes.c_size_t()
+    assert lib.mpk_gs2_smooth_work_bytes(split._h, 2, 1, ctypes.byref(nb)) == 0 and nb.value > 0
+    need_perm = nb.value
+    assert lib.mpk_gs2_smooth_work_bytes(split._h, 2, 0, ctypes.byref(nb)) == 0 and nb.value > need_perm
+    assert lib.mpk_gs2_smooth_work_bytes(split._h, -1, 1, ctypes.byref(nb)) == -1
+    assert lib.mpk_gs2_smooth_work_bytes(split._h, 17, 1, ctypes.byref(nb)) == -1
+    need = need_perm
+    fake = ctypes.c_void_p(1 << 20)
+    assert lib.mpk_gs2_smooth(plain._h, 1, 2, fake, fake, fake, 1, fake, need, None) == -1   # not split
+    assert lib.mpk_gs2_smooth(split._h, 17, 2, fake, fake, fake, 1, fake, need, None) == -1  # gamma
+    assert lib.mpk_gs2_smooth(split._h, 1, -1, fake, fake, fake, 1, fake, need, None) == -1  # sweeps
+    assert lib.mpk_gs2_smooth(split._h, 1, 1 << 17, fake, fake, fake, 1, fake, need, None) == -1
+    assert lib.mpk_gs2_smooth(split._h, 1, 2, None, fake, fake, 1, fake, need, None) == -1   # null b
+    assert lib.mpk_gs2_smooth(split._h, 1, 2, fake, fake, None, 1, fake, need, None) == -1   # null r
+    assert lib.mpk_gs2_smooth(split._h, 1, 2, fake, fake, fake, 64, fake, need, None) == -1  # flag bit
+    assert lib.mpk_gs2_smooth(split._h, 2, 2, fake, fake, fake, 1, fake, need - 8, None) == -1  # work
+    assert lib.mpk_gs2_smooth(split._h, 2, 2, fake, fake, fake, 1, ctypes.c_void_p((1 << 20) + 8), need,
+                              None) == -1                                                   # misaligned
+    assert lib.mpk_gs2_smooth(split._h, 2, 2, fake, fake, fake, 1, fake, need, None) == -6    # not uploaded
+
+
 def test_block_cap_and_tuner_argument_errors_without_gpu():
     lib = M.lib()
     plan = M.Plan.from_csr(S.laplacian_2d(8))
