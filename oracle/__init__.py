@@ -43,6 +43,8 @@ sparse iterative solvers on multi-core CPUs"):
 * ``gs2_smooth_residual`` -- Sec. 5.3, the AMG pre-smoother (outer GS2 sweeps in the
   non-compact form, gamma = 0: Jacobi) followed by the residual the cycle needs next,
   reading R23
+* ``arnoldi``, ``ritz_shifts`` -- Sec. 4, Newton shifts from the Ritz values of a few
+  standard Arnoldi (GMRES) steps, reading R24
 * ``interval_shifts``, ``sstep_gmres_precond`` -- s-step GMRES without a
   preconditioner or with the diagonal (Jacobi) one, a blocked Newton MPK per
   block of s vectors, reading R22

@@ -14,7 +14,7 @@ pinned   spmv, mpk, round_values, round_values_bf16_rowscale, chebyshev_inverse_
          leja_order, chebyshev_scale, newton_shifts, cholqr_truncated, sstep_cycle, sstep_gmres,
          diagonal, jacobi_precondition, jacobi_mpk, spmv_lower, gs2_precondition, gs2_mpk,
          gs2_smooth_residual,
-         interval_shifts, sstep_gmres_precond,
+         interval_shifts, sstep_gmres_precond, arnoldi, ritz_shifts,
          pattern_graph, bfs_levels, level_permutation, permute_symmetric,
          group_levels, wavefront_schedule, validate_schedule, run_schedule
          (pins: exact integer arithmetic, closed-form Laplacian eigenpairs,
@@ -131,6 +131,16 @@ READINGS = {
            "value is rounded once to the nearest FP32 value (ties to even); vectors, "
            "products and sums stay FP64, so the result is the FP64 MPK of the rounded "
            "matrix.",
+    "R24": "Newton shifts from Ritz values (Sec. 4: shifts from a few steps of standard "
+           "GMRES): s steps of standard Arnoldi (Alg. 3b's one-vector-at-a-time subspace "
+           "generation) on M from q0 = r0 / ||r0|| of the first cycle, stopped early if the "
+           "Krylov space becomes invariant (a new vector's norm at most 2^-48 of ||M q_j||); "
+           "the Ritz values are the eigenvalues of the square Hessenberg matrix. The shifts "
+           "are their real parts (a complex pair gives its common real part twice, which keeps "
+           "the basis real; the paper's shifts are real) in the Leja order of R18, repeated "
+           "cyclically when fewer than s were found, kept for the whole solve; every column is "
+           "scaled by a quarter of the spread of the shifts (the capacity of the interval they "
+           "span; |shift| or 1 when they coincide).",
     "R23": "AMG pre-smoother fused with the residual (Sec. 5.3): nu outer GS2 sweeps on "
            "A x = b from a given x^0, then r = b - A x^nu. The paper names its GS2 listing "
            "the non-compact form of Gauss-Seidel, x^{k+1} = x^k + (D + L)^{-1}(b - A x^k), "
@@ -440,6 +450,42 @@ def sstep_cycle(apply_M, q0, m, s, lambdas, sigmas, beta, target):
             return Q[:max(c, 1)], H, y, rho
 
 
+def arnoldi(apply_M, q0, k):
+    """Standard Arnoldi on ``apply_M`` from the unit vector q0 (the one-vector-at-a-time
+    subspace generation of Alg. 3b, modified Gram-Schmidt), k steps, stopped when the
+    Krylov space becomes invariant (reading R24).  Returns (Q, H) with Q the j + 1
+    orthonormal vectors (rows) and H the (j + 1) x j Hessenberg matrix, M Q[:j] = Q H; on an
+    early stop H is j x j (M Q = Q H) and Q holds j vectors."""
+    Q = [np.asarray(q0, dtype=np.float64)]
+    H = np.zeros((k + 1, k))
+    for j in range(k):
+        w = apply_M(Q[j])
+        wn = float(np.linalg.norm(w))
+        for i in range(j + 1):
+            H[i, j] = float(Q[i] @ w)
+            w = w - H[i, j] * Q[i]
+        H[j + 1, j] = float(np.linalg.norm(w))
+        if not H[j + 1, j] > 2.0 ** -48 * wn:
+            return np.array(Q), H[: j + 1, : j + 1]
+        Q.append(w / H[j + 1, j])
+    return np.array(Q), H
+
+
+def ritz_shifts(apply_M, q0, s):
+    """Reading R24: Newton shifts from the Ritz values of s Arnoldi steps on M from q0:
+    the real parts of the eigenvalues of the square Hessenberg matrix in Leja order (R18),
+    repeated cyclically up to s, each column scaled by a quarter of their spread.
+    Returns (lambdas, sigmas)."""
+    Q, H = arnoldi(apply_M, q0, s)
+    k = H.shape[1]
+    theta = np.linalg.eigvals(H[:k, :k])
+    lam = leja_order(np.real(theta))
+    lam = np.array([lam[i % lam.size] for i in range(s)])
+    spread = float(lam.max() - lam.min())
+    sig = spread / 4.0 if spread > 0.0 else (abs(float(lam[0])) if lam[0] != 0.0 else 1.0)
+    return lam, np.full(s, sig)
+
+
 def interval_shifts(s, lo, hi):
     """Reading R22: Newton shifts for an operator whose spectrum lies in [lo, hi]: the s
     Chebyshev points of the interval in Leja order, every column scaled by a quarter of
@@ -457,7 +503,8 @@ def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, va
     Jacobi preconditioner is k sweeps (R20), applied through B = A D^{-1} whose diagonal is
     one: M = jacobi_mpk(B) = I - (I - B)^k and x = x0 + D^{-1} jacobi_precondition(B, Q y).
     [lmin, lmax] holds the
-    spectrum of M, the shifts are those of interval_shifts, and the cycle is sstep_cycle.
+    spectrum of M, the shifts are those of interval_shifts, and the cycle is sstep_cycle;
+    with lmin = lmax = None the shifts are ritz_shifts of the first cycle's q0 (R24).
     With ``values`` the basis and the preconditioner use the rounded matrix.
     Returns (x, history, iters)."""
     if precond not in ("none", "jacobi", "gs2"):
@@ -478,7 +525,8 @@ def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, va
     else:
         def apply_M(w):
             return spmv(Mlo, w)
-    lambdas, sigmas = interval_shifts(s, lmin, lmax)
+    ritz = lmin is None and lmax is None
+    lambdas, sigmas = (None, None) if ritz else interval_shifts(s, lmin, lmax)
     b = np.asarray(b, dtype=np.float64)
     x = np.array(x0, dtype=np.float64)
     nb = float(np.linalg.norm(b))
@@ -489,6 +537,8 @@ def sstep_gmres_precond(A, b, x0, s, m, precond, lmin, lmax, tol, max_cycles, va
         hist.append(beta / nb if nb > 0 else beta)
         if hist[-1] <= tol or cyc == max_cycles or beta == 0.0:
             break
+        if lambdas is None:
+            lambdas, sigmas = ritz_shifts(apply_M, r / beta, s)
         Q, H, y, rho = sstep_cycle(apply_M, r / beta, m, s, lambdas, sigmas, beta, tol * nb)
         iters += H.shape[1]
         z = np.zeros_like(x)

@@ -361,3 +361,102 @@ def test_jacobi_k_sweeps_cycle_equals_textbook_gmres(k, s, m):
     x_ref = P @ textbook_gmres_cycle(M, b, m)
     assert iters == m
     np.testing.assert_allclose(x1, x_ref, rtol=0, atol=1e-9 * np.abs(x_ref).max())
+
+
+# ---- Newton shifts from Ritz values (reading R24) ---------------------------------------
+def test_arnoldi_relation_and_orthonormal_basis():
+    # M Q[:k] = Q H with Q orthonormal, on a nonsymmetric dense operator
+    A = S.random_pattern(40, 5, 3, symmetric=False)
+    M = dense(A)
+    q0 = S.uniform_vector(40, 1)
+    q0 = q0 / np.linalg.norm(q0)
+    Q, H = O.arnoldi(lambda v: M @ v, q0, 8)
+    assert Q.shape == (9, 40) and H.shape == (9, 8)
+    np.testing.assert_allclose(Q @ Q.T, np.eye(9), atol=1e-12)
+    np.testing.assert_allclose(M @ Q[:8].T, Q.T @ H, atol=1e-11)
+    assert np.all(np.tril(H, -2) == 0.0)
+
+
+@pytest.mark.parametrize("k", [3, 6])
+def test_ritz_values_are_eigenvalues_of_the_projected_operator(k):
+    # independent construction: an orthonormal basis of the Krylov space from numpy's QR
+    # of [q0, M q0, ..., M^{k-1} q0]; the Ritz values are the eigenvalues of V^T M V
+    # catches: eigenvalues of a rectangular or shifted block of H, a transposed H
+    A = S.random_pattern(30, 4, 5, symmetric=False)
+    M = dense(A)
+    M[np.arange(30), np.arange(30)] += 3.0
+    q0 = S.uniform_vector(30, 2)
+    q0 = q0 / np.linalg.norm(q0)
+    K = np.empty((30, k))
+    K[:, 0] = q0
+    for j in range(1, k):
+        K[:, j] = M @ K[:, j - 1]
+    V, _ = np.linalg.qr(K)
+    ref = np.linalg.eigvals(V.T @ M @ V)
+    lam, sig = O.ritz_shifts(lambda v: M @ v, q0, k)
+    np.testing.assert_allclose(np.sort(lam), np.sort(ref.real), rtol=1e-9, atol=1e-10)
+    assert np.allclose(sig, (lam.max() - lam.min()) / 4)
+
+
+def test_ritz_shifts_on_a_diagonal_operator_are_its_entries_in_leja_order():
+    # s = n distinct entries: the Krylov space is everything, the Ritz values are exact
+    d = np.array([0.5, 3.0, 1.25, 2.0, 4.5, 0.75])
+    q0 = np.ones(6) / math.sqrt(6)
+    lam, sig = O.ritz_shifts(lambda v: d * v, q0, 6)
+    np.testing.assert_allclose(lam, O.leja_order(d), rtol=1e-10)
+    assert lam[0] == pytest.approx(4.5) and sig[0] == pytest.approx((4.5 - 0.5) / 4)
+
+
+def test_ritz_shifts_stop_on_an_invariant_subspace_and_repeat():
+    # three distinct eigenvalues: Arnoldi stops after three steps with the exact values,
+    # and the shifts repeat them cyclically
+    d = np.array([1.0, 1.0, 2.0, 2.0, 5.0, 5.0])
+    q0 = np.ones(6) / math.sqrt(6)
+    Q, H = O.arnoldi(lambda v: d * v, q0, 5)
+    assert H.shape == (3, 3)
+    lam, _ = O.ritz_shifts(lambda v: d * v, q0, 5)
+    np.testing.assert_allclose(lam, [5.0, 1.0, 2.0, 5.0, 1.0], rtol=1e-10)
+
+
+def test_symmetric_operator_gives_a_tridiagonal_hessenberg():
+    A = S.laplacian_2d(7, 6)
+    M = dense(A)
+    q0 = S.uniform_vector(42, 3)
+    q0 = q0 / np.linalg.norm(q0)
+    _, H = O.arnoldi(lambda v: M @ v, q0, 8)
+    assert np.abs(np.triu(H, 2)).max() < 1e-12
+
+
+def test_complex_pairs_give_their_real_part():
+    # a rotation block [[1, -2], [2, 1]] and a real eigenvalue 4: Ritz values 1 +- 2i, 4
+    M = np.array([[1.0, -2.0, 0.0], [2.0, 1.0, 0.0], [0.0, 0.0, 4.0]])
+    q0 = np.array([1.0, 1.0, 1.0]) / math.sqrt(3)
+    lam, sig = O.ritz_shifts(lambda v: M @ v, q0, 3)
+    np.testing.assert_allclose(lam, [4.0, 1.0, 1.0], rtol=1e-10)
+    assert sig[0] == pytest.approx(0.75)
+
+
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
+def test_gmres_with_ritz_shifts_solves_knn_laplacian(precond):
+    # no spectrum interval given: the shifts come from the first cycle's Arnoldi steps;
+    # the converged solution against SciPy's direct solve
+    A = S.knn_graph_laplacian(1500, seed=2)
+    n, rp, c, v = A
+    b = S.uniform_vector(n, 5)
+    x, hist, iters = O.sstep_gmres_precond(A, b, np.zeros(n), 8, 48, precond, None, None, 1e-10, 80)
+    ref = spla.spsolve(csr_matrix((v, c, rp), shape=(n, n)).tocsc(), b)
+    assert hist[-1] <= 1e-10
+    assert np.linalg.norm(x - ref) <= 2e-10 * 2000 * np.linalg.norm(ref)
+
+
+def test_one_cycle_with_ritz_shifts_equals_textbook_gmres():
+    # GMRES's iterate depends on the Krylov space only, not on the shifts of its basis
+    A = S.random_pattern(60, 5, 11, symmetric=False)
+    Ad = dense(A)
+    Ad[np.arange(60), np.arange(60)] = 1.0 + np.abs(Ad).sum(axis=1)
+    A = S.from_dense(Ad)
+    b = S.uniform_vector(60, 4)
+    x1, hist, iters = O.sstep_gmres_precond(A, b, np.zeros(60), 4, 12, "none", None, None, 0.0, 1)
+    u = textbook_gmres_cycle(Ad, b, 12)
+    assert iters == 12
+    np.testing.assert_allclose(x1, u, rtol=0, atol=1e-9 * np.abs(u).max())
