@@ -65,6 +65,8 @@ typedef enum {
 #define MPK_STAGED 4u      /* the level-group wavefront of Sec. 3 (see
                               mpk_get_schedule): one launch per stage, same
                               per-row arithmetic; ignored with MPK_PLAIN       */
+#define MPK_RITZ_SHIFTS 16u /* mpk_sstep_gmres_ex only: Newton shifts from Ritz values
+                               (see there) instead of a spectrum interval */
 #define MPK_LAST_POWER 8u  /* mpk_server_submit_apply only: Y receives y_p alone
                               (n doubles) instead of all p powers                */
 
@@ -493,13 +495,33 @@ mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, i
  * A D^{-1}; k > 1 with one Jacobi chain of s k sub-powers (mpk_jacobi_apply)
  * with the shifts applied as each link closes, and x = x0 + D^{-1}
  * sum_{i<k} (I - A D^{-1})^i Q y.  `degree` is unused by MPK_PRECOND_NONE
- * (pass 1); lmin may be <= 0 for all but Chebyshev.  Errors as mpk_sstep_gmres, plus MPK_ERR_ARG for an unknown
- * preconditioner or a `lo` plan of the wrong form.
+ * (pass 1); lmin may be <= 0 for all but Chebyshev.  With MPK_RITZ_SHIFTS in
+ * flags (not for MPK_PRECOND_CHEBYSHEV) lmin and lmax are ignored and the shifts
+ * come from Ritz values, as Sec. 4 takes them from a few steps of standard GMRES:
+ * the first cycle runs s Arnoldi steps on M from r0 / ||r0|| (classical
+ * Gram-Schmidt with one reorthogonalisation, stopping early on an invariant
+ * space), the eigenvalues of the square Hessenberg matrix are the Ritz values,
+ * and their real parts in Leja order (repeated cyclically when fewer than s were
+ * found) are the shifts of the whole solve, each column scaled by a quarter of
+ * their spread.  Errors as mpk_sstep_gmres, plus MPK_ERR_ARG for an unknown
+ * preconditioner, a `lo` plan of the wrong form or MPK_RITZ_SHIFTS with the
+ * Chebyshev preconditioner, and MPK_ERR_UNSUPPORTED if the Ritz values' QR
+ * iteration does not converge.
  */
 mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t precond, int32_t s, int32_t m, int32_t degree,
                               double lmin, double lmax, const double* b, double* x, double tol,
                               int32_t max_cycles, uint32_t flags, void* work, size_t work_bytes,
                               int32_t* iters_out, int32_t* cycles_out, double* relres_out, void* stream);
+
+/*
+ * Eigenvalues of the k x k upper Hessenberg matrix H (host, column-major, leading
+ * dimension ldh >= k; entries below the subdiagonal are ignored), e.g. the Ritz
+ * values of an Arnoldi run (Sec. 4: Newton shifts from Ritz values): re[i] + i im[i],
+ * i < k, in no particular order.  Shifted QR iteration in complex arithmetic, host
+ * only.  Errors: MPK_ERR_ARG (k outside 0..512, ldh < k, null pointers),
+ * MPK_ERR_UNSUPPORTED (no convergence), MPK_ERR_NOMEM.
+ */
+mpk_status mpk_ritz_values(const double* H, int64_t ldh, int32_t k, double* re, double* im);
 
 /* Device work bytes that mpk_sstep_gmres or mpk_sstep_gmres_ex needs for these
  * arguments (n, s, m, d and MPK_IO_PERMUTED in flags; the same for every

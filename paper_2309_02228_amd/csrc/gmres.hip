@@ -19,8 +19,10 @@
 
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstdint>
 #include <cstring>
+#include <limits>
 #include <new>
 #include <vector>
 
@@ -244,6 +246,91 @@ std::vector<double> least_squares(const std::vector<double>& H, int rows, int co
     return y;
 }
 
+// ------------------------------------------------------------------ host helpers
+using cplx = std::complex<double>;
+
+// Eigenvalues of the k x k upper Hessenberg matrix A (column-major, leading dimension
+// k; overwritten) by the shifted QR algorithm in complex arithmetic: a Wilkinson
+// shift from the trailing 2 x 2 block of the active part, one QR step as Givens
+// rotations of neighbouring rows followed by their adjoints from the right, and
+// deflation where a subdiagonal entry is negligible against its diagonal neighbours.
+// Returns false if one eigenvalue takes more than 64 steps.
+bool hessenberg_eigenvalues(std::vector<cplx>& A, int k, std::vector<cplx>& ev) {
+    auto at = [&](int i, int j) -> cplx& { return A[(size_t)j * k + i]; };
+    const double eps = std::numeric_limits<double>::epsilon();
+    ev.assign(k, cplx(0.0, 0.0));
+    std::vector<cplx> cs(k), sn(k);
+    int hi = k - 1, steps = 0;
+    while (hi >= 0) {
+        int lo = hi;
+        for (; lo > 0; --lo) {
+            const double scale = std::abs(at(lo - 1, lo - 1)) + std::abs(at(lo, lo));
+            if (std::abs(at(lo, lo - 1)) <= eps * (scale > 0.0 ? scale : 1.0)) {
+                at(lo, lo - 1) = 0.0;
+                break;
+            }
+        }
+        if (lo == hi) {  // a 1 x 1 block: an eigenvalue
+            ev[hi] = at(hi, hi);
+            --hi;
+            steps = 0;
+            continue;
+        }
+        if (++steps > 64) return false;
+        const cplx a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+        const cplx half = 0.5 * (a + d), disc = std::sqrt(half * half - (a * d - b * c));
+        cplx mu = std::abs(half + disc - d) < std::abs(half - disc - d) ? half + disc : half - disc;
+        if (steps % 11 == 10) mu = d + std::abs(c);  // an exceptional shift breaks a cycle
+        for (int j = lo; j <= hi; ++j) at(j, j) -= mu;
+        for (int j = lo; j < hi; ++j) {  // R = G_{hi-1} ... G_lo (A - mu I)
+            const cplx x = at(j, j), y = at(j + 1, j);
+            const double r = std::hypot(std::abs(x), std::abs(y));
+            const cplx c_ = r > 0.0 ? x / r : cplx(1.0, 0.0), s_ = r > 0.0 ? y / r : cplx(0.0, 0.0);
+            for (int col = j; col <= hi; ++col) {
+                const cplx u = at(j, col), v = at(j + 1, col);
+                at(j, col) = std::conj(c_) * u + std::conj(s_) * v;
+                at(j + 1, col) = -s_ * u + c_ * v;
+            }
+            cs[j] = c_;
+            sn[j] = s_;
+        }
+        for (int j = lo; j < hi; ++j)  // R G_lo^H ... G_{hi-1}^H
+            for (int row = lo; row <= j + 1; ++row) {
+                const cplx u = at(row, j), v = at(row, j + 1);
+                at(row, j) = u * cs[j] + v * sn[j];
+                at(row, j + 1) = -u * std::conj(sn[j]) + v * std::conj(cs[j]);
+            }
+        for (int j = lo; j <= hi; ++j) at(j, j) += mu;
+    }
+    return true;
+}
+
+// Leja order (reading R18): the largest modulus first, then each point maximising the
+// product of its distances to those already taken; ties to the lowest index.
+std::vector<double> leja(const std::vector<double>& pts) {
+    std::vector<double> out;
+    std::vector<bool> used(pts.size(), false);
+    for (size_t t = 0; t < pts.size(); ++t) {
+        int best = -1;
+        double best_val = -1.0;
+        for (size_t i = 0; i < pts.size(); ++i) {
+            if (used[i]) continue;
+            double v = 1.0;
+            if (t == 0)
+                v = std::fabs(pts[i]);
+            else
+                for (double z : out) v *= std::fabs(pts[i] - z);
+            if (v > best_val) {
+                best = (int)i;
+                best_val = v;
+            }
+        }
+        used[best] = true;
+        out.push_back(pts[best]);
+    }
+    return out;
+}
+
 struct Solver {
     mpk_plan_t hi, lo;
     int32_t n;
@@ -324,6 +411,72 @@ struct Solver {
         const double params[2] = {theta, delta};
         return poly_apply(lo, MPK_POLY_CHEBYSHEV, degree, c.data(), params, in, out, poly_flags, vec(L.poly),
                           L.poly_bytes, st);
+    }
+
+    // out = M in for the block operator without a shift (A, A D^{-1}, the k-sweep Jacobi
+    // or the GS2 operator A P^{-1}), on `lo`
+    mpk_status apply_M(const double* in, double* out) {
+        if (precond == MPK_PRECOND_GS2)
+            return mpk::gs2_chain(lo, degree, in, out, L.ld, 1, nullptr, nullptr, 0, poly_flags, vec(L.poly),
+                                  L.poly_bytes, st);
+        if (precond == MPK_PRECOND_JACOBI && degree > 1)
+            return mpk::jacobi_chain(lo, degree, in, out, L.ld, 1, nullptr, nullptr, poly_flags, vec(L.poly),
+                                     L.poly_bytes, st);
+        return mpk_apply(lo, in, out, L.ld, 1, poly_flags, nullptr, 0, st);
+    }
+
+    // Reading R24: Newton shifts from Ritz values.  s steps of standard Arnoldi on M
+    // from Q_0 (classical Gram-Schmidt with one reorthogonalisation), writing Q_1.. and
+    // stopping when a new vector's norm is at most 2^-48 of ||M q_j|| (an invariant
+    // space); the eigenvalues of the square Hessenberg matrix; their real parts in Leja
+    // order, repeated cyclically up to s; columns scaled by a quarter of the spread.
+    mpk_status ritz_shifts() {
+        const int ldh = s + 1;
+        std::vector<double> H((size_t)ldh * s, 0.0), g, h, h2;
+        int k = s;
+        for (int j = 0; j < s; ++j) {
+            double* w = W(0);
+            mpk_status e = apply_M(Q(j), w);
+            if (e == MPK_OK) e = gram(w, 1, w, 1, g);
+            if (e != MPK_OK) return e;
+            const double wn = std::sqrt(g[0]);
+            for (int pass = 0; pass < 2; ++pass) {  // w -= Q_{0..j} (Q^T w), twice
+                e = gram(Q(0), j + 1, w, 1, pass == 0 ? h : h2);
+                if (e != MPK_OK) return e;
+                const std::vector<double>& hp = pass == 0 ? h : h2;
+                std::vector<double> neg(j + 1);
+                for (int i = 0; i <= j; ++i) {
+                    neg[i] = -hp[i];
+                    H[(size_t)j * ldh + i] += hp[i];
+                }
+                e = lincomb(w, 1.0, Q(0), j + 1, neg, 1, w, pass);
+                if (e != MPK_OK) return e;
+            }
+            e = gram(w, 1, w, 1, g);
+            if (e != MPK_OK) return e;
+            const double nrm = std::sqrt(g[0]);
+            if (!(nrm > std::ldexp(1.0, -48) * wn)) {
+                k = j + 1;
+                break;
+            }
+            H[(size_t)j * ldh + j + 1] = nrm;
+            e = lincomb(nullptr, 0.0, w, 1, std::vector<double>{1.0 / nrm}, 1, Q(j + 1), 2);
+            if (e != MPK_OK) return e;
+        }
+        std::vector<cplx> Hk((size_t)k * k), ev;
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i <= std::min(j + 1, k - 1); ++i) Hk[(size_t)j * k + i] = H[(size_t)j * ldh + i];
+        if (!hessenberg_eigenvalues(Hk, k, ev))
+            return mpk::set_error(MPK_ERR_UNSUPPORTED, "Ritz values: the QR iteration did not converge");
+        std::vector<double> re(k);
+        for (int i = 0; i < k; ++i) re[i] = ev[i].real();
+        const std::vector<double> order = leja(re);
+        lam.assign(s, 0.0);
+        for (int i = 0; i < s; ++i) lam[i] = order[i % k];
+        const auto mm = std::minmax_element(lam.begin(), lam.end());
+        const double spread = *mm.second - *mm.first;
+        sig.assign(s, spread > 0.0 ? 0.25 * spread : (lam[0] != 0.0 ? std::fabs(lam[0]) : 1.0));
+        return MPK_OK;
     }
 
     // out = s(A) in
@@ -569,12 +722,16 @@ MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t prec
                                            "for GS2, 1 <= k <= 64 for Jacobi)", kMaxS, kMaxM);
     if (precond == MPK_PRECOND_GS2 && !mpk::plan_split_lower(lo))
         return mpk::set_error(MPK_ERR_ARG, "lo must be built with split_lower for the GS2 preconditioner");
+    const bool ritz = flags & MPK_RITZ_SHIFTS;
+    if (ritz && precond == MPK_PRECOND_CHEBYSHEV)
+        return mpk::set_error(MPK_ERR_ARG, "MPK_RITZ_SHIFTS needs MPK_PRECOND_NONE, _JACOBI or _GS2");
     if (precond == MPK_PRECOND_CHEBYSHEV && !(lmin > 0.0))
         return mpk::set_error(MPK_ERR_ARG, "need 0 < lmin < lmax");
-    if (!(lmax > lmin)) return mpk::set_error(MPK_ERR_ARG, "need lmin < lmax");
+    if (!ritz && !(lmax > lmin)) return mpk::set_error(MPK_ERR_ARG, "need lmin < lmax");
     if (!(tol >= 0.0)) return mpk::set_error(MPK_ERR_ARG, "tol must be >= 0");
     if (max_cycles < 0) return mpk::set_error(MPK_ERR_ARG, "max_cycles must be >= 0");
-    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED)) return mpk::set_error(MPK_ERR_ARG, "unknown flag bits");
+    if (flags & ~(MPK_IO_PERMUTED | MPK_PLAIN | MPK_STAGED | MPK_RITZ_SHIFTS))
+        return mpk::set_error(MPK_ERR_ARG, "unknown flag bits");
     int64_t n64 = 0;
     mpk_status st = mpk_plan_info(hi, &n64, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr);
     if (st != MPK_OK) return st;
@@ -624,25 +781,7 @@ MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t prec
         const double mid = precond == MPK_PRECOND_CHEBYSHEV ? 1.0 : 0.5 * (lmax + lmin);
         std::vector<double> pts(s);
         for (int i = 0; i < s; ++i) pts[i] = mid + eps * std::cos(3.14159265358979323846 * (2 * i + 1) / (2.0 * s));
-        std::vector<bool> used(s, false);
-        for (int t = 0; t < s; ++t) {
-            int best = -1;
-            double best_val = -1.0;
-            for (int i = 0; i < s; ++i) {
-                if (used[i]) continue;
-                double v = 1.0;
-                if (t == 0)
-                    v = std::fabs(pts[i]);
-                else
-                    for (double z : S.lam) v *= std::fabs(pts[i] - z);
-                if (v > best_val) {
-                    best = i;
-                    best_val = v;
-                }
-            }
-            used[best] = true;
-            S.lam.push_back(pts[best]);
-        }
+        S.lam = leja(pts);
         S.sig.assign(s, 0.5 * eps);
         // level-order copies of b and x when the caller's vectors are in original order
         const double* bp = b;
@@ -675,6 +814,10 @@ MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t prec
             std::vector<double> inv{1.0 / beta};
             st = S.lincomb(nullptr, 0.0, S.Q(0), 1, inv, 1, S.Q(0), 0);
             if (st != MPK_OK) return st;
+            if (ritz && cyc == 0) {  // shifts from the first cycle's Arnoldi steps (R24)
+                st = S.ritz_shifts();
+                if (st != MPK_OK) return st;
+            }
             int cols = 0;
             st = S.cycle(beta, tol * nb, xp, &cols);
             if (st != MPK_OK) return st;
@@ -694,6 +837,27 @@ MPK_API mpk_status mpk_sstep_gmres_ex(mpk_plan_t hi, mpk_plan_t lo, int32_t prec
     } catch (const std::bad_alloc&) {
         return mpk::set_error(MPK_ERR_NOMEM, "out of host memory");
     }
+}
+
+MPK_API mpk_status mpk_ritz_values(const double* H, int64_t ldh, int32_t k, double* re, double* im) {
+    if (k < 0 || k > 512) return mpk::set_error(MPK_ERR_ARG, "k must be in 0..512 (got %d)", k);
+    if (k == 0) return MPK_OK;
+    if (!H || !re || !im) return mpk::set_error(MPK_ERR_ARG, "null argument");
+    if (ldh < k) return mpk::set_error(MPK_ERR_ARG, "ldh must be >= k");
+    try {
+        std::vector<cplx> A((size_t)k * k), ev;
+        for (int j = 0; j < k; ++j)
+            for (int i = 0; i <= std::min(j + 1, k - 1); ++i) A[(size_t)j * k + i] = H[(size_t)j * ldh + i];
+        if (!hessenberg_eigenvalues(A, k, ev))
+            return mpk::set_error(MPK_ERR_UNSUPPORTED, "the QR iteration did not converge");
+        for (int i = 0; i < k; ++i) {
+            re[i] = ev[i].real();
+            im[i] = ev[i].imag();
+        }
+    } catch (const std::bad_alloc&) {
+        return mpk::set_error(MPK_ERR_NOMEM, "out of host memory");
+    }
+    return MPK_OK;
 }
 
 MPK_API mpk_status mpk_sstep_gmres(mpk_plan_t hi, mpk_plan_t lo, int32_t s, int32_t m, int32_t degree, double lmin,

@@ -17,6 +17,7 @@ MPK_IO_PERMUTED = 1
 MPK_PLAIN = 2
 MPK_STAGED = 4
 MPK_LAST_POWER = 8  # server applies: return y_p only
+MPK_RITZ_SHIFTS = 16  # s-step GMRES: Newton shifts from Ritz values
 VALUE_TYPES = {"f64": 0, "f32": 1, "bf16": 2}  # bf16: BF16 values with a per-row FP32 scale
 POLY_KINDS = {"monomial": 0, "newton": 1, "chebyshev": 2}
 # operator kinds of mpk_block_powers
@@ -42,7 +43,7 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_set_block", "mpk_tune_block", "mpk_block_powers", "mpk_set_watchdog",
            "poly_apply_static", "mpk_update_values", "mpk_plan_cache_create", "mpk_plan_cache_get",
            "mpk_plan_cache_release", "mpk_plan_cache_stats", "mpk_plan_cache_destroy", "mpk_server_create_ex",
-           "mpk_gs2_smooth", "mpk_gs2_smooth_work_bytes"]
+           "mpk_gs2_smooth", "mpk_gs2_smooth_work_bytes", "mpk_ritz_values"]
 
 
 class MPKError(RuntimeError):
@@ -125,6 +126,7 @@ def _load():
         "mpk_gs2_work_bytes": (I32, [P, I32, I32, U32, pSZ]),
         "mpk_gs2_smooth": (I32, [P, I32, I32, P, P, P, U32, P, SZ, P]),
         "mpk_gs2_smooth_work_bytes": (I32, [P, I32, U32, pSZ]),
+        "mpk_ritz_values": (I32, [P, I64, I32, P, P]),
         "mpk_set_block": (I32, [P, I32]),
         "mpk_tune_block": (I32, [P, I32, P, P, I64, P, pI32, ctypes.POINTER(ctypes.c_double)]),
         "mpk_server_submit_gmres": (I32, [P, P, P, P, P, I32, I32, I32, ctypes.c_double, ctypes.c_double,
@@ -434,9 +436,11 @@ class Plan:
     def sstep_gmres(self, lo, b, s, m, degree, lmin, lmax, tol=1e-10, max_cycles=100, x=None, permuted=True,
                     plain=False, staged=False, stream=None, work=None, precond="chebyshev"):
         """Solve A x = b by restarted s-step GMRES (blocks of ``s``, restart ``m``) with the
-        right degree-``degree`` Chebyshev polynomial preconditioner on [lmin, lmax]:
-        FP64 residuals with this plan, basis and preconditioner with ``lo`` (the same
-        matrix, FP32 or FP64 values).  Returns (x, basis vectors built, cycles, final
+        right degree-``degree`` Chebyshev polynomial preconditioner on [lmin, lmax] (or
+        ``precond`` none / jacobi / gs2): FP64 residuals with this plan, basis and
+        preconditioner with ``lo`` (the same matrix, FP32 or FP64 values).  With
+        lmin = lmax = None (not for Chebyshev) the Newton shifts come from Ritz values of
+        the first cycle's Arnoldi steps.  Returns (x, basis vectors built, cycles, final
         ||r|| / ||b||)."""
         import torch
         if x is None:
@@ -448,6 +452,9 @@ class Plan:
         it, cy, rel = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
         if precond not in PRECONDS:
             raise ValueError(f"precond must be one of {sorted(PRECONDS)}")
+        if lmin is None and lmax is None:
+            flags |= MPK_RITZ_SHIFTS
+            lmin = lmax = 0.0
         _check(_lib.mpk_sstep_gmres_ex(self._h, lo._h, PRECONDS[precond], int(s), int(m), int(degree), float(lmin),
                                        float(lmax), _dptr(b), _dptr(x), float(tol), int(max_cycles), flags,
                                        _dptr(work), work.numel() * work.element_size(), ctypes.byref(it),

@@ -463,3 +463,57 @@ def test_update_values_checks_the_pattern():
         plan.update_values(S.laplacian_2d(20, 18))
     with pytest.raises(M.MPKError, match="MPK_ERR_CSR"):
         plan.update_values(S.CSR(A.n, A.rowptr, A.col[::-1].copy(), A.val))
+
+
+def _ritz(H):
+    lib = M.lib()
+    k = H.shape[0]
+    Hf = np.asfortranarray(H, dtype=np.float64)
+    re, im = np.zeros(k), np.zeros(k)
+    code = lib.mpk_ritz_values(Hf.ctypes.data_as(ctypes.c_void_p), k, k, re.ctypes.data_as(ctypes.c_void_p),
+                               im.ctypes.data_as(ctypes.c_void_p))
+    assert code == 0, lib.mpk_last_error()
+    return re + 1j * im
+
+
+def _match(got, ref, tol):
+    # eigenvalues as multisets: greedy nearest matching
+    ref = list(ref)
+    for z in got:
+        i = int(np.argmin([abs(z - w) for w in ref]))
+        assert abs(z - ref[i]) <= tol * max(1.0, abs(ref[i])), (z, ref[i])
+        ref.pop(i)
+
+
+@pytest.mark.parametrize("k,seed", [(1, 0), (2, 1), (5, 2), (12, 3), (16, 4), (40, 5)])
+def test_ritz_values_match_numpy_on_random_hessenberg(k, seed):
+    rng = np.random.default_rng(seed)
+    H = np.triu(rng.standard_normal((k, k)), -1)
+    _match(_ritz(H), np.linalg.eigvals(H), 1e-9)
+
+
+def test_ritz_values_symmetric_tridiagonal_and_complex_pairs():
+    n = 10
+    T = np.diag(np.full(n, 2.0)) - np.diag(np.ones(n - 1), 1) - np.diag(np.ones(n - 1), -1)
+    ref = 2 - 2 * np.cos(np.arange(1, n + 1) * np.pi / (n + 1))
+    got = _ritz(T)
+    assert np.abs(got.imag).max() < 1e-12
+    np.testing.assert_allclose(np.sort(got.real), ref, atol=1e-12)
+    R = np.array([[1.0, -2.0, 0.5], [2.0, 1.0, 0.3], [0.0, 0.0, 4.0]])  # 1 +- 2i and 4
+    _match(_ritz(R), [1 + 2j, 1 - 2j, 4.0], 1e-12)
+    # already triangular (every subdiagonal zero) and a rank-deficient block
+    U = np.triu(np.arange(1.0, 17.0).reshape(4, 4))
+    _match(_ritz(U), np.diag(U), 1e-12)
+    Z = np.zeros((3, 3))
+    _match(_ritz(Z), [0.0, 0.0, 0.0], 1e-12)
+
+
+def test_ritz_values_argument_errors():
+    lib = M.lib()
+    x = np.zeros(4)
+    p = x.ctypes.data_as(ctypes.c_void_p)
+    assert lib.mpk_ritz_values(None, 0, 0, None, None) == 0                 # k = 0: nothing to do
+    assert lib.mpk_ritz_values(p, 2, -1, p, p) == -1
+    assert lib.mpk_ritz_values(p, 1, 2, p, p) == -1                         # ldh < k
+    assert lib.mpk_ritz_values(None, 2, 2, p, p) == -1
+    assert lib.mpk_ritz_values(p, 600, 513, p, p) == -1
