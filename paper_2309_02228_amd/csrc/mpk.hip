@@ -372,10 +372,21 @@ __device__ bool poll_until(const BlockArgs& a, __amdgpu_buffer_rsrc_t dr, const 
     }
 }
 
+// Waves per SIMD the compiler must allow for: the FP32-valued polynomial kernels with
+// two chunks of up to 7 register slots per wave need a few registers more than five waves
+// leave (the Chebyshev one 99), and five waves with the 4 spilled registers measured
+// faster than four (the s-step GMRES solve at 160^3: 70.3 ms against 75.8 ms); every
+// other instance keeps its natural count (wider rows and FP64 values spill far more).
+template <int REG, int G, bool POLY, typename VT>
+constexpr int block_min_waves() {
+    return (POLY && G == 2 && REG <= 7 && sizeof(VT) == 4) ? 5 : 1;
+}
+
 // Unit = G consecutive chunks of a partition's sequence, carried together
 // through the q powers of a block; its SELL slots stay in registers.
 template <int REG, int G, int KIND, bool POLY, typename VT>
-__global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(block_min_waves<REG, G, POLY, VT>(), 8)))
+void mpk_block_kernel(BlockArgs a) {
     const VT* val = (const VT*)a.P.val;
     const int lane = threadIdx.x & 63;
     const int part = blockIdx.x % kParts;
