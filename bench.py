@@ -895,8 +895,8 @@ def main():
             "note": f"{args.solve_reps} sequential solves of one system after one warm-up (no serving or batching)",
         }
         out["solve_latency_ms"] = {"p50": mixed["p50_ms"], "p99": mixed["p99_ms"],
-                                   "note": "sequential mixed-precision solves of one system; the served "
-                                           "(continuously batched) solve is not built"}
+                                   "note": "sequential mixed-precision solves of one system (replaced by the "
+                                           "served solves' latency when the serving leg runs)"}
         log(f"solve: mixed {mixed['p50_ms']:.1f} ms p50 ({mixed['corrections']} corrections), fp64 plain "
             f"{fp64_plain['p50_ms']:.1f} ms p50")
     if not args.no_solve and args.only == "both":
