@@ -607,6 +607,7 @@ def main():
     achieved = bytes_per_launch / avg_launch / 1e9
     sha = kernel_sha()
     traffic = load_traffic(sha) if key == "blocked" else None
+    shape = plan.block_shape("powers")  # waves per XCD, chunks per wave, register slots
 
     out = {
         "metric": "MPK GFLOP/s vs p×SpMV (7-pt 160^3, p=4) + solve p50/p99 latency",
@@ -629,8 +630,8 @@ def main():
                       "matrix may still sit in the 256 MB Infinity Cache from the previous call); HIP events "
                       "on the launch stream; cold_cache_timing gives each call timed alone after writing "
                       "2 GiB",
-            "chunks_per_worker": args.chunks_per_worker or None,
-            "workers_per_xcd": info["workers_per_xcd"],
+            "chunks_per_worker": shape[1],
+            "workers_per_xcd": shape[0],
         },
         "roofline": {
             "bound": "hbm",

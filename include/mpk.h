@@ -112,7 +112,9 @@ typedef struct {
                                 together through a block (1, 2 or 4; 0 = 2;
                                 always 1 when rows need more than 16 register
                                 slots).  With FP32 values, 4 suits mpk_apply
-                                on rows of at most 8 slots                    */
+                                on rows of at most 8 slots.  With 0 and FP64
+                                values on rows of at most 8 slots, mpk_apply
+                                may carry 3 (mpk_block_shape)                 */
     int32_t value_type;      /* storage of the matrix values on the device:
                                 MPK_VALUES_F64 (0), MPK_VALUES_F32 (1) or
                                 MPK_VALUES_BF16_ROWSCALE (2).  The reduced
@@ -228,6 +230,18 @@ mpk_status mpk_get_deps(mpk_plan_t plan, int64_t* ndeps, int32_t* dep_ptr, int32
  */
 mpk_status mpk_min_workers(mpk_plan_t plan, int32_t q, int32_t* workers_per_xcd);
 
+/*
+ * mpk_min_workers for units of chunks_per_worker chunks.  A plan holds the
+ * units of its own chunks_per_worker and, when it stores FP64 values, its
+ * chunks_per_worker was left at 0 and its rows fit 8 register slots, units of
+ * 3 as well: the matrix powers' kernel carrying three chunks per wave still
+ * keeps three waves per SIMD resident, so mpk_upload gives it to mpk_apply
+ * when it admits more powers per launch, or as many with more rows in flight.
+ * Errors: MPK_ERR_ARG (null pointers, q outside 1..p_block, no units of that
+ * size in the plan).
+ */
+mpk_status mpk_min_workers_units(mpk_plan_t plan, int32_t chunks_per_worker, int32_t q, int32_t* workers_per_xcd);
+
 /* Operator kinds of mpk_block_powers. */
 #define MPK_OP_POWERS 0           /* mpk_apply (and mpk_jacobi_apply with k = 1)  */
 #define MPK_OP_POLY_MONOMIAL 1    /* poly_apply, MPK_POLY_MONOMIAL                */
@@ -250,6 +264,16 @@ mpk_status mpk_min_workers(mpk_plan_t plan, int32_t q, int32_t* workers_per_xcd)
  * uploaded).
  */
 mpk_status mpk_block_powers(mpk_plan_t plan, int32_t op, int32_t* q);
+
+/*
+ * Launch shape of the blocked kernel that calls of operator kind op use on
+ * this uploaded plan: its waves per XCD partition, the chunks each wave
+ * carries (the units of mpk_min_workers_units) and the SELL slots per row it
+ * keeps in registers.  Any output pointer may be null.
+ * Errors: MPK_ERR_ARG (unknown op), MPK_ERR_STATE (not uploaded).
+ */
+mpk_status mpk_block_shape(mpk_plan_t plan, int32_t op, int32_t* workers_per_xcd, int32_t* chunks_per_worker,
+                           int32_t* reg_slots);
 
 /*
  * Binds caller-owned device memory (at least device_bytes from

@@ -851,8 +851,8 @@ void set_error_text(const char* msg) { g_err = msg; }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, dep_ptr, dep_idx, done, tickets,
-        status, lmask, dslot, total;
+    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, unit_ptr3, unit_rec3, dep_ptr,
+        dep_idx, done, tickets, status, lmask, dslot, total;
 };
 
 Layout make_layout(const mpk::HostPlan& H) {
@@ -873,7 +873,9 @@ Layout make_layout(const mpk::HostPlan& H) {
     L.seq = take((size_t)H.nchunks * 4);
     L.seq_ptr = take((kParts + 1) * 4);
     L.unit_ptr = take((kParts + 1) * 4);
-    L.unit_rec = take(std::max<size_t>(1, H.unit_rec.size()) * 4);
+    L.unit_rec = take(std::max<size_t>(1, H.units.rec.size()) * 4);
+    L.unit_ptr3 = take(H.units3.ptr.size() * 4);
+    L.unit_rec3 = take(H.units3.rec.size() * 4);
     L.dep_ptr = take((H.nchunks + 1) * 4);
     L.dep_idx = take(std::max<size_t>(1, H.dep_idx.size()) * 4);
     L.done = take(std::max<size_t>(1, H.nchunks) * 4 * kFlagStride);
@@ -899,6 +901,9 @@ struct mpk_plan_s {
     int grid_block[kKinds][2] = {};
     int q_eff[kKinds][2] = {};    // powers per launch meeting the deadlock bound
     int reg[kKinds][2] = {};      // register slots per row of the kernel in use
+    int group[kKinds][2] = {};    // chunks per worker of the kernel in use (H.units or H.units3)
+    const int32_t* unit_ptr3 = nullptr;  // device copy of H.units3
+    const int32_t* unit_rec3 = nullptr;
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
     int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
@@ -951,10 +956,22 @@ BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
 }
 
 // The planner keeps one chunk per worker when rows need more than 16 slots.
-BlockFn pick_block(const mpk::HostPlan& H, int reg, int kind, bool poly) {
-    if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_vt<uint16_t>(reg, H.group, kind, poly);
-    return H.value_type == MPK_VALUES_F32 ? pick_block_vt<float>(reg, H.group, kind, poly)
-                                          : pick_block_vt<double>(reg, H.group, kind, poly);
+// Three chunks per worker exist for the FP64 powers only (H.units3): that
+// kernel still fits three waves per SIMD at rows of up to 8 slots, where
+// every other FP64 variant at G = 3 would drop to two.
+BlockFn pick_block(const mpk::HostPlan& H, int group, int reg, int kind, bool poly) {
+    if (group == 3) {
+        if (H.value_type != MPK_VALUES_F64 || kind != KIND_MONO || poly) return nullptr;
+        switch (reg) {
+            case 4: return mpk_block_kernel<4, 3, KIND_MONO, false, double>;
+            case 7: return mpk_block_kernel<7, 3, KIND_MONO, false, double>;
+            case 8: return mpk_block_kernel<8, 3, KIND_MONO, false, double>;
+            default: return nullptr;
+        }
+    }
+    if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_vt<uint16_t>(reg, group, kind, poly);
+    return H.value_type == MPK_VALUES_F32 ? pick_block_vt<float>(reg, group, kind, poly)
+                                          : pick_block_vt<double>(reg, group, kind, poly);
 }
 
 template <typename VT>
@@ -1050,11 +1067,16 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
         p->epoch = 0;
     }
     a.P = p->D;
+    const int group = p->group[kind][poly];
+    if (group == 3) {
+        a.P.unit_ptr = p->unit_ptr3;
+        a.P.unit_rec = p->unit_rec3;
+    }
     a.epoch = ++p->epoch;
     a.workers = p->workers[kind][poly];
     a.status = status_slot(p, st, true);
     a.spin_limit = p->H.watchdog == 0 ? kSpinLimit : p->H.watchdog;
-    const BlockFn fn = pick_block(p->H, p->reg[kind][poly], kind, poly);
+    const BlockFn fn = pick_block(p->H, group, p->reg[kind][poly], kind, poly);
     if (!fn) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this row width and group");
     hipLaunchKernelGGL(fn, dim3(p->grid_block[kind][poly]),
                        dim3(kBlockThreads), 0, st, a);
@@ -1491,20 +1513,43 @@ MPK_API mpk_status mpk_get_deps(mpk_plan_t p, int64_t* ndeps, int32_t* dep_ptr, 
 MPK_API mpk_status mpk_min_workers(mpk_plan_t p, int32_t q, int32_t* w) {
     if (!p || !w) return fail(MPK_ERR_ARG, "null argument");
     if (q < 1 || q > p->H.p_block) return fail(MPK_ERR_ARG, "q must be in 1..p_block (%d)", p->H.p_block);
-    *w = p->H.min_workers[q];
+    *w = p->H.units.min_workers[q];
     return MPK_OK;
 }
 
+MPK_API mpk_status mpk_min_workers_units(mpk_plan_t p, int32_t group, int32_t q, int32_t* w) {
+    if (!p || !w) return fail(MPK_ERR_ARG, "null argument");
+    if (q < 1 || q > p->H.p_block) return fail(MPK_ERR_ARG, "q must be in 1..p_block (%d)", p->H.p_block);
+    const mpk::Units* U = group == p->H.units.group ? &p->H.units : group == p->H.units3.group ? &p->H.units3 : nullptr;
+    if (!U || group < 1) return fail(MPK_ERR_ARG, "the plan holds no units of %d chunks", group);
+    *w = U->min_workers[q];
+    return MPK_OK;
+}
+
+namespace {
+// operator kinds of the ABI (MPK_OP_*) -> kernel kind and polynomial flag
+constexpr int kOpKind[8] = {KIND_MONO, KIND_MONO, KIND_NEWTON, KIND_CHEB, KIND_NEWTON, KIND_JCHAIN, KIND_GS2, KIND_SMOOTH};
+constexpr int kOpPoly[8] = {0, 1, 1, 1, 0, 0, 0, 0};
+}  // namespace
+
 MPK_API mpk_status mpk_block_powers(mpk_plan_t p, int32_t op, int32_t* q) {
     if (!p || !q) return fail(MPK_ERR_ARG, "null argument");
-    static const int kind_of[8] = {KIND_MONO,   KIND_MONO,  KIND_NEWTON, KIND_CHEB,
-                                   KIND_NEWTON, KIND_JCHAIN, KIND_GS2,    KIND_SMOOTH};
-    static const int poly_of[8] = {0, 1, 1, 1, 0, 0, 0, 0};
     if (op < 0 || op > 7) return fail(MPK_ERR_ARG, "unknown operator kind %d", op);
     mpk_status s = check_uploaded(p);
     if (s != MPK_OK) return s;
-    const int qe = p->q_eff[kind_of[op]][poly_of[op]];
+    const int qe = p->q_eff[kOpKind[op]][kOpPoly[op]];
     *q = p->q_cap > 0 ? std::min(qe, p->q_cap) : qe;
+    return MPK_OK;
+}
+
+MPK_API mpk_status mpk_block_shape(mpk_plan_t p, int32_t op, int32_t* workers, int32_t* group, int32_t* reg) {
+    if (!p) return fail(MPK_ERR_ARG, "null plan");
+    if (op < 0 || op > 7) return fail(MPK_ERR_ARG, "unknown operator kind %d", op);
+    mpk_status s = check_uploaded(p);
+    if (s != MPK_OK) return s;
+    if (workers) *workers = p->workers[kOpKind[op]][kOpPoly[op]];
+    if (group) *group = p->group[kOpKind[op]][kOpPoly[op]];
+    if (reg) *reg = p->reg[kOpKind[op]][kOpPoly[op]];
     return MPK_OK;
 }
 
@@ -1596,8 +1641,10 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     HIP_TRY(put(L.iperm, H.iperm.data(), H.iperm.size() * 4));
     HIP_TRY(put(L.seq, H.seq.data(), H.seq.size() * 4));
     HIP_TRY(put(L.seq_ptr, H.seq_ptr.data(), H.seq_ptr.size() * 4));
-    HIP_TRY(put(L.unit_ptr, H.unit_ptr.data(), H.unit_ptr.size() * 4));
-    HIP_TRY(put(L.unit_rec, H.unit_rec.data(), H.unit_rec.size() * 4));
+    HIP_TRY(put(L.unit_ptr, H.units.ptr.data(), H.units.ptr.size() * 4));
+    HIP_TRY(put(L.unit_rec, H.units.rec.data(), H.units.rec.size() * 4));
+    HIP_TRY(put(L.unit_ptr3, H.units3.ptr.data(), H.units3.ptr.size() * 4));
+    HIP_TRY(put(L.unit_rec3, H.units3.rec.data(), H.units3.rec.size() * 4));
     HIP_TRY(put(L.dep_ptr, H.dep_ptr.data(), H.dep_ptr.size() * 4));
     HIP_TRY(put(L.dep_idx, H.dep_idx.data(), H.dep_idx.size() * 4));
     HIP_TRY(put(L.lmask, H.lmask.data(), H.lmask.size() * 4));
@@ -1621,6 +1668,8 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     D.seq_ptr = (const int32_t*)(d + L.seq_ptr);
     D.unit_ptr = (const int32_t*)(d + L.unit_ptr);
     D.unit_rec = (const int32_t*)(d + L.unit_rec);
+    p->unit_ptr3 = (const int32_t*)(d + L.unit_ptr3);
+    p->unit_rec3 = (const int32_t*)(d + L.unit_rec3);
     D.ndeps = (int32_t)H.dep_idx.size();
     D.dep_ptr = (const int32_t*)(d + L.dep_ptr);
     D.dep_idx = (const int32_t*)(d + L.dep_idx);
@@ -1645,9 +1694,42 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
     int maxlen = 0;
     for (int x = 0; x < kParts; ++x) maxlen = std::max(maxlen, H.seq_ptr[x + 1] - H.seq_ptr[x]);
-    const int maxunits = (maxlen + H.group - 1) / H.group;
+    // one candidate kernel: its powers per launch (qe) and the chunks its launch
+    // keeps in flight (waves x chunks per worker)
+    struct Shape {
+        int qe = 0, wg_per_part = 0, chunks = 0;
+    };
+    auto shape_of = [&](BlockFn fn, const mpk::Units& U, Shape& sh) -> mpk_status {
+        int occ = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, kBlockThreads, 0));
+        int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
+        if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));
+        // no more waves than units
+        const int maxunits = (maxlen + U.group - 1) / U.group;
+        wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
+        // units come from in-order tickets, so only running waves hold work, and
+        // every launched workgroup is resident at once on an idle GPU (the grid is
+        // the occupancy limit) or starts once the kernels ahead of it finish: a
+        // block of q powers needs the deadlock bound within the launched waves
+        sh.qe = 1;
+        for (int q = H.p_block; q >= 1; --q)
+            if (U.min_workers[q] <= wg_per_part * kWaves) {
+                sh.qe = q;
+                break;
+            }
+        sh.wg_per_part = wg_per_part;
+        sh.chunks = wg_per_part * kWaves * U.group;
+        return MPK_OK;
+    };
     for (int kind = 0; kind < kKinds; ++kind)
         for (int poly = 0; poly < 2; ++poly) {
+            auto take = [&](const Shape& sh, int reg, int group) {
+                p->q_eff[kind][poly] = sh.qe;
+                p->reg[kind][poly] = reg;
+                p->group[kind][poly] = group;
+                p->grid_block[kind][poly] = sh.wg_per_part * kParts;
+                p->workers[kind][poly] = sh.wg_per_part * kWaves;
+            };
             // wide rows: the kernel holding 32 slots per row in registers and the one
             // holding 16 (streaming the rest at each power) use the same units of
             // one chunk; the leaner one keeps more waves resident, which deep level
@@ -1655,31 +1737,26 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
             // more powers per launch, the 32-slot one on a tie.
             const int cand[2] = {H.reg_slots, H.reg_slots >= 32 ? 16 : 0};
             p->q_eff[kind][poly] = 0;
+            Shape best;
             for (int ci = 0; ci < 2 && cand[ci] > 0; ++ci) {
-                const BlockFn fn = pick_block(H, cand[ci], kind, poly);
+                const BlockFn fn = pick_block(H, H.units.group, cand[ci], kind, poly);
                 if (!fn) return fail(MPK_ERR_UNSUPPORTED, "no blocked kernel for this plan");
-                int occ = 0;
-                HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, (const void*)fn, kBlockThreads, 0));
-                int wg_per_part = std::max(1, (cus / kParts) * std::max(occ, 1));
-                if (H.workers_req > 0) wg_per_part = std::min(wg_per_part, std::max(1, H.workers_req / kWaves));
-                // no more waves than units
-                wg_per_part = std::min(wg_per_part, std::max(1, (maxunits + kWaves - 1) / kWaves));
-                // units come from in-order tickets, so only running waves hold work, and
-                // every launched workgroup is resident at once on an idle GPU (the grid is
-                // the occupancy limit) or starts once the kernels ahead of it finish: a
-                // block of q powers needs the deadlock bound within the launched waves
-                int qe = 1;
-                for (int q = H.p_block; q >= 1; --q)
-                    if (H.min_workers[q] <= wg_per_part * kWaves) {
-                        qe = q;
-                        break;
-                    }
-                if (qe > p->q_eff[kind][poly]) {
-                    p->q_eff[kind][poly] = qe;
-                    p->reg[kind][poly] = cand[ci];
-                    p->grid_block[kind][poly] = wg_per_part * kParts;
-                    p->workers[kind][poly] = wg_per_part * kWaves;
+                Shape sh;
+                mpk_status ss = shape_of(fn, H.units, sh);
+                if (ss != MPK_OK) return ss;
+                if (sh.qe > best.qe) {
+                    best = sh;
+                    take(sh, cand[ci], H.units.group);
                 }
+            }
+            // three chunks per worker where a kernel exists for them: taken when it
+            // admits more powers per launch, or as many with more rows in flight
+            const BlockFn fn3 = H.units3.group == 3 ? pick_block(H, 3, H.reg_slots, kind, poly) : nullptr;
+            if (fn3) {
+                Shape sh;
+                mpk_status ss = shape_of(fn3, H.units3, sh);
+                if (ss != MPK_OK) return ss;
+                if (sh.qe > best.qe || (sh.qe == best.qe && sh.chunks > best.chunks)) take(sh, H.reg_slots, 3);
             }
         }
     // plain launches: up to 32 workgroups per CU (128 waves), a few chunks per

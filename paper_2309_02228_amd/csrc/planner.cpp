@@ -412,6 +412,95 @@ void pattern_hash(int32_t n, const int32_t* rowptr, const int32_t* col, uint64_t
     out[1] = h.b;
 }
 
+// Units of G consecutive chunks of each partition's sequence, carried together
+// by one worker, and the smallest deadlock-free worker count per block size q
+// (D3): bmin[u] = smallest first chunk among units within h unit hops of u; the
+// condition for W workers holds iff W > max over unit positions j of
+// (j - first position whose first chunk is >= bmin[unit j]), per partition.
+static void build_units(const HostPlan& P, int32_t G, Units& U) {
+    U.group = G;
+    U.ptr.assign(kParts + 1, 0);
+    std::vector<int32_t>& unit_ptr = U.ptr;
+    std::vector<int32_t> first, unit_of(P.nchunks);
+    for (int x = 0; x < kParts; ++x) {
+        const int32_t len = P.seq_ptr[x + 1] - P.seq_ptr[x];
+        for (int32_t j = 0; j < len; j += G) {
+            for (int32_t t = j; t < std::min(len, j + G); ++t)
+                unit_of[P.seq[P.seq_ptr[x] + t]] = (int32_t)first.size();
+            first.push_back(P.seq[P.seq_ptr[x] + j]);
+        }
+        unit_ptr[x + 1] = (int32_t)first.size();
+    }
+    const int32_t nunits = (int32_t)first.size();
+    // one record per unit, read by the blocked kernel in a single scalar load
+    U.stride = G <= 1 ? 8 : (G == 2 ? 16 : 32);
+    U.rec.assign((size_t)nunits * U.stride, 0);
+    for (int x = 0; x < kParts; ++x) {
+        const int32_t len = P.seq_ptr[x + 1] - P.seq_ptr[x];
+        for (int32_t u = unit_ptr[x]; u < unit_ptr[x + 1]; ++u) {
+            int32_t* r = U.rec.data() + (size_t)u * U.stride;
+            for (int32_t g = 0; g < G; ++g) {
+                const int32_t t = (u - unit_ptr[x]) * G + g;
+                if (t >= len) {
+                    r[5 * g] = -1;
+                    continue;
+                }
+                const int32_t c = P.seq[P.seq_ptr[x] + t];
+                r[5 * g + 0] = c;
+                r[5 * g + 1] = (int32_t)(P.chunk_off[c] / kChunkRows);
+                r[5 * g + 2] = (int32_t)((P.chunk_off[c + 1] - P.chunk_off[c]) / kChunkRows);
+                r[5 * g + 3] = P.dep_ptr[c];
+                r[5 * g + 4] = P.dep_ptr[c + 1];
+            }
+        }
+    }
+    std::vector<int32_t> udep_ptr(nunits + 1, 0), udep;
+    {
+        std::vector<int32_t> stamp(nunits, -1), list;
+        for (int x = 0; x < kParts; ++x)
+            for (int32_t u = unit_ptr[x]; u < unit_ptr[x + 1]; ++u) {
+                list.clear();
+                stamp[u] = u;
+                const int32_t j0 = (u - unit_ptr[x]) * G;
+                const int32_t len = P.seq_ptr[x + 1] - P.seq_ptr[x];
+                for (int32_t t = j0; t < std::min(len, j0 + G); ++t) {
+                    const int32_t c = P.seq[P.seq_ptr[x] + t];
+                    for (int32_t e = P.dep_ptr[c]; e < P.dep_ptr[c + 1]; ++e) {
+                        const int32_t v = unit_of[P.dep_idx[e]];
+                        if (stamp[v] != u) {
+                            stamp[v] = u;
+                            list.push_back(v);
+                        }
+                    }
+                }
+                udep.insert(udep.end(), list.begin(), list.end());
+                udep_ptr[u + 1] = (int32_t)udep.size();
+            }
+    }
+    U.min_workers.assign(P.p_block + 1, 1);
+    std::vector<int32_t> bmin(first), nb(nunits);
+    for (int32_t q = 1; q <= P.p_block; ++q) {
+        if (q >= 2) {  // one more hop
+            for (int32_t u = 0; u < nunits; ++u) {
+                int32_t m = bmin[u];
+                for (int32_t e = udep_ptr[u]; e < udep_ptr[u + 1]; ++e) m = std::min(m, bmin[udep[e]]);
+                nb[u] = m;
+            }
+            bmin.swap(nb);
+        }
+        int32_t need = 1;
+        for (int x = 0; x < kParts; ++x) {
+            const int32_t* f = first.data() + unit_ptr[x];
+            const int32_t len = unit_ptr[x + 1] - unit_ptr[x];
+            for (int32_t j = 0; j < len; ++j) {
+                int32_t lo = (int32_t)(std::lower_bound(f, f + j + 1, bmin[unit_ptr[x] + j]) - f);
+                need = std::max(need, j - lo + 1);
+            }
+        }
+        U.min_workers[q] = need;
+    }
+}
+
 void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* col,
                 const double* val) {
     P.n = n;
@@ -536,6 +625,7 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
     // chunks per worker when the caller leaves it open: two (four chunks of
     // FP32 values fit the plain power kernel better, but not the polynomial
     // kernels, and a plan serves both); wide rows leave room for one chunk only
+    const bool auto_group = P.group == 0;
     if (P.group == 0) P.group = 2;
     if (P.reg_slots >= 32) P.group = 1;
 
@@ -595,92 +685,12 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
         });
     }
 
-    // ---- smallest deadlock-free worker count per block size q (D3) ----------
-    // Units: G consecutive chunks of a partition's sequence, carried together.
-    // bmin[u] = smallest first chunk among units within h unit hops of u; the
-    // condition for W workers holds iff W > max over unit positions j of
-    // (j - first position whose first chunk is >= bmin[unit j]), per partition.
-    const int32_t G = std::max(1, P.group);
-    P.unit_ptr.assign(kParts + 1, 0);
-    std::vector<int32_t>& unit_ptr = P.unit_ptr;
-    std::vector<int32_t> first, unit_of(P.nchunks);
-    for (int x = 0; x < kParts; ++x) {
-        const int32_t len = P.seq_ptr[x + 1] - P.seq_ptr[x];
-        for (int32_t j = 0; j < len; j += G) {
-            for (int32_t t = j; t < std::min(len, j + G); ++t)
-                unit_of[P.seq[P.seq_ptr[x] + t]] = (int32_t)first.size();
-            first.push_back(P.seq[P.seq_ptr[x] + j]);
-        }
-        unit_ptr[x + 1] = (int32_t)first.size();
-    }
-    const int32_t nunits = (int32_t)first.size();
-    // one record per unit, read by the blocked kernel in a single scalar load
-    P.unit_stride = G <= 1 ? 8 : (G == 2 ? 16 : 32);
-    P.unit_rec.assign((size_t)nunits * P.unit_stride, 0);
-    for (int x = 0; x < kParts; ++x) {
-        const int32_t len = P.seq_ptr[x + 1] - P.seq_ptr[x];
-        for (int32_t u = unit_ptr[x]; u < unit_ptr[x + 1]; ++u) {
-            int32_t* r = P.unit_rec.data() + (size_t)u * P.unit_stride;
-            for (int32_t g = 0; g < G; ++g) {
-                const int32_t t = (u - unit_ptr[x]) * G + g;
-                if (t >= len) {
-                    r[5 * g] = -1;
-                    continue;
-                }
-                const int32_t c = P.seq[P.seq_ptr[x] + t];
-                r[5 * g + 0] = c;
-                r[5 * g + 1] = (int32_t)(P.chunk_off[c] / kChunkRows);
-                r[5 * g + 2] = (int32_t)((P.chunk_off[c + 1] - P.chunk_off[c]) / kChunkRows);
-                r[5 * g + 3] = P.dep_ptr[c];
-                r[5 * g + 4] = P.dep_ptr[c + 1];
-            }
-        }
-    }
-    std::vector<int32_t> udep_ptr(nunits + 1, 0), udep;
-    {
-        std::vector<int32_t> stamp(nunits, -1), list;
-        for (int x = 0; x < kParts; ++x)
-            for (int32_t u = unit_ptr[x]; u < unit_ptr[x + 1]; ++u) {
-                list.clear();
-                stamp[u] = u;
-                const int32_t j0 = (u - unit_ptr[x]) * G;
-                const int32_t len = P.seq_ptr[x + 1] - P.seq_ptr[x];
-                for (int32_t t = j0; t < std::min(len, j0 + G); ++t) {
-                    const int32_t c = P.seq[P.seq_ptr[x] + t];
-                    for (int32_t e = P.dep_ptr[c]; e < P.dep_ptr[c + 1]; ++e) {
-                        const int32_t v = unit_of[P.dep_idx[e]];
-                        if (stamp[v] != u) {
-                            stamp[v] = u;
-                            list.push_back(v);
-                        }
-                    }
-                }
-                udep.insert(udep.end(), list.begin(), list.end());
-                udep_ptr[u + 1] = (int32_t)udep.size();
-            }
-    }
-    P.min_workers.assign(P.p_block + 1, 1);
-    std::vector<int32_t> bmin(first), nb(nunits);
-    for (int32_t q = 1; q <= P.p_block; ++q) {
-        if (q >= 2) {  // one more hop
-            for (int32_t u = 0; u < nunits; ++u) {
-                int32_t m = bmin[u];
-                for (int32_t e = udep_ptr[u]; e < udep_ptr[u + 1]; ++e) m = std::min(m, bmin[udep[e]]);
-                nb[u] = m;
-            }
-            bmin.swap(nb);
-        }
-        int32_t need = 1;
-        for (int x = 0; x < kParts; ++x) {
-            const int32_t* f = first.data() + unit_ptr[x];
-            const int32_t len = unit_ptr[x + 1] - unit_ptr[x];
-            for (int32_t j = 0; j < len; ++j) {
-                int32_t lo = (int32_t)(std::lower_bound(f, f + j + 1, bmin[unit_ptr[x] + j]) - f);
-                need = std::max(need, j - lo + 1);
-            }
-        }
-        P.min_workers[q] = need;
-    }
+    // ---- work units and their deadlock bound (D3) ------------------------------
+    build_units(P, std::max(1, P.group), P.units);
+    // the FP64 power kernel also has a variant carrying three chunks per worker;
+    // the upload takes it where it keeps more rows in flight
+    P.units3 = Units{};
+    if (auto_group && P.value_type == 0 && P.group == 2 && P.reg_slots <= 8) build_units(P, 3, P.units3);
 }
 
 std::vector<int32_t> group_levels(const HostPlan& P, int32_t q) {

@@ -37,6 +37,19 @@ constexpr int kChunkRows = 64;  // rows per chunk = lanes per wavefront
 constexpr int kParts = 8;       // XCD partitions of the MI355X
 constexpr int kMaxBlock = 15;   // largest p_block (4 bits of the done counters)
 
+// Work units of G consecutive chunks of a partition's sequence: units of
+// partition x are ptr[x] .. ptr[x + 1] - 1; unit u's record is rec[u * stride +
+// 5 g + {0: chunk (-1 past the end), 1: slot offset / 64, 2: width, 3: first
+// dependency, 4: end of dependencies}].
+struct Units {
+    int32_t group = 0;                 // G
+    std::vector<int32_t> ptr;          // kParts + 1
+    std::vector<int32_t> rec;
+    int32_t stride = 0;                // ints per record: 8, 16 or 32 for G = 1, 2, 3..4
+    std::vector<int32_t> min_workers;  // index q = 0..p_block (entry 0 unused): the
+                                       // smallest deadlock-free worker count (D3)
+};
+
 struct HostPlan {
     int32_t n = 0;
     int64_t nnz = 0;
@@ -76,15 +89,9 @@ struct HostPlan {
     std::vector<int32_t> seq, seq_ptr;   // chunks of each partition, ascending; kParts + 1
     std::vector<int32_t> dep_ptr;        // nchunks + 1
     std::vector<int32_t> dep_idx;        // dependency chunk ids
-    // work units of G consecutive chunks of a partition's sequence: units of
-    // partition x are unit_ptr[x] .. unit_ptr[x + 1) - 1; unit u's record is
-    // unit_rec[u * unit_stride + 5 g + {0: chunk (-1 past the end), 1: slot
-    // offset / 64, 2: width, 3: first dependency, 4: end of dependencies}]
-    std::vector<int32_t> unit_ptr;       // kParts + 1
-    std::vector<int32_t> unit_rec;
-    int32_t unit_stride = 0;             // ints per record: 8, 16 or 32 for G = 1, 2, 4
-    std::vector<int32_t> min_workers;    // index q = 0..p_block (entry 0 unused), in units
-                                         // of G chunks per worker
+    Units units;   // G = group: every blocked kernel
+    Units units3;  // G = 3 (group 0 when absent): the FP64 power kernel only, built
+                   // when the caller left the group to the planner
 };
 
 // One task of the wavefront schedule (R15): power k (1..q) of a block on the

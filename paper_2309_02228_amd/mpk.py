@@ -43,7 +43,8 @@ EXPORTS = ["mpk_options_default", "mpk_version", "mpk_last_error", "mpk_build_le
            "mpk_set_block", "mpk_tune_block", "mpk_block_powers", "mpk_set_watchdog",
            "poly_apply_static", "mpk_update_values", "mpk_plan_cache_create", "mpk_plan_cache_get",
            "mpk_plan_cache_release", "mpk_plan_cache_stats", "mpk_plan_cache_destroy", "mpk_server_create_ex",
-           "mpk_gs2_smooth", "mpk_gs2_smooth_work_bytes", "mpk_ritz_values"]
+           "mpk_gs2_smooth", "mpk_gs2_smooth_work_bytes", "mpk_ritz_values", "mpk_min_workers_units",
+           "mpk_block_shape"]
 
 
 class MPKError(RuntimeError):
@@ -87,6 +88,8 @@ def _load():
         "mpk_get_deps": (I32, [P, pI64, P, P]),
         "mpk_min_workers": (I32, [P, I32, pI32]),
         "mpk_block_powers": (I32, [P, I32, pI32]),
+        "mpk_min_workers_units": (I32, [P, I32, I32, pI32]),
+        "mpk_block_shape": (I32, [P, I32, pI32, pI32, pI32]),
         "mpk_set_watchdog": (I32, [P, I32]),
         "poly_apply_static": (I32, [P, I32, I32, P, P, D, D, U32, P]),
         "mpk_update_values": (I32, [P, I32, P, P, P, P]),
@@ -267,9 +270,14 @@ class Plan:
         _check(_lib.mpk_get_schedule(self._h, int(q), ctypes.byref(nt), ctypes.byref(ng), _ptr(t)))
         return ng.value, t[:nt.value]
 
-    def min_workers(self, q):
+    def min_workers(self, q, chunks_per_worker=None):
+        """Deadlock bound (waves per XCD) for blocks of q powers, for the plan's units or,
+        given chunks_per_worker, for the units of that size the plan holds."""
         w = ctypes.c_int32()
-        _check(_lib.mpk_min_workers(self._h, int(q), ctypes.byref(w)))
+        if chunks_per_worker is None:
+            _check(_lib.mpk_min_workers(self._h, int(q), ctypes.byref(w)))
+        else:
+            _check(_lib.mpk_min_workers_units(self._h, int(chunks_per_worker), int(q), ctypes.byref(w)))
         return w.value
 
     def block_powers(self, op="powers"):
@@ -278,6 +286,13 @@ class Plan:
         q = ctypes.c_int32()
         _check(_lib.mpk_block_powers(self._h, OPS[op], ctypes.byref(q)))
         return q.value
+
+    def block_shape(self, op="powers"):
+        """(waves per XCD, chunks per wave, register slots per row) of the blocked kernel
+        that calls of operator kind ``op`` use."""
+        w, g, r = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(_lib.mpk_block_shape(self._h, OPS[op], ctypes.byref(w), ctypes.byref(g), ctypes.byref(r)))
+        return w.value, g.value, r.value
 
     def info(self):
         n, nnz, slots = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
