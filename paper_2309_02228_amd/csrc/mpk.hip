@@ -124,6 +124,28 @@ __device__ __forceinline__ double smooth_value(double sA, double sL, double z, d
     return r == gl - 1 ? z + g : g;
 }
 
+// Gathers of vector entries by 32-bit row index through a structured buffer
+// resource (8-byte records, n of them): an index past the end (the column -1
+// of padding slots) reads 0.0 instead of faulting, so no lane mask is needed.
+typedef int gi32x4 __attribute__((ext_vector_type(4)));
+typedef int gi32x2 __attribute__((ext_vector_type(2)));
+__device__ gi32x2 struct_buffer_load_b64(gi32x4 rsrc, int vindex, int voffset, int soffset, int aux)
+    __asm("llvm.amdgcn.struct.buffer.load.v2i32");
+__device__ __forceinline__ gi32x4 vec_rsrc(const double* base, int n) {
+    const uint64_t b = (uint64_t)base;
+    gi32x4 r;
+    r.x = (int)(uint32_t)b;
+    r.y = (int)(((uint32_t)(b >> 32) & 0xffffu) | (8u << 16));  // stride 8 bytes
+    r.z = n;
+    r.w = 0x00020000;
+    return r;
+}
+// AUX 16: a device-coherent read (sc1), for powers written in the same launch
+template <int AUX>
+__device__ __forceinline__ double gather(gi32x4 r, int i) {
+    return __builtin_bit_cast(double, struct_buffer_load_b64(r, i, 0, 0, AUX));
+}
+
 __device__ __forceinline__ double load_coherent(const double* p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -513,6 +535,26 @@ void mpk_block_kernel(BlockArgs a) {
                 sl[g] = 0.0;
                 if (local) continue;
                 double xv[REG];
+                if constexpr (sizeof(VT) == 8) {
+                    // FP64 values: gathers by 32-bit row index through a buffer resource
+                    // (no 64-bit addresses to keep); padding slots (column -1, value 0)
+                    // gather 0.0 and add an exact +0 to a sum that starts at +0
+                    const gi32x4 xr = vec_rsrc(src, a.P.n);
+                    if (kl == 0 || a.plain_gather) {
+#pragma unroll
+                        for (int j = 0; j < REG; ++j) xv[j] = gather<0>(xr, rc[g][j]);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < REG; ++j) xv[j] = gather<16>(xr, rc[g][j]);
+                    }
+#pragma unroll
+                    for (int j = 0; j < REG; ++j) {
+                        s[g] = fma(decode<VT>(rv[g][j], rsc[g]), xv[j], s[g]);
+                        if (split_kind(KIND) && ((lm[g] >> j) & 1u))
+                            sl[g] = fma(decode<VT>(rv[g][j], rsc[g]), xv[j], sl[g]);
+                    }
+                    continue;
+                }
 #pragma unroll
                 for (int j = 0; j < REG; ++j)
                     xv[j] = rc[g][j] < 0 ? 0.0
@@ -955,20 +997,33 @@ BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
     return pick_block_g<4, VT>(reg, kind, poly);
 }
 
-// The planner keeps one chunk per worker when rows need more than 16 slots.
-// Three chunks per worker exist for the FP64 powers only (H.units3): that
-// kernel still fits three waves per SIMD at rows of up to 8 slots, where
-// every other FP64 variant at G = 3 would drop to two.
-BlockFn pick_block(const mpk::HostPlan& H, int group, int reg, int kind, bool poly) {
-    if (group == 3) {
-        if (H.value_type != MPK_VALUES_F64 || kind != KIND_MONO || poly) return nullptr;
-        switch (reg) {
-            case 4: return mpk_block_kernel<4, 3, KIND_MONO, false, double>;
-            case 7: return mpk_block_kernel<7, 3, KIND_MONO, false, double>;
-            case 8: return mpk_block_kernel<8, 3, KIND_MONO, false, double>;
-            default: return nullptr;
-        }
+// Three chunks per worker (H.units3): FP64 values and rows of up to 8 slots,
+// where these kernels keep three waves per SIMD (at 7 slots, 138 to 156 VGPRs);
+// the smoother's would drop to two (182), so it has none.
+template <int KIND, bool POLY>
+BlockFn block_fn3(int reg) {
+    switch (reg) {
+        case 4: return mpk_block_kernel<4, 3, KIND, POLY, double>;
+        case 7: return mpk_block_kernel<7, 3, KIND, POLY, double>;
+        case 8: return mpk_block_kernel<8, 3, KIND, POLY, double>;
+        default: return nullptr;
     }
+}
+
+BlockFn pick_block3(int reg, int kind, bool poly) {
+    switch (kind) {
+        case KIND_MONO: return poly ? block_fn3<KIND_MONO, true>(reg) : block_fn3<KIND_MONO, false>(reg);
+        case KIND_NEWTON: return poly ? block_fn3<KIND_NEWTON, true>(reg) : block_fn3<KIND_NEWTON, false>(reg);
+        case KIND_CHEB: return poly ? block_fn3<KIND_CHEB, true>(reg) : block_fn3<KIND_CHEB, false>(reg);
+        case KIND_JCHAIN: return block_fn3<KIND_JCHAIN, false>(reg);
+        case KIND_GS2: return block_fn3<KIND_GS2, false>(reg);
+        default: return nullptr;
+    }
+}
+
+// The planner keeps one chunk per worker when rows need more than 16 slots.
+BlockFn pick_block(const mpk::HostPlan& H, int group, int reg, int kind, bool poly) {
+    if (group == 3) return H.value_type == MPK_VALUES_F64 ? pick_block3(reg, kind, poly) : nullptr;
     if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_vt<uint16_t>(reg, group, kind, poly);
     return H.value_type == MPK_VALUES_F32 ? pick_block_vt<float>(reg, group, kind, poly)
                                           : pick_block_vt<double>(reg, group, kind, poly);
@@ -1694,10 +1749,9 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev_id));
     int maxlen = 0;
     for (int x = 0; x < kParts; ++x) maxlen = std::max(maxlen, H.seq_ptr[x + 1] - H.seq_ptr[x]);
-    // one candidate kernel: its powers per launch (qe) and the chunks its launch
-    // keeps in flight (waves x chunks per worker)
+    // one candidate kernel: its powers per launch (qe) and workgroups per partition
     struct Shape {
-        int qe = 0, wg_per_part = 0, chunks = 0;
+        int qe = 0, wg_per_part = 0;
     };
     auto shape_of = [&](BlockFn fn, const mpk::Units& U, Shape& sh) -> mpk_status {
         int occ = 0;
@@ -1718,7 +1772,6 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
                 break;
             }
         sh.wg_per_part = wg_per_part;
-        sh.chunks = wg_per_part * kWaves * U.group;
         return MPK_OK;
     };
     for (int kind = 0; kind < kKinds; ++kind)
@@ -1749,14 +1802,16 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
                     take(sh, cand[ci], H.units.group);
                 }
             }
-            // three chunks per worker where a kernel exists for them: taken when it
-            // admits more powers per launch, or as many with more rows in flight
+            // three chunks per worker where a kernel exists for them, taken when it
+            // admits as many powers per launch: at 160^3 with 7 slots, 3 waves of 3
+            // chunks ran a block of 4 powers in 203 us, 4 or 5 waves of 2 in 220 us,
+            // and the Jacobi and GS2 chains ran 7 % and 2-4 % faster than at 2 chunks
             const BlockFn fn3 = H.units3.group == 3 ? pick_block(H, 3, H.reg_slots, kind, poly) : nullptr;
             if (fn3) {
                 Shape sh;
                 mpk_status ss = shape_of(fn3, H.units3, sh);
                 if (ss != MPK_OK) return ss;
-                if (sh.qe > best.qe || (sh.qe == best.qe && sh.chunks > best.chunks)) take(sh, H.reg_slots, 3);
+                if (sh.qe >= best.qe) take(sh, H.reg_slots, 3);
             }
         }
     // plain launches: up to 32 workgroups per CU (128 waves), a few chunks per
