@@ -822,11 +822,10 @@ def main():
         log("jacobi: " + ", ".join(f"{kk}: {v['blocked_us']} us blocked, {v['speedup']}x" for kk, v in jac.items()))
         del planj, Yj
     for vals in ([] if args.no_f32 or args.only != "both" else ["f32", "bf16"]):
-        # reduced-precision storage of the matrix values (vectors, products and sums stay FP64)
-        # with four chunks per wave: the narrow values leave registers for them (measured
-        # faster than two for the power kernel)
+        # reduced-precision storage of the matrix values (vectors, products and sums stay FP64),
+        # chunks per wave chosen by the planner as for FP64 values
         plan_r = Plan.from_csr(A, p_block=args.p_block or min(p, 15),
-                               chunks_per_worker=args.chunks_per_worker or 4, values=vals).upload(dev)
+                               chunks_per_worker=args.chunks_per_worker, values=vals).upload(dev)
         xd_r = plan_r.permute(torch.tensor(x, device=dev), 0)
         Y_r = torch.empty_like(Y)
         wb_r, _ = timed(False, plan_r, xd_r, Y_r)
@@ -842,7 +841,7 @@ def main():
             "ms_per_step": round(wb_r / args.steps * 1e3, 5),
             "speedup_vs_plain": round(wp_r / wb_r, 3),
             "speedup_vs_f64_blocked": round(wall / wb_r, 3) if key == "blocked" else None,
-            "chunks_per_worker": args.chunks_per_worker or 4,
+            "chunks_per_worker": plan_r.block_shape("powers")[1],
             "bytes_per_launch": int(bytes_per_launch - (8 - vbytes) * nnz / launches_per_step
                                     + (4 * n if vals == "bf16" else 0) / launches_per_step),
             "max_rel_err_vs_f64_per_power": float(err.max()),

@@ -394,21 +394,10 @@ __device__ bool poll_until(const BlockArgs& a, __amdgpu_buffer_rsrc_t dr, const 
     }
 }
 
-// Waves per SIMD the compiler must allow for: the FP32-valued polynomial kernels with
-// two chunks of up to 7 register slots per wave need a few registers more than five waves
-// leave (the Chebyshev one 99), and five waves with the 4 spilled registers measured
-// faster than four (the s-step GMRES solve at 160^3: 70.3 ms against 75.8 ms); every
-// other instance keeps its natural count (wider rows and FP64 values spill far more).
-template <int REG, int G, bool POLY, typename VT>
-constexpr int block_min_waves() {
-    return (POLY && G == 2 && REG <= 7 && sizeof(VT) == 4) ? 5 : 1;
-}
-
 // Unit = G consecutive chunks of a partition's sequence, carried together
 // through the q powers of a block; its SELL slots stay in registers.
 template <int REG, int G, int KIND, bool POLY, typename VT>
-__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(block_min_waves<REG, G, POLY, VT>(), 8)))
-void mpk_block_kernel(BlockArgs a) {
+__global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
     const VT* val = (const VT*)a.P.val;
     const int lane = threadIdx.x & 63;
     const int part = blockIdx.x % kParts;
@@ -534,41 +523,27 @@ void mpk_block_kernel(BlockArgs a) {
                 s[g] = 0.0;
                 sl[g] = 0.0;
                 if (local) continue;
+                // gathers by 32-bit row index through a buffer resource (no 64-bit
+                // addresses to keep across the powers); padding slots (column -1,
+                // value 0) gather 0.0 and add an exact +0 to a sum that starts at +0
+                const gi32x4 xr = vec_rsrc(src, a.P.n);
                 double xv[REG];
-                if constexpr (sizeof(VT) == 8) {
-                    // FP64 values: gathers by 32-bit row index through a buffer resource
-                    // (no 64-bit addresses to keep); padding slots (column -1, value 0)
-                    // gather 0.0 and add an exact +0 to a sum that starts at +0
-                    const gi32x4 xr = vec_rsrc(src, a.P.n);
-                    if (kl == 0 || a.plain_gather) {
+                if (kl == 0 || a.plain_gather) {
 #pragma unroll
-                        for (int j = 0; j < REG; ++j) xv[j] = gather<0>(xr, rc[g][j]);
-                    } else {
+                    for (int j = 0; j < REG; ++j) xv[j] = gather<0>(xr, rc[g][j]);
+                } else {
 #pragma unroll
-                        for (int j = 0; j < REG; ++j) xv[j] = gather<16>(xr, rc[g][j]);
-                    }
-#pragma unroll
-                    for (int j = 0; j < REG; ++j) {
-                        s[g] = fma(decode<VT>(rv[g][j], rsc[g]), xv[j], s[g]);
-                        if (split_kind(KIND) && ((lm[g] >> j) & 1u))
-                            sl[g] = fma(decode<VT>(rv[g][j], rsc[g]), xv[j], sl[g]);
-                    }
-                    continue;
+                    for (int j = 0; j < REG; ++j) xv[j] = gather<16>(xr, rc[g][j]);
                 }
 #pragma unroll
-                for (int j = 0; j < REG; ++j)
-                    xv[j] = rc[g][j] < 0 ? 0.0
-                            : (kl == 0 || a.plain_gather ? src[rc[g][j]] : load_coherent(src + rc[g][j]));
-#pragma unroll
-                for (int j = 0; j < REG; ++j)
-                    if (rc[g][j] >= 0) {
-                        VT r = rv[g][j];
-                        // keep narrow values narrow in registers: convert at each use
-                        // instead of letting the compiler hoist a widened copy
-                        if constexpr (sizeof(VT) < 8) asm volatile("" : "+v"(r));
-                        s[g] = fma(decode<VT>(r, rsc[g]), xv[j], s[g]);
-                        if (split_kind(KIND) && ((lm[g] >> j) & 1u)) sl[g] = fma(decode<VT>(r, rsc[g]), xv[j], sl[g]);
-                    }
+                for (int j = 0; j < REG; ++j) {
+                    VT r = rv[g][j];
+                    // keep narrow values narrow in registers: convert at each use
+                    // instead of letting the compiler hoist a widened copy
+                    if constexpr (sizeof(VT) < 8) asm volatile("" : "+v"(r));
+                    s[g] = fma(decode<VT>(r, rsc[g]), xv[j], s[g]);
+                    if (split_kind(KIND) && ((lm[g] >> j) & 1u)) sl[g] = fma(decode<VT>(r, rsc[g]), xv[j], sl[g]);
+                }
             }
             // slots beyond the register cache, streamed at every power.  The wide-row
             // kernels, which rely on this path, take eight slots per batch (columns and
@@ -997,33 +972,38 @@ BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
     return pick_block_g<4, VT>(reg, kind, poly);
 }
 
-// Three chunks per worker (H.units3): FP64 values and rows of up to 8 slots,
-// where these kernels keep three waves per SIMD (at 7 slots, 138 to 156 VGPRs);
-// the smoother's would drop to two (182), so it has none.
-template <int KIND, bool POLY>
+// Three chunks per worker (H.units3): rows of up to 8 slots, where these kernels
+// keep three waves per SIMD (at 7 slots, FP64 values: 138 to 156 VGPRs); the
+// smoother's would drop to two (182), so it has none.
+template <int KIND, bool POLY, typename VT>
 BlockFn block_fn3(int reg) {
     switch (reg) {
-        case 4: return mpk_block_kernel<4, 3, KIND, POLY, double>;
-        case 7: return mpk_block_kernel<7, 3, KIND, POLY, double>;
-        case 8: return mpk_block_kernel<8, 3, KIND, POLY, double>;
+        case 4: return mpk_block_kernel<4, 3, KIND, POLY, VT>;
+        case 7: return mpk_block_kernel<7, 3, KIND, POLY, VT>;
+        case 8: return mpk_block_kernel<8, 3, KIND, POLY, VT>;
         default: return nullptr;
     }
 }
 
+template <typename VT>
 BlockFn pick_block3(int reg, int kind, bool poly) {
     switch (kind) {
-        case KIND_MONO: return poly ? block_fn3<KIND_MONO, true>(reg) : block_fn3<KIND_MONO, false>(reg);
-        case KIND_NEWTON: return poly ? block_fn3<KIND_NEWTON, true>(reg) : block_fn3<KIND_NEWTON, false>(reg);
-        case KIND_CHEB: return poly ? block_fn3<KIND_CHEB, true>(reg) : block_fn3<KIND_CHEB, false>(reg);
-        case KIND_JCHAIN: return block_fn3<KIND_JCHAIN, false>(reg);
-        case KIND_GS2: return block_fn3<KIND_GS2, false>(reg);
+        case KIND_MONO: return poly ? block_fn3<KIND_MONO, true, VT>(reg) : block_fn3<KIND_MONO, false, VT>(reg);
+        case KIND_NEWTON:
+            return poly ? block_fn3<KIND_NEWTON, true, VT>(reg) : block_fn3<KIND_NEWTON, false, VT>(reg);
+        case KIND_CHEB: return poly ? block_fn3<KIND_CHEB, true, VT>(reg) : block_fn3<KIND_CHEB, false, VT>(reg);
+        case KIND_JCHAIN: return block_fn3<KIND_JCHAIN, false, VT>(reg);
+        case KIND_GS2: return block_fn3<KIND_GS2, false, VT>(reg);
         default: return nullptr;
     }
 }
 
 // The planner keeps one chunk per worker when rows need more than 16 slots.
 BlockFn pick_block(const mpk::HostPlan& H, int group, int reg, int kind, bool poly) {
-    if (group == 3) return H.value_type == MPK_VALUES_F64 ? pick_block3(reg, kind, poly) : nullptr;
+    if (group == 3) {
+        if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block3<uint16_t>(reg, kind, poly);
+        return H.value_type == MPK_VALUES_F32 ? pick_block3<float>(reg, kind, poly) : pick_block3<double>(reg, kind, poly);
+    }
     if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_vt<uint16_t>(reg, group, kind, poly);
     return H.value_type == MPK_VALUES_F32 ? pick_block_vt<float>(reg, group, kind, poly)
                                           : pick_block_vt<double>(reg, group, kind, poly);

@@ -90,8 +90,8 @@ struct HostPlan {
     std::vector<int32_t> dep_ptr;        // nchunks + 1
     std::vector<int32_t> dep_idx;        // dependency chunk ids
     Units units;   // G = group: every blocked kernel
-    Units units3;  // G = 3 (group 0 when absent): the FP64 power kernel only, built
-                   // when the caller left the group to the planner
+    Units units3;  // G = 3 (group 0 when absent), built when the caller left the group
+                   // to the planner and rows fit 8 register slots
 };
 
 // One task of the wavefront schedule (R15): power k (1..q) of a block on the

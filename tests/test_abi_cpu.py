@@ -124,20 +124,20 @@ def test_planner_unit_bound_by_group(G):
         assert plan.min_workers(q) == SM.min_workers(ref["owner"], ref["deps"], G, q)
 
 
-def test_planner_three_chunk_units_of_fp64_plans():
-    # FP64 plans whose group is left to the planner, on rows of at most 8 slots, also
-    # hold units of 3 chunks for the matrix powers' kernel; their deadlock bound is
-    # the model's for units of 3
+@pytest.mark.parametrize("values", ["f64", "f32", "bf16"])
+def test_planner_three_chunk_units(values):
+    # plans whose group is left to the planner, on rows of at most 8 slots, also hold
+    # units of 3 chunks; their deadlock bound is the model's for units of 3
     A = S.laplacian_3d(14, 12, 10)
     ref = reference_plan(A)
-    plan = M.Plan.from_csr(A, p_block=5)
+    plan = M.Plan.from_csr(A, p_block=5, values=values)
     assert plan.info()["reg_slots"] == 7
     for q in range(1, 6):
         assert plan.min_workers(q, 3) == SM.min_workers(ref["owner"], ref["deps"], 3, q)
         assert plan.min_workers(q, 2) == plan.min_workers(q)
-    # none for an explicit group, reduced-precision values or wide rows
-    for p in (M.Plan.from_csr(A, p_block=5, chunks_per_worker=2), M.Plan.from_csr(A, p_block=5, values="f32"),
-              M.Plan.from_csr(S.knn_graph_laplacian(3000, k=12, seed=1), p_block=5)):
+    # none for an explicit group or wide rows
+    for p in (M.Plan.from_csr(A, p_block=5, chunks_per_worker=2, values=values),
+              M.Plan.from_csr(S.knn_graph_laplacian(3000, k=12, seed=1), p_block=5, values=values)):
         with pytest.raises(M.MPKError, match="no units of 3"):
             p.min_workers(2, 3)
     with pytest.raises(M.MPKError, match="no units of 0"):
