@@ -868,7 +868,7 @@ void set_error_text(const char* msg) { g_err = msg; }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, unit_ptr3, unit_rec3, dep_ptr,
+    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, wide_ptr[2], wide_rec[2], dep_ptr,
         dep_idx, done, tickets, status, lmask, dslot, total;
 };
 
@@ -891,8 +891,10 @@ Layout make_layout(const mpk::HostPlan& H) {
     L.seq_ptr = take((kParts + 1) * 4);
     L.unit_ptr = take((kParts + 1) * 4);
     L.unit_rec = take(std::max<size_t>(1, H.units.rec.size()) * 4);
-    L.unit_ptr3 = take(H.units3.ptr.size() * 4);
-    L.unit_rec3 = take(H.units3.rec.size() * 4);
+    for (int i = 0; i < 2; ++i) {
+        L.wide_ptr[i] = take(H.wide[i].ptr.size() * 4);
+        L.wide_rec[i] = take(H.wide[i].rec.size() * 4);
+    }
     L.dep_ptr = take((H.nchunks + 1) * 4);
     L.dep_idx = take(std::max<size_t>(1, H.dep_idx.size()) * 4);
     L.done = take(std::max<size_t>(1, H.nchunks) * 4 * kFlagStride);
@@ -918,9 +920,9 @@ struct mpk_plan_s {
     int grid_block[kKinds][2] = {};
     int q_eff[kKinds][2] = {};    // powers per launch meeting the deadlock bound
     int reg[kKinds][2] = {};      // register slots per row of the kernel in use
-    int group[kKinds][2] = {};    // chunks per worker of the kernel in use (H.units or H.units3)
-    const int32_t* unit_ptr3 = nullptr;  // device copy of H.units3
-    const int32_t* unit_rec3 = nullptr;
+    int group[kKinds][2] = {};    // chunks per worker of the kernel in use (H.units or H.wide)
+    const int32_t* wide_ptr[2] = {};  // device copies of H.wide
+    const int32_t* wide_rec[2] = {};
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
     int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
@@ -972,37 +974,49 @@ BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
     return pick_block_g<4, VT>(reg, kind, poly);
 }
 
-// Three chunks per worker (H.units3): rows of up to 8 slots, where these kernels
-// keep three waves per SIMD (at 7 slots, FP64 values: 138 to 156 VGPRs); the
-// smoother's would drop to two (182), so it has none.
-template <int KIND, bool POLY, typename VT>
-BlockFn block_fn3(int reg) {
+// Three and five chunks per worker (H.wide): rows of up to 8 slots.  At 7 slots
+// and FP64 values the three-chunk kernels take 138 to 156 VGPRs (three waves
+// per SIMD) and the five-chunk ones 225 to 255 (two); the smoother's would
+// drop a wave more than the others, so it has neither.
+template <int G, int KIND, bool POLY, typename VT>
+BlockFn block_fn_wide(int reg) {
     switch (reg) {
-        case 4: return mpk_block_kernel<4, 3, KIND, POLY, VT>;
-        case 7: return mpk_block_kernel<7, 3, KIND, POLY, VT>;
-        case 8: return mpk_block_kernel<8, 3, KIND, POLY, VT>;
+        case 4: return mpk_block_kernel<4, G, KIND, POLY, VT>;
+        case 7: return mpk_block_kernel<7, G, KIND, POLY, VT>;
+        case 8: return mpk_block_kernel<8, G, KIND, POLY, VT>;
+        default: return nullptr;
+    }
+}
+
+template <int G, typename VT>
+BlockFn pick_block_wide(int reg, int kind, bool poly) {
+    switch (kind) {
+        case KIND_MONO:
+            return poly ? block_fn_wide<G, KIND_MONO, true, VT>(reg) : block_fn_wide<G, KIND_MONO, false, VT>(reg);
+        case KIND_NEWTON:
+            return poly ? block_fn_wide<G, KIND_NEWTON, true, VT>(reg) : block_fn_wide<G, KIND_NEWTON, false, VT>(reg);
+        case KIND_CHEB:
+            return poly ? block_fn_wide<G, KIND_CHEB, true, VT>(reg) : block_fn_wide<G, KIND_CHEB, false, VT>(reg);
+        case KIND_JCHAIN: return block_fn_wide<G, KIND_JCHAIN, false, VT>(reg);
+        // the GS2 chain measured 7-9 % slower at five chunks (two waves) than at three
+        case KIND_GS2: return G == 3 ? block_fn_wide<G, KIND_GS2, false, VT>(reg) : nullptr;
         default: return nullptr;
     }
 }
 
 template <typename VT>
-BlockFn pick_block3(int reg, int kind, bool poly) {
-    switch (kind) {
-        case KIND_MONO: return poly ? block_fn3<KIND_MONO, true, VT>(reg) : block_fn3<KIND_MONO, false, VT>(reg);
-        case KIND_NEWTON:
-            return poly ? block_fn3<KIND_NEWTON, true, VT>(reg) : block_fn3<KIND_NEWTON, false, VT>(reg);
-        case KIND_CHEB: return poly ? block_fn3<KIND_CHEB, true, VT>(reg) : block_fn3<KIND_CHEB, false, VT>(reg);
-        case KIND_JCHAIN: return block_fn3<KIND_JCHAIN, false, VT>(reg);
-        case KIND_GS2: return block_fn3<KIND_GS2, false, VT>(reg);
-        default: return nullptr;
-    }
+BlockFn pick_block_wide_vt(int group, int reg, int kind, bool poly) {
+    if (group == 3) return pick_block_wide<3, VT>(reg, kind, poly);
+    if (group == 5) return pick_block_wide<5, VT>(reg, kind, poly);
+    return nullptr;
 }
 
 // The planner keeps one chunk per worker when rows need more than 16 slots.
 BlockFn pick_block(const mpk::HostPlan& H, int group, int reg, int kind, bool poly) {
-    if (group == 3) {
-        if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block3<uint16_t>(reg, kind, poly);
-        return H.value_type == MPK_VALUES_F32 ? pick_block3<float>(reg, kind, poly) : pick_block3<double>(reg, kind, poly);
+    if (group == 3 || group == 5) {
+        if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_wide_vt<uint16_t>(group, reg, kind, poly);
+        return H.value_type == MPK_VALUES_F32 ? pick_block_wide_vt<float>(group, reg, kind, poly)
+                                              : pick_block_wide_vt<double>(group, reg, kind, poly);
     }
     if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_vt<uint16_t>(reg, group, kind, poly);
     return H.value_type == MPK_VALUES_F32 ? pick_block_vt<float>(reg, group, kind, poly)
@@ -1103,10 +1117,11 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
     }
     a.P = p->D;
     const int group = p->group[kind][poly];
-    if (group == 3) {
-        a.P.unit_ptr = p->unit_ptr3;
-        a.P.unit_rec = p->unit_rec3;
-    }
+    for (int i = 0; i < 2; ++i)
+        if (group == mpk::kWideGroups[i]) {
+            a.P.unit_ptr = p->wide_ptr[i];
+            a.P.unit_rec = p->wide_rec[i];
+        }
     a.epoch = ++p->epoch;
     a.workers = p->workers[kind][poly];
     a.status = status_slot(p, st, true);
@@ -1555,7 +1570,9 @@ MPK_API mpk_status mpk_min_workers(mpk_plan_t p, int32_t q, int32_t* w) {
 MPK_API mpk_status mpk_min_workers_units(mpk_plan_t p, int32_t group, int32_t q, int32_t* w) {
     if (!p || !w) return fail(MPK_ERR_ARG, "null argument");
     if (q < 1 || q > p->H.p_block) return fail(MPK_ERR_ARG, "q must be in 1..p_block (%d)", p->H.p_block);
-    const mpk::Units* U = group == p->H.units.group ? &p->H.units : group == p->H.units3.group ? &p->H.units3 : nullptr;
+    const mpk::Units* U = group == p->H.units.group ? &p->H.units : nullptr;
+    for (const mpk::Units& W : p->H.wide)
+        if (group == W.group) U = &W;
     if (!U || group < 1) return fail(MPK_ERR_ARG, "the plan holds no units of %d chunks", group);
     *w = U->min_workers[q];
     return MPK_OK;
@@ -1678,8 +1695,10 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     HIP_TRY(put(L.seq_ptr, H.seq_ptr.data(), H.seq_ptr.size() * 4));
     HIP_TRY(put(L.unit_ptr, H.units.ptr.data(), H.units.ptr.size() * 4));
     HIP_TRY(put(L.unit_rec, H.units.rec.data(), H.units.rec.size() * 4));
-    HIP_TRY(put(L.unit_ptr3, H.units3.ptr.data(), H.units3.ptr.size() * 4));
-    HIP_TRY(put(L.unit_rec3, H.units3.rec.data(), H.units3.rec.size() * 4));
+    for (int i = 0; i < 2; ++i) {
+        HIP_TRY(put(L.wide_ptr[i], H.wide[i].ptr.data(), H.wide[i].ptr.size() * 4));
+        HIP_TRY(put(L.wide_rec[i], H.wide[i].rec.data(), H.wide[i].rec.size() * 4));
+    }
     HIP_TRY(put(L.dep_ptr, H.dep_ptr.data(), H.dep_ptr.size() * 4));
     HIP_TRY(put(L.dep_idx, H.dep_idx.data(), H.dep_idx.size() * 4));
     HIP_TRY(put(L.lmask, H.lmask.data(), H.lmask.size() * 4));
@@ -1703,8 +1722,10 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     D.seq_ptr = (const int32_t*)(d + L.seq_ptr);
     D.unit_ptr = (const int32_t*)(d + L.unit_ptr);
     D.unit_rec = (const int32_t*)(d + L.unit_rec);
-    p->unit_ptr3 = (const int32_t*)(d + L.unit_ptr3);
-    p->unit_rec3 = (const int32_t*)(d + L.unit_rec3);
+    for (int i = 0; i < 2; ++i) {
+        p->wide_ptr[i] = (const int32_t*)(d + L.wide_ptr[i]);
+        p->wide_rec[i] = (const int32_t*)(d + L.wide_rec[i]);
+    }
     D.ndeps = (int32_t)H.dep_idx.size();
     D.dep_ptr = (const int32_t*)(d + L.dep_ptr);
     D.dep_idx = (const int32_t*)(d + L.dep_idx);
@@ -1731,7 +1752,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     for (int x = 0; x < kParts; ++x) maxlen = std::max(maxlen, H.seq_ptr[x + 1] - H.seq_ptr[x]);
     // one candidate kernel: its powers per launch (qe) and workgroups per partition
     struct Shape {
-        int qe = 0, wg_per_part = 0;
+        int qe = 0, wg_per_part = 0, occ = 0;  // occ: workgroups (= waves per SIMD) per CU
     };
     auto shape_of = [&](BlockFn fn, const mpk::Units& U, Shape& sh) -> mpk_status {
         int occ = 0;
@@ -1752,6 +1773,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
                 break;
             }
         sh.wg_per_part = wg_per_part;
+        sh.occ = occ;
         return MPK_OK;
     };
     for (int kind = 0; kind < kKinds; ++kind)
@@ -1782,16 +1804,22 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
                     take(sh, cand[ci], H.units.group);
                 }
             }
-            // three chunks per worker where a kernel exists for them, taken when it
-            // admits as many powers per launch: at 160^3 with 7 slots, 3 waves of 3
-            // chunks ran a block of 4 powers in 203 us, 4 or 5 waves of 2 in 220 us,
-            // and the Jacobi and GS2 chains ran 7 % and 2-4 % faster than at 2 chunks
-            const BlockFn fn3 = H.units3.group == 3 ? pick_block(H, 3, H.reg_slots, kind, poly) : nullptr;
-            if (fn3) {
+            // three, then five chunks per worker where a kernel exists for them: the
+            // largest that keeps two waves per SIMD and admits as many powers per
+            // launch.  Fewer, larger units cost fewer tickets, polls and store waits
+            // per row: at 160^3 with 7 slots a block of 4 powers took 278, 220, 202,
+            // 201 and 190 us at 1 to 5 chunks per wave (7, 5, 3, 2 and 2 waves)
+            for (int i = 0; i < 2; ++i) {
+                const mpk::Units& W = H.wide[i];
+                const BlockFn fw = W.group > 0 ? pick_block(H, W.group, H.reg_slots, kind, poly) : nullptr;
+                if (!fw) continue;
                 Shape sh;
-                mpk_status ss = shape_of(fn3, H.units3, sh);
+                mpk_status ss = shape_of(fw, W, sh);
                 if (ss != MPK_OK) return ss;
-                if (sh.qe >= best.qe) take(sh, H.reg_slots, 3);
+                if (sh.occ >= 2 && sh.qe >= best.qe) {
+                    best = sh;
+                    take(sh, H.reg_slots, W.group);
+                }
             }
         }
     // plain launches: up to 32 workgroups per CU (128 waves), a few chunks per

@@ -63,7 +63,7 @@ def test_chunk_owner_fraction_rule():
     assert list(own) == [0, 0] + [(8 * i) // 15 for i in range(15)]
 
 
-@pytest.mark.parametrize("group", [1, 2, 3, 4])
+@pytest.mark.parametrize("group", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("mk,cr,parts,q,p", [
     (lambda: S.laplacian_2d(16, 16), 8, 4, 3, 7),
     (lambda: S.laplacian_3d(6, 6, 6), 16, 8, 4, 4),
@@ -166,7 +166,7 @@ def test_window_condition_is_sufficient(seed):
     A = S.laplacian_2d(int(rng.integers(8, 20)), int(rng.integers(8, 20)))
     B, perm, owner, deps, clev = _schedule(A, 4, 2)
     q = int(rng.integers(2, 5))
-    g = int(rng.choice([1, 2, 3, 4]))
+    g = int(rng.choice([1, 2, 3, 4, 5]))
     w = SM.min_workers(owner, deps, g, q)
     Y = SM.simulate_blocked_mpk(B, np.ones(A.n), q, q, 4, owner, deps, w, group=g)
     assert np.array_equal(Y, O.mpk(B, np.ones(A.n), q))
