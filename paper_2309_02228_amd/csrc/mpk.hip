@@ -76,8 +76,7 @@ struct DevPlan {
     const int32_t* unit_ptr;  // kParts + 1
     const int32_t* unit_rec;  // one record of unit_stride ints per unit
     int32_t ndeps;            // length of dep_idx
-    const int32_t* dep_ptr;
-    const int32_t* dep_idx;
+    const int32_t* dep_idx;   // the unit table's dependency lists (completion-word chunk ids)
     uint32_t* done;
     uint32_t* tickets;  // [4 launch slots][kParts], one per 128-byte line
     const uint32_t* lmask;  // per permuted row: slots of the strictly lower triangle (split plans)
@@ -424,33 +423,27 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
         if (lane == 0) t = atomicAdd(tick, 1u);
         const int u = (int)__builtin_amdgcn_readfirstlane(t);
         if (u >= nunits) break;
-        // the unit's record: chunk, slot offset / 64, width and dependency
-        // range of each of its chunks, in one scalar load
+        // the unit's record: chunk, slot offset / 64 and width of each of its
+        // chunks and the range of its dependency list, in one scalar load
         kint* rec = (kint*)a.P.unit_rec + (int64_t)(ub + u) * kStride;
-        int c[G], width[G], d0[G], d1[G], row[G];
+        int c[G], width[G], row[G];
         int64_t off[G];
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             c[g] = rec[5 * g];
             off[g] = (int64_t)rec[5 * g + 1] * kChunkRows;
             width[g] = rec[5 * g + 2];
-            d0[g] = rec[5 * g + 3];
-            d1[g] = rec[5 * g + 4];
             row[g] = c[g] * kChunkRows + lane;
         }
-        // first batch of each dependency list: one lane per dependency; lanes
-        // past the list read out of range and get 0
-        uint32_t wo[G];
-        bool need[G];
-        bool long_list = false;
-#pragma unroll
-        for (int g = 0; g < G; ++g) {
-            const int i = d0[g] + lane;
-            need[g] = i < d1[g];
-            wo[g] = (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(depr, need[g] ? i * 4 : -1, 0, 0) *
-                    (4u * kFlagStride);
-            long_list = long_list || (d1[g] - d0[g] > 64);
-        }
+        // the other units its rows read, each by the completion word of its first
+        // chunk: one lane per unit in the first batch; lanes past the list read
+        // out of range and get 0
+        const int d0 = rec[3], d1 = rec[4];
+        const int di = d0 + lane;
+        const bool need = di < d1;
+        const uint32_t wo[1] = {(uint32_t)__builtin_amdgcn_raw_buffer_load_b32(depr, need ? di * 4 : -1, 0, 0) *
+                                (4u * kFlagStride)};
+        const bool long_list = d1 - d0 > 64;
         VT rv[G][REG];
         int rc[G][REG];
 #pragma unroll
@@ -500,20 +493,15 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
             const bool local = KIND == KIND_GS2 && (a.base + kl) % a.C.jk == 0;
             if (kl > 0 && !local) {
                 const uint32_t target = a.epoch * 16u + (uint32_t)kl;
-                bool ok[G];
-#pragma unroll
-                for (int g = 0; g < G; ++g) ok[g] = !need[g];
-                if (!poll_until<G>(a, dr, wo, ok, target, c[0], kl)) return;
+                bool ok[1] = {!need};
+                if (!poll_until<1>(a, dr, wo, ok, target, c[0], kl)) return;
                 if (long_list) {  // dependency lists longer than one wave
-#pragma unroll
-                    for (int g = 0; g < G; ++g)
-                        for (int b = d0[g] + 64; b < d1[g]; b += 64) {
-                            const int i = b + lane;
-                            const uint32_t wx[1] = {(uint32_t)(i < d1[g] ? a.P.dep_idx[i] : 0) *
-                                                    (4u * kFlagStride)};
-                            bool okx[1] = {!(i < d1[g])};
-                            if (!poll_until<1>(a, dr, wx, okx, target, c[g], kl)) return;
-                        }
+                    for (int b = d0 + 64; b < d1; b += 64) {
+                        const int i = b + lane;
+                        const uint32_t wx[1] = {(uint32_t)(i < d1 ? a.P.dep_idx[i] : 0) * (4u * kFlagStride)};
+                        bool okx[1] = {!(i < d1)};
+                        if (!poll_until<1>(a, dr, wx, okx, target, c[0], kl)) return;
+                    }
                 }
                 asm volatile("" ::: "memory");
             }
@@ -635,13 +623,12 @@ __global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
                 prev[g] = y;
             }
             if (!last) {
-                // publish power kl+1 of the unit's chunks once their stores completed
+                // publish power kl+1 of the unit's chunks once all their stores
+                // completed, in the completion word of its first chunk
                 asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-#pragma unroll
-                for (int g = 0; g < G; ++g)
-                    if (lane == g && c[g] >= 0)
-                        __hip_atomic_store(a.P.done + kFlagStride * c[g], a.epoch * 16u + (uint32_t)(kl + 1),
-                                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (lane == 0)
+                    __hip_atomic_store(a.P.done + kFlagStride * c[0], a.epoch * 16u + (uint32_t)(kl + 1),
+                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
         }
         if (POLY) {
@@ -868,8 +855,8 @@ void set_error_text(const char* msg) { g_err = msg; }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, wide_ptr[2], wide_rec[2], dep_ptr,
-        dep_idx, done, tickets, status, lmask, dslot, total;
+    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, wide_ptr[2], wide_rec[2],
+        wide_dep[2], dep_idx, done, tickets, status, lmask, dslot, total;
 };
 
 Layout make_layout(const mpk::HostPlan& H) {
@@ -894,9 +881,9 @@ Layout make_layout(const mpk::HostPlan& H) {
     for (int i = 0; i < 2; ++i) {
         L.wide_ptr[i] = take(H.wide[i].ptr.size() * 4);
         L.wide_rec[i] = take(H.wide[i].rec.size() * 4);
+        L.wide_dep[i] = take(H.wide[i].dep_idx.size() * 4);
     }
-    L.dep_ptr = take((H.nchunks + 1) * 4);
-    L.dep_idx = take(std::max<size_t>(1, H.dep_idx.size()) * 4);
+    L.dep_idx = take(std::max<size_t>(1, H.units.dep_idx.size()) * 4);
     L.done = take(std::max<size_t>(1, H.nchunks) * 4 * kFlagStride);
     L.tickets = take(4 * kParts * 4 * kFlagStride);
     L.status = take(kStatusSlots * 4 * kFlagStride);
@@ -923,6 +910,7 @@ struct mpk_plan_s {
     int group[kKinds][2] = {};    // chunks per worker of the kernel in use (H.units or H.wide)
     const int32_t* wide_ptr[2] = {};  // device copies of H.wide
     const int32_t* wide_rec[2] = {};
+    const int32_t* wide_dep[2] = {};
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
     int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
@@ -1121,6 +1109,8 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
         if (group == mpk::kWideGroups[i]) {
             a.P.unit_ptr = p->wide_ptr[i];
             a.P.unit_rec = p->wide_rec[i];
+            a.P.dep_idx = p->wide_dep[i];
+            a.P.ndeps = (int32_t)p->H.wide[i].dep_idx.size();
         }
     a.epoch = ++p->epoch;
     a.workers = p->workers[kind][poly];
@@ -1698,9 +1688,9 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     for (int i = 0; i < 2; ++i) {
         HIP_TRY(put(L.wide_ptr[i], H.wide[i].ptr.data(), H.wide[i].ptr.size() * 4));
         HIP_TRY(put(L.wide_rec[i], H.wide[i].rec.data(), H.wide[i].rec.size() * 4));
+        HIP_TRY(put(L.wide_dep[i], H.wide[i].dep_idx.data(), H.wide[i].dep_idx.size() * 4));
     }
-    HIP_TRY(put(L.dep_ptr, H.dep_ptr.data(), H.dep_ptr.size() * 4));
-    HIP_TRY(put(L.dep_idx, H.dep_idx.data(), H.dep_idx.size() * 4));
+    HIP_TRY(put(L.dep_idx, H.units.dep_idx.data(), H.units.dep_idx.size() * 4));
     HIP_TRY(put(L.lmask, H.lmask.data(), H.lmask.size() * 4));
     HIP_TRY(put(L.dslot, H.dslot.data(), H.dslot.size() * 4));
     const int64_t nd = (int64_t)std::max<int32_t>(1, H.nchunks) * kFlagStride;
@@ -1725,9 +1715,9 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     for (int i = 0; i < 2; ++i) {
         p->wide_ptr[i] = (const int32_t*)(d + L.wide_ptr[i]);
         p->wide_rec[i] = (const int32_t*)(d + L.wide_rec[i]);
+        p->wide_dep[i] = (const int32_t*)(d + L.wide_dep[i]);
     }
-    D.ndeps = (int32_t)H.dep_idx.size();
-    D.dep_ptr = (const int32_t*)(d + L.dep_ptr);
+    D.ndeps = (int32_t)H.units.dep_idx.size();
     D.dep_idx = (const int32_t*)(d + L.dep_idx);
     D.done = (uint32_t*)(d + L.done);
     D.lmask = (const uint32_t*)(d + L.lmask);

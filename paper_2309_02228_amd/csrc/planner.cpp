@@ -449,12 +449,14 @@ static void build_units(const HostPlan& P, int32_t G, Units& U) {
                 r[5 * g + 0] = c;
                 r[5 * g + 1] = (int32_t)(P.chunk_off[c] / kChunkRows);
                 r[5 * g + 2] = (int32_t)((P.chunk_off[c + 1] - P.chunk_off[c]) / kChunkRows);
-                r[5 * g + 3] = P.dep_ptr[c];
-                r[5 * g + 4] = P.dep_ptr[c + 1];
             }
         }
     }
-    std::vector<int32_t> udep_ptr(nunits + 1, 0), udep;
+    // the units each unit's rows read (its own excluded); the dependency range
+    // of the record and the completion words polled come from these lists
+    std::vector<int32_t>& udep_ptr = U.dep_ptr;
+    udep_ptr.assign(nunits + 1, 0);
+    std::vector<int32_t> udep;
     {
         std::vector<int32_t> stamp(nunits, -1), list;
         for (int x = 0; x < kParts; ++x)
@@ -476,6 +478,12 @@ static void build_units(const HostPlan& P, int32_t G, Units& U) {
                 udep.insert(udep.end(), list.begin(), list.end());
                 udep_ptr[u + 1] = (int32_t)udep.size();
             }
+    }
+    U.dep_idx.resize(udep.size());
+    for (size_t e = 0; e < udep.size(); ++e) U.dep_idx[e] = first[udep[e]];
+    for (int32_t u = 0; u < nunits; ++u) {
+        U.rec[(size_t)u * U.stride + 3] = udep_ptr[u];
+        U.rec[(size_t)u * U.stride + 4] = udep_ptr[u + 1];
     }
     U.min_workers.assign(P.p_block + 1, 1);
     std::vector<int32_t> bmin(first), nb(nunits);

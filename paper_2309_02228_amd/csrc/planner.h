@@ -40,13 +40,19 @@ constexpr int kWideGroups[2] = {3, 5};  // chunks per worker of the planner's ex
 
 // Work units of G consecutive chunks of a partition's sequence: units of
 // partition x are ptr[x] .. ptr[x + 1] - 1; unit u's record is rec[u * stride +
-// 5 g + {0: chunk (-1 past the end), 1: slot offset / 64, 2: width, 3: first
-// dependency, 4: end of dependencies}].
+// 5 g + {0: chunk (-1 past the end), 1: slot offset / 64, 2: width}] for each
+// chunk g, and rec[u * stride + {3, 4}] = dep_ptr[u], dep_ptr[u + 1] (the other
+// chunks' fields 3 and 4 are 0).  A unit's chunks publish each power together,
+// after one wait for all their stores, and only the first chunk's completion
+// word is written: dep_idx[dep_ptr[u] ..] lists that word (the chunk id) for
+// every other unit that u's rows read.
 struct Units {
     int32_t group = 0;                 // G
     std::vector<int32_t> ptr;          // kParts + 1
     std::vector<int32_t> rec;
-    int32_t stride = 0;                // ints per record: 8, 16 or 32 for G = 1, 2, 3..4
+    std::vector<int32_t> dep_ptr;      // units + 1
+    std::vector<int32_t> dep_idx;
+    int32_t stride = 0;                // ints per record: 8, 16 or 32 for G = 1, 2, 3..6
     std::vector<int32_t> min_workers;  // index q = 0..p_block (entry 0 unused): the
                                        // smallest deadlock-free worker count (D3)
 };
