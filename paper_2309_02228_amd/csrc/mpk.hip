@@ -3,17 +3,19 @@
 // Device layout of a plan (one caller-owned buffer, 256-byte aligned pieces):
 //   SELL-64 values (f64) and columns (i32, -1 = padding) of P A P^T,
 //   chunk slot offsets (i64), perm / iperm (i32), per-XCD chunk sequences,
-//   dependency lists, per-chunk completion words (u32) and a status block.
+//   work-unit tables with their dependency lists, completion words (u32,
+//   one per chunk, written for the first chunk of each unit) and a status
+//   block.
 //
 // Two kernels compute powers:
 //   * spmv_kernel: one launch per power (Alg. 1), waves stride over the
 //     chunks of their XCD partition.  It is the plain comparator.
 //   * mpk_block_kernel: one persistent launch per block of q powers.  Each
-//     wave takes a chunk, keeps its SELL slots in registers and advances it
-//     through the q powers; before power k it waits until every dependency
-//     chunk has published power k-1.  The matrix therefore streams from HBM
-//     once per block instead of once per power (Sec. 3, temporal blocking
-//     along the level structure).
+//     wave takes a unit of G chunks, keeps their SELL slots in registers and
+//     advances them through the q powers; before power k it waits until
+//     every unit its rows read has published power k-1.  The matrix
+//     therefore streams from HBM once per block instead of once per power
+//     (Sec. 3, temporal blocking along the level structure).
 // Vectors written inside the blocked kernel use device-coherent (sc1)
 // stores and loads: the L2 of one XCD is not kept coherent with plain
 // write-back stores of another XCD, and agent-scope fences cost far more
