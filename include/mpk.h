@@ -113,8 +113,8 @@ typedef struct {
                                 always 1 when rows need more than 16 register
                                 slots).  With FP32 values, 4 suits mpk_apply
                                 on rows of at most 8 slots.  With 0 on rows
-                                of at most 8 slots the kernels may carry 3
-                                or 5 (mpk_block_shape)                        */
+                                of at most 8 slots the kernels may carry 3,
+                                5 or 6 (mpk_block_shape)                      */
     int32_t value_type;      /* storage of the matrix values on the device:
                                 MPK_VALUES_F64 (0), MPK_VALUES_F32 (1) or
                                 MPK_VALUES_BF16_ROWSCALE (2).  The reduced
@@ -233,11 +233,11 @@ mpk_status mpk_min_workers(mpk_plan_t plan, int32_t q, int32_t* workers_per_xcd)
 /*
  * mpk_min_workers for units of chunks_per_worker chunks.  A plan holds the
  * units of its own chunks_per_worker and, when its chunks_per_worker was left
- * at 0 and its rows fit 8 register slots, units of 3 and of 5 as well.  For
+ * at 0 and its rows fit 8 register slots, units of 3, 5 and 6 as well.  For
  * each operator kind mpk_upload takes the largest of these whose kernel keeps
- * two waves per SIMD resident and admits as many powers per launch (5 for most
- * kinds at 7 slots, 3 for MPK_OP_GS2_CHAIN, 2 for MPK_OP_GS2_SMOOTH; see
- * mpk_block_shape).
+ * two waves per SIMD resident and admits as many powers per launch (at 7
+ * slots: 6 for MPK_OP_POWERS with FP64 or FP32 values, 5 for the other kinds,
+ * 3 for MPK_OP_GS2_CHAIN, 2 for MPK_OP_GS2_SMOOTH; see mpk_block_shape).
  * Errors: MPK_ERR_ARG (null pointers, q outside 1..p_block, no units of that
  * size in the plan).
  */

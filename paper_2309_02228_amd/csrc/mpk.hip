@@ -398,7 +398,8 @@ __device__ bool poll_until(const BlockArgs& a, __amdgpu_buffer_rsrc_t dr, const 
 // Unit = G consecutive chunks of a partition's sequence, carried together
 // through the q powers of a block; its SELL slots stay in registers.
 template <int REG, int G, int KIND, bool POLY, typename VT>
-__global__ __launch_bounds__(kBlockThreads) void mpk_block_kernel(BlockArgs a) {
+__global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(G == 6 ? 2 : 1, 8)))
+void mpk_block_kernel(BlockArgs a) {
     const VT* val = (const VT*)a.P.val;
     const int lane = threadIdx.x & 63;
     const int part = blockIdx.x % kParts;
@@ -857,8 +858,8 @@ void set_error_text(const char* msg) { g_err = msg; }
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, wide_ptr[2], wide_rec[2],
-        wide_dep[2], dep_idx, done, tickets, status, lmask, dslot, total;
+    size_t val, rowscale, col, off, perm, iperm, seq, seq_ptr, unit_ptr, unit_rec, wide_ptr[mpk::kWide], wide_rec[mpk::kWide],
+        wide_dep[mpk::kWide], dep_idx, done, tickets, status, lmask, dslot, total;
 };
 
 Layout make_layout(const mpk::HostPlan& H) {
@@ -880,7 +881,7 @@ Layout make_layout(const mpk::HostPlan& H) {
     L.seq_ptr = take((kParts + 1) * 4);
     L.unit_ptr = take((kParts + 1) * 4);
     L.unit_rec = take(std::max<size_t>(1, H.units.rec.size()) * 4);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < mpk::kWide; ++i) {
         L.wide_ptr[i] = take(H.wide[i].ptr.size() * 4);
         L.wide_rec[i] = take(H.wide[i].rec.size() * 4);
         L.wide_dep[i] = take(H.wide[i].dep_idx.size() * 4);
@@ -910,9 +911,9 @@ struct mpk_plan_s {
     int q_eff[kKinds][2] = {};    // powers per launch meeting the deadlock bound
     int reg[kKinds][2] = {};      // register slots per row of the kernel in use
     int group[kKinds][2] = {};    // chunks per worker of the kernel in use (H.units or H.wide)
-    const int32_t* wide_ptr[2] = {};  // device copies of H.wide
-    const int32_t* wide_rec[2] = {};
-    const int32_t* wide_dep[2] = {};
+    const int32_t* wide_ptr[mpk::kWide] = {};  // device copies of H.wide
+    const int32_t* wide_rec[mpk::kWide] = {};
+    const int32_t* wide_dep[mpk::kWide] = {};
     int grid_spmv = 0;       // workgroups of a plain launch
     int cus = 0;             // compute units of the device the plan was uploaded on
     int column_scaling = MPK_SCALE_NONE;             // the plan holds A, or B = A D^{-1}
@@ -964,10 +965,10 @@ BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
     return pick_block_g<4, VT>(reg, kind, poly);
 }
 
-// Three and five chunks per worker (H.wide): rows of up to 8 slots.  At 7 slots
-// and FP64 values the three-chunk kernels take 138 to 156 VGPRs (three waves
-// per SIMD) and the five-chunk ones 225 to 255 (two); the smoother's would
-// drop a wave more than the others, so it has neither.
+// Three, five and six chunks per worker (H.wide): rows of up to 8 slots.  At 7
+// slots and FP64 values the three-chunk kernels take 138 to 156 VGPRs (three
+// waves per SIMD) and the five-chunk ones 216 to 255 (two); the smoother's
+// would drop a wave more than the others, so it has none of them.
 template <int G, int KIND, bool POLY, typename VT>
 BlockFn block_fn_wide(int reg) {
     switch (reg) {
@@ -998,6 +999,12 @@ template <typename VT>
 BlockFn pick_block_wide_vt(int group, int reg, int kind, bool poly) {
     if (group == 3) return pick_block_wide<3, VT>(reg, kind, poly);
     if (group == 5) return pick_block_wide<5, VT>(reg, kind, poly);
+    // six chunks: the plain powers at 7 slots with FP64 or FP32 values only,
+    // held to two waves per SIMD (FP64: 3 registers spill); 2-3 % faster than
+    // five at 160^3 (166 against 169 us for a block of 4 powers, 284 against
+    // 294 us for 8).  BF16 values and 8 slots spill far more.
+    if constexpr (sizeof(VT) >= 4)
+        if (group == 6 && kind == KIND_MONO && !poly && reg == 7) return mpk_block_kernel<7, 6, KIND_MONO, false, VT>;
     return nullptr;
 }
 
@@ -1107,7 +1114,7 @@ mpk_status launch_block(mpk_plan_t p, hipStream_t st, int kind, bool poly, Block
     }
     a.P = p->D;
     const int group = p->group[kind][poly];
-    for (int i = 0; i < 2; ++i)
+    for (int i = 0; i < mpk::kWide; ++i)
         if (group == mpk::kWideGroups[i]) {
             a.P.unit_ptr = p->wide_ptr[i];
             a.P.unit_rec = p->wide_rec[i];
@@ -1687,7 +1694,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     HIP_TRY(put(L.seq_ptr, H.seq_ptr.data(), H.seq_ptr.size() * 4));
     HIP_TRY(put(L.unit_ptr, H.units.ptr.data(), H.units.ptr.size() * 4));
     HIP_TRY(put(L.unit_rec, H.units.rec.data(), H.units.rec.size() * 4));
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < mpk::kWide; ++i) {
         HIP_TRY(put(L.wide_ptr[i], H.wide[i].ptr.data(), H.wide[i].ptr.size() * 4));
         HIP_TRY(put(L.wide_rec[i], H.wide[i].rec.data(), H.wide[i].rec.size() * 4));
         HIP_TRY(put(L.wide_dep[i], H.wide[i].dep_idx.data(), H.wide[i].dep_idx.size() * 4));
@@ -1714,7 +1721,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
     D.seq_ptr = (const int32_t*)(d + L.seq_ptr);
     D.unit_ptr = (const int32_t*)(d + L.unit_ptr);
     D.unit_rec = (const int32_t*)(d + L.unit_rec);
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < mpk::kWide; ++i) {
         p->wide_ptr[i] = (const int32_t*)(d + L.wide_ptr[i]);
         p->wide_rec[i] = (const int32_t*)(d + L.wide_rec[i]);
         p->wide_dep[i] = (const int32_t*)(d + L.wide_dep[i]);
@@ -1801,7 +1808,7 @@ MPK_API mpk_status mpk_upload(mpk_plan_t p, void* dev_buf, size_t bytes, void* s
             // launch.  Fewer, larger units cost fewer tickets, polls and store waits
             // per row: at 160^3 with 7 slots a block of 4 powers took 278, 220, 202,
             // 201 and 190 us at 1 to 5 chunks per wave (7, 5, 3, 2 and 2 waves)
-            for (int i = 0; i < 2; ++i) {
+            for (int i = 0; i < mpk::kWide; ++i) {
                 const mpk::Units& W = H.wide[i];
                 const BlockFn fw = W.group > 0 ? pick_block(H, W.group, H.reg_slots, kind, poly) : nullptr;
                 if (!fw) continue;

@@ -695,9 +695,9 @@ void build_plan(HostPlan& P, int32_t n, const int32_t* rowptr, const int32_t* co
 
     // ---- work units and their deadlock bound (D3) ------------------------------
     build_units(P, std::max(1, P.group), P.units);
-    // the blocked kernels also have variants carrying three and five chunks per
-    // worker at rows of up to 8 slots; the upload decides where to use them
-    for (int i = 0; i < 2; ++i) {
+    // the blocked kernels also have variants carrying three, five and six chunks
+    // per worker at rows of up to 8 slots; the upload decides where to use them
+    for (int i = 0; i < kWide; ++i) {
         P.wide[i] = Units{};
         if (auto_group && P.group == 2 && P.reg_slots <= 8) build_units(P, kWideGroups[i], P.wide[i]);
     }

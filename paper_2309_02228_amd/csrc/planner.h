@@ -36,7 +36,8 @@ struct NoInit : std::allocator<T> {
 constexpr int kChunkRows = 64;  // rows per chunk = lanes per wavefront
 constexpr int kParts = 8;       // XCD partitions of the MI355X
 constexpr int kMaxBlock = 15;   // largest p_block (4 bits of the done counters)
-constexpr int kWideGroups[2] = {3, 5};  // chunks per worker of the planner's extra unit tables
+constexpr int kWide = 3;                        // extra unit tables of a plan
+constexpr int kWideGroups[kWide] = {3, 5, 6};  // their chunks per worker
 
 // Work units of G consecutive chunks of a partition's sequence: units of
 // partition x are ptr[x] .. ptr[x + 1] - 1; unit u's record is rec[u * stride +
@@ -99,7 +100,7 @@ struct HostPlan {
     Units units;   // G = group: every blocked kernel
     // G = kWideGroups[i] (group 0 when absent), built when the caller left the group to
     // the planner and rows fit 8 register slots
-    Units wide[2];
+    Units wide[kWide];
 };
 
 // One task of the wavefront schedule (R15): power k (1..q) of a block on the

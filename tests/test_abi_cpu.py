@@ -127,19 +127,19 @@ def test_planner_unit_bound_by_group(G):
 @pytest.mark.parametrize("values", ["f64", "f32", "bf16"])
 def test_planner_wide_units(values):
     # plans whose group is left to the planner, on rows of at most 8 slots, also hold
-    # units of 3 and 5 chunks; their deadlock bounds are the model's for those sizes
+    # units of 3, 5 and 6 chunks; their deadlock bounds are the model's for those sizes
     A = S.laplacian_3d(14, 12, 10)
     ref = reference_plan(A)
     plan = M.Plan.from_csr(A, p_block=5, values=values)
     assert plan.info()["reg_slots"] == 7
     for q in range(1, 6):
-        for g in (3, 5):
+        for g in (3, 5, 6):
             assert plan.min_workers(q, g) == SM.min_workers(ref["owner"], ref["deps"], g, q)
         assert plan.min_workers(q, 2) == plan.min_workers(q)
     # none for an explicit group or wide rows
     for p in (M.Plan.from_csr(A, p_block=5, chunks_per_worker=2, values=values),
               M.Plan.from_csr(S.knn_graph_laplacian(3000, k=12, seed=1), p_block=5, values=values)):
-        for g in (3, 5):
+        for g in (3, 5, 6):
             with pytest.raises(M.MPKError, match=f"no units of {g}"):
                 p.min_workers(2, g)
     with pytest.raises(M.MPKError, match="no units of 0"):

@@ -320,14 +320,14 @@ def test_full_size_160_cubed():
 @pytest.mark.parametrize("mk", [lambda: S.laplacian_3d(100), lambda: S.laplacian_2d(1100, 1000)])
 def test_wide_units_of_the_fp64_kernels(mk, pb):
     # rows of 7 slots, enough units per partition to fill every resident wave: the FP64
-    # kernels carry 5 chunks per wave at 2 waves per SIMD, except the GS2 chain's (3)
-    # and the smoother's (2)
+    # kernels carry 5 chunks per wave at 2 waves per SIMD, the plain powers' 6, the GS2
+    # chain's 3 and the smoother's 2
     A = mk()
     plan, perm = make_plan(A, p_block=pb)
     w, g, reg = plan.block_shape("powers")
-    assert (g, reg) == (5, 7)
+    assert (g, reg) == (6, 7)
     q = plan.block_powers()
-    assert q >= 2 and plan.min_workers(q, 5) <= w
+    assert q >= 2 and plan.min_workers(q, 6) <= w
     for op in ("poly_monomial", "poly_newton", "poly_chebyshev", "newton_basis", "jacobi_chain", "gs2_chain"):
         wo, go, _ = plan.block_shape(op)
         assert go == (3 if op == "gs2_chain" else 5) and plan.min_workers(plan.block_powers(op), go) <= wo, op

@@ -63,7 +63,7 @@ def test_chunk_owner_fraction_rule():
     assert list(own) == [0, 0] + [(8 * i) // 15 for i in range(15)]
 
 
-@pytest.mark.parametrize("group", [1, 2, 3, 4, 5])
+@pytest.mark.parametrize("group", [1, 2, 3, 4, 5, 6])
 @pytest.mark.parametrize("mk,cr,parts,q,p", [
     (lambda: S.laplacian_2d(16, 16), 8, 4, 3, 7),
     (lambda: S.laplacian_3d(6, 6, 6), 16, 8, 4, 4),
