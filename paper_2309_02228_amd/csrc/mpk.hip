@@ -962,7 +962,8 @@ template <typename VT>
 BlockFn pick_block_vt(int reg, int group, int kind, bool poly) {
     if (reg >= 32 || group == 1) return pick_block_g<1, VT>(reg, kind, poly);
     if (group == 2) return pick_block_g<2, VT>(reg, kind, poly);
-    return pick_block_g<4, VT>(reg, kind, poly);
+    if (group == 4) return pick_block_g<4, VT>(reg, kind, poly);
+    return nullptr;
 }
 
 // Three, five and six chunks per worker (H.wide): rows of up to 8 slots.  At 7
@@ -1010,7 +1011,9 @@ BlockFn pick_block_wide_vt(int group, int reg, int kind, bool poly) {
 
 // The planner keeps one chunk per worker when rows need more than 16 slots.
 BlockFn pick_block(const mpk::HostPlan& H, int group, int reg, int kind, bool poly) {
-    if (group == 3 || group == 5) {
+    // every group of an extra unit table goes to the kernels built for that group (a
+    // kernel of another G would leave part of each unit's chunks undone)
+    if (group != 1 && group != 2 && group != 4) {
         if (H.value_type == MPK_VALUES_BF16_ROWSCALE) return pick_block_wide_vt<uint16_t>(group, reg, kind, poly);
         return H.value_type == MPK_VALUES_F32 ? pick_block_wide_vt<float>(group, reg, kind, poly)
                                               : pick_block_wide_vt<double>(group, reg, kind, poly);
