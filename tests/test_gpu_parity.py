@@ -341,6 +341,22 @@ def test_wide_units_of_the_fp64_kernels(mk, pb):
     plan2, perm2 = make_plan(A, p_block=pb, chunks_per_worker=2)
     assert plan2.block_shape("powers")[1] == 2
     assert np.array_equal(run_apply(plan2, perm2, x, 2 * pb + 1), got)
+    # every kind runs the kernel built for its unit table: blocked equals plain bitwise
+    # for the polynomials and the Newton basis too (a kernel of another G would leave
+    # part of each unit's rows unwritten)
+    xd = torch.tensor(x[perm], device=DEV)
+    c = np.linspace(0.5, -0.3, 2 * pb + 1)
+    for kind, params in (("monomial", None), ("newton", np.linspace(0.1, 2.0, 2 * pb)),
+                         ("chebyshev", np.array([6.0, 6.0]))):
+        yb = plan.poly(kind, c, xd, params=params)
+        yp = plan.poly(kind, c, xd, params=params, plain=True)
+        plan.check()
+        assert torch.equal(yb, yp), kind
+    lam = np.linspace(0.5, 5.0, pb)
+    Vb = plan.sstep(xd, lam)
+    Vp = plan.sstep(xd, lam, plain=True)
+    plan.check()
+    assert torch.equal(Vb, Vp)
 
 
 @pytest.mark.parametrize("G", [1, 2, 4])
